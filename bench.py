@@ -1,0 +1,207 @@
+"""Time-to-chi benchmark on one MI355X.
+
+One "step" is one pass of the whole hot path for one synthetic problem:
+spectral bounds -> X_1, Y_1 -> SP2 recursion merged with the susceptibility
+sweep (Eq. DMSuscept) with device-side sigma/stop decisions -> occupied-virtual
+projection -> D, chi, a0 -> responses Tr[chi H1] for 8 perturbations (Eq. dual).
+
+Workload: N = 8192, N_occ = 4096, banded tight-binding H (half-bandwidth 64,
+hopping ~ N(0, 0.05^2), onsite ~ U(-1, 1)) with a 0.1 gap opened at N_occ,
+A = centred site-position operator, 8 Frobenius-normalised random H1
+(synthetic stand-in for the paper's water-cluster Fockians, which are not
+available).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-χ (ms) + MFMA TFLOP/s at N=8192, split-BF16 vs FP32, at stated error"
+PEAK = {"bf16": 2516.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X)
+PRODUCTS = {"split3_bf16": 6, "split_bf16": 3, "fp32": 1, "bf16": 1}   # MFMA products per FP32-equivalent product
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--precision", default="split3_bf16")
+    ap.add_argument("--compare", default="fp32,split_bf16", help="other precisions timed for context")
+    ap.add_argument("--compare-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=1, help="FP64 oracle SP2+chi steps in the CPU sample")
+    return ap.parse_args()
+
+
+def property_errors(torch, H, A, D, chi, nocc, spin):
+    """Checks that hold at any size: idempotency, trace, symmetry, Tr chi = 0 and
+    the commutator identity [H, chi'] = [D, A] (chi' = chi / s), on the device
+    in FP64 (cast copies)."""
+    Hd, Ad, Dd, Cd = H.double(), A.double(), D.double(), chi.double() / spin
+    out = {}
+    out["idempotency"] = (torch.linalg.norm(Dd @ Dd - Dd) / torch.linalg.norm(Dd)).item()
+    out["trace_d_minus_nocc"] = (torch.trace(Dd) - nocc).item()
+    out["chi_asymmetry"] = torch.linalg.norm(Cd - Cd.T).item()
+    out["trace_chi_rel"] = (torch.trace(Cd).abs() / (torch.linalg.norm(Cd) * Cd.shape[0] ** 0.5)).item()
+    da = Dd @ Ad
+    lhs = Hd @ Cd - Cd @ Hd
+    rhs = da - da.T
+    out["commutator_residual"] = (torch.linalg.norm(lhs - rhs) / torch.linalg.norm(rhs)).item()
+    return out
+
+
+def run_path(dm, torch, H, A, H1, nocc, prec, steps, warmup):
+    for _ in range(warmup):
+        chi, D, a0, info = dm.susceptibility(H, A, nocc, precision=prec, profile=True)
+        dm.response(chi, H1)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        chi, D, a0, info = dm.susceptibility(H, A, nocc, precision=prec, profile=True)
+        resp = dm.response(chi, H1)
+        infos.append(info)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return ms, chi, D, a0, resp, infos
+
+
+def cpu_baseline(wl, m_steps, steps):
+    """The FP64 oracle's merged recursion (Eq. DMSuscept) on the host cores for
+    `steps` SP2 steps at the full size, scaled to the GPU's step count M."""
+    import numpy as np
+    from oracle import sp2
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads", 0) for p in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        threads = os.cpu_count()
+    h = wl.H.astype(np.float64)
+    a = wl.A[0].astype(np.float64)
+    emin, emax = sp2.gershgorin_bounds(h)
+    alpha, beta = sp2.sp2_coefficients(emin, emax)
+    x = alpha * np.eye(wl.n) + beta * h
+    y = beta * a
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s = sp2.choose_sigma(np.trace(x), np.sum(x * x), wl.nocc)
+        y = sp2.response_update(y, x, s)
+        x = sp2.sp2_update(x, s)
+    per_step = (time.perf_counter() - t0) / steps
+    return {
+        "value": per_step * m_steps * 1e3,
+        "unit": "ms",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} FP64 SP2+chi step(s) (Eq. DMSuscept, numpy GEMMs) at N={wl.n}, "
+                  f"{per_step:.2f} s/step, scaled to the GPU's M={m_steps} steps",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2409_17033_amd as dm
+    import workloads as W
+
+    dm.load()
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    wl = W.banded_gapped(args.n, cfg=2)
+    log(f"workload N={wl.n} generated in {time.perf_counter() - t:.1f} s")
+    H = torch.from_numpy(wl.H).to(dev)
+    A = torch.from_numpy(wl.A[0]).to(dev)
+    H1 = torch.from_numpy(wl.H1).to(dev)
+    torch.cuda.synchronize()
+
+    results = {}
+    for prec, steps, warm in [(args.precision, args.steps, args.warmup)] + \
+            [(p, args.compare_steps, 1) for p in args.compare.split(",") if p and p != args.precision]:
+        ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, prec, steps, warm)
+        info = infos[-1]
+        props = property_errors(torch, H, A, D, chi, wl.nocc, 2.0)
+        m = info["m"]
+        n3 = float(wl.n) ** 3
+        step_flops = 3.0 * n3 * PRODUCTS[prec]                   # per SP2 step, upper triangle
+        step_avg_ms = info["step_ms"] / max(m, 1)
+        results[prec] = {
+            "ms": ms, "m": m, "step_ms_total": info["step_ms"], "step_avg_ms": step_avg_ms,
+            "bounds_ms": info["bounds_ms"], "project_ms": info["project_ms"], "output_ms": info["output_ms"],
+            "elapsed_ms": info["elapsed_ms"],
+            "mfma_tflops": step_flops / (step_avg_ms * 1e-3) / 1e12 if step_avg_ms > 0 else None,
+            "algorithmic_tflops": 3.0 * n3 * m / (ms * 1e-3) / 1e12,
+            "a0": a0[0], "response": [float(v) for v in resp[0]], "props": props,
+        }
+        log(f"{prec}: {ms:.1f} ms/step  M={m}  kernel avg {step_avg_ms:.2f} ms/launch  "
+            f"MFMA {results[prec]['mfma_tflops']:.1f} TF/s  props {props}")
+        del chi, D
+        torch.cuda.empty_cache()
+
+    main_prec = args.precision
+    r = results[main_prec]
+    dtype = "fp32" if main_prec == "fp32" else "bf16"
+    roof = {
+        "bound": "mfma",
+        "kernel": f"k_step<{main_prec}> (one SP2 + chi step)",
+        "achieved": r["mfma_tflops"],
+        "peak": PEAK[dtype],
+        "unit": "TFLOP/s",
+        "frac": r["mfma_tflops"] / PEAK[dtype] if r["mfma_tflops"] else None,
+        "traffic": None,
+    }
+    cpu = None
+    if not args.no_cpu:
+        t = time.perf_counter()
+        cpu = cpu_baseline(wl, r["m"], args.cpu_steps)
+        log(f"cpu baseline in {time.perf_counter() - t:.1f} s: {cpu}")
+    line = {
+        "metric": METRIC,
+        "value": round(r["ms"], 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"banded gapped tight-binding H, N={wl.n}, N_occ={wl.nocc}, half-bandwidth 64, "
+                        "gap 0.1, A = site position, 8 random H1",
+            "n": wl.n, "nocc": wl.nocc, "precision": main_prec,
+            "sweep": "forward merged (Eq. DMSuscept) + occupied-virtual projection",
+            "bounds": "lanczos",
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
+                      if kk not in ("response",)} for k, v in results.items()},
+        "speedup_vs_fp32": (results["fp32"]["ms"] / r["ms"]) if "fp32" in results and main_prec != "fp32" else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

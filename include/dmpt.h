@@ -1,0 +1,198 @@
+/*
+ * dmpt.h - C ABI of the MI355X (gfx950) implementation of recursive density
+ * matrix perturbation theory in its susceptibility ("dual") form,
+ * arXiv 2409.17033 (Niklasson, Habib, Finkelstein, Rubensson).
+ *
+ * The problem the calls solve, as the paper states it:
+ *   given a real symmetric Hamiltonian H (N x N) and N_occ, produce the
+ *   zero-temperature density matrix D = theta(mu I - H), Tr D = N_occ
+ *   (Sec. II, Eq. DM0); given an observable A = A^T, produce its static
+ *   susceptibility chi^A_ij = s * dTr[A D]/dH_ij (Eq. Suscept, computed by the
+ *   merged forward sweep Eq. DMSuscept or the backward sweep Eq. DM2); then the
+ *   linear response for any number of perturbations H1 is
+ *   delta<A> = Tr[chi^A H1] (Eq. dual).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Matrices are DEVICE pointers to row-major FP32 with leading dimension n,
+ *    full symmetric storage.  Only the symmetric part of H and A is used
+ *    (entry (i,j) and (j,i) are averaged).  Batches (A, chi, H1) are
+ *    contiguous stacks of n x n matrices.
+ *  - The caller owns all memory, including the device workspace sized by the
+ *    matching *_workspace_bytes call.  The library never allocates or frees
+ *    device memory and keeps no state between calls; concurrent calls must use
+ *    distinct workspaces.
+ *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null stream).
+ *    Every call returns after synchronising that stream, because it fills
+ *    host-side results (dmpt_info, a0, out).
+ *  - Errors are returned as a dmpt_status; nothing is thrown across the ABI.
+ *    dmpt_last_error() gives a message for the calling thread.  Arguments are
+ *    validated before any HIP call, so DMPT_ERR_ARG never touches the device.
+ *  - The spin factor s multiplies chi and a0 (s = 2 for a closed-shell
+ *    system, s = 1 for the paper's spin-less chi).  With A := H1 and s = 1 the
+ *    susceptibility call returns D^(1) of Eq. DM1/DMPert, because the
+ *    recursions are identical (Eq. Equivalence).
+ */
+#ifndef DMPT_H
+#define DMPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMPT_ABI_VERSION 1
+#define DMPT_MAX_STEPS 255
+
+typedef enum dmpt_status {
+  DMPT_OK = 0,
+  DMPT_ERR_ARG = 1,            /* invalid argument (null pointer, size, enum) */
+  DMPT_ERR_NONFINITE = 2,      /* NaN/Inf in an input matrix */
+  DMPT_ERR_NOT_CONVERGED = 3,  /* max_iter reached, or a state stuck at mid-gap (no gap at N_occ) */
+  DMPT_ERR_BOUNDS = 4,         /* [emin, emax] did not enclose the spectrum: the recursion left [0,1] */
+  DMPT_ERR_DEVICE = 5,         /* a HIP runtime call failed */
+  DMPT_ERR_WORKSPACE = 6,      /* workspace missing or smaller than required */
+  DMPT_ERR_UNSUPPORTED = 7     /* valid request this build does not implement */
+} dmpt_status;
+
+/* Arithmetic of the dense products on the matrix cores (Sec. VI.B).
+ * The FP32 master copies of X_n and Y_n, the epilogue updates and all traces
+ * are FP32/FP64 in every mode. */
+typedef enum dmpt_precision {
+  DMPT_FP32 = 0,        /* FP32 operands, FP32 MFMA */
+  DMPT_SPLIT_BF16 = 1,  /* Eq. doubleHalf with BF16: x = hi + lo, products hi*hi + hi*lo + lo*hi
+                           (lo*lo dropped, Eq. MixPrecMult), FP32 accumulate */
+  DMPT_SPLIT3_BF16 = 2, /* three BF16 terms hi+mid+lo (FP32-equivalent operands); the six
+                           products of order >= 2^-16 (hh, hm, mh, hl, lh, mm) are kept */
+  DMPT_BF16 = 3         /* one BF16 term (plain BF16 operands), FP32 accumulate */
+} dmpt_precision;
+
+typedef enum dmpt_bounds_mode {
+  DMPT_BOUNDS_LANCZOS = 0,     /* Lanczos extreme Ritz values widened by max(residual, 1% of width) */
+  DMPT_BOUNDS_GERSHGORIN = 1,  /* Gershgorin discs: always encloses the spectrum */
+  DMPT_BOUNDS_GIVEN = 2        /* opts.emin / opts.emax as supplied */
+} dmpt_bounds_mode;
+
+typedef enum dmpt_sweep {
+  DMPT_SWEEP_FORWARD = 0,  /* Eq. DMSuscept: X and Y updated together, no X_n storage */
+  DMPT_SWEEP_ADJOINT = 1   /* Eq. DM0 storing every X_n, then the backward sweep Eq. DM2 */
+} dmpt_sweep;
+
+typedef struct dmpt_opts {
+  int32_t n;              /* matrix dimension, 1 <= n <= 65536 */
+  int32_t nocc;           /* occupied states, 0 <= nocc <= n */
+  int32_t precision;      /* dmpt_precision */
+  int32_t bounds;         /* dmpt_bounds_mode */
+  double emin, emax;      /* spectral bounds, read iff bounds == DMPT_BOUNDS_GIVEN */
+  int32_t lanczos_steps;  /* Lanczos iterations for DMPT_BOUNDS_LANCZOS; 0 -> 64 */
+  int32_t max_iter;       /* SP2 step limit, <= DMPT_MAX_STEPS; 0 -> 100 */
+  int32_t min_iter;       /* steps before the stopping test may fire; < 0 -> 10 */
+  int32_t sweep;          /* dmpt_sweep (susceptibility only) */
+  double idem_tol;        /* also stop when |Tr X - ||X||_F^2| <= idem_tol; 0 -> parameter-free test only */
+  int32_t project;        /* susceptibility only: 1 -> finish with the occupied-virtual projection
+                             (two FP32 sweep steps with X frozen at D: sigma = +1 then -1) */
+  int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
+  double spin;            /* s; 0 -> 2 */
+  void* stream;           /* hipStream_t */
+  void* workspace;        /* device memory owned by the caller */
+  size_t workspace_bytes;
+} dmpt_opts;
+
+typedef struct dmpt_info {
+  int32_t m;                            /* SP2 steps taken (M) */
+  int32_t status;                       /* dmpt_status of the call */
+  double emin, emax;                    /* bounds used */
+  double beta;                          /* -1/(emax - emin), Eq. DM0 */
+  double trace_d;                       /* Tr D (FP64) */
+  double idem_err;                      /* Tr D - ||D||_F^2 (FP64) */
+  double elapsed_ms;                    /* device time of the call (events on opts.stream) */
+  int8_t sigma[DMPT_MAX_STEPS + 1];     /* sigma_n, n = 1..m */
+  double trace_x[DMPT_MAX_STEPS + 1];   /* Tr X_n, n = 1..m+1 */
+  double sqnorm_x[DMPT_MAX_STEPS + 1];  /* ||X_n||_F^2, n = 1..m+1 */
+  /* Filled when opts.profile = 1 (event pairs on opts.stream around each launch): */
+  double bounds_ms;                     /* spectral bounds + X_1/Y_1 initialisation */
+  double step_ms;                       /* sum over the m working step-kernel launches */
+  double project_ms;                    /* occupied-virtual projection (or adjoint sweep + projection) */
+  double output_ms;                     /* D / chi / a0 output kernel */
+  int32_t step_launches;                /* step kernels launched (>= m + 1: the last one decides the stop) */
+  int32_t tile;                         /* output tile edge of the step kernel */
+} dmpt_info;
+
+/* ABI version compiled into the library (DMPT_ABI_VERSION). */
+int32_t dmpt_abi_version(void);
+
+/* Fill *opts with defaults for an n x n problem with nocc occupied states:
+ * FP32, Lanczos bounds, max_iter 100, min_iter 10, forward sweep, projection on,
+ * spin 2, null stream, no workspace. */
+void dmpt_opts_default(dmpt_opts* opts, int32_t n, int32_t nocc);
+
+/* Device workspace (bytes) that dmpt_sp2_density (nobs = 0) or
+ * dmpt_susceptibility (nobs >= 1 observables) needs for these options.
+ * Returns 0 if the options are invalid. */
+size_t dmpt_workspace_bytes(const dmpt_opts* opts, int32_t nobs);
+
+/* Eq. DM0 (Sec. II): D = theta(mu I - H) by the SP2 recursion.
+ *   H    device, n x n, read only
+ *   D    device, n x n, written (FP32)
+ *   info host, optional (NULL allowed), filled on return (also on
+ *        NOT_CONVERGED / BOUNDS, where D holds the last iterate). */
+dmpt_status dmpt_sp2_density(const float* H, float* D, const dmpt_opts* opts, dmpt_info* info);
+
+/* Eq. DMSuscept (forward, default) or Eq. DM2 (opts.sweep = ADJOINT):
+ * chi_k = s * dTr[A_k D]/dH for nobs observables sharing one SP2 recursion.
+ *   H    device, n x n
+ *   A    device, nobs x n x n (symmetric observables)
+ *   chi  device, nobs x n x n, written
+ *   D    device, n x n, written if not NULL
+ *   a0   host, nobs doubles, a0_k = s * Tr[A_k D] (Eq. expectation), written if not NULL
+ *   info host, optional.
+ * The adjoint sweep supports nobs == 1 and stores every X_n in the workspace. */
+dmpt_status dmpt_susceptibility(const float* H, const float* A, int32_t nobs, float* chi,
+                                float* D, double* a0, const dmpt_opts* opts, dmpt_info* info);
+
+/* Device workspace (bytes) for dmpt_response. */
+size_t dmpt_response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n);
+
+/* Eq. dual: out[k * npert + p] = Tr[chi_k H1_p] = sum_ij chi_k,ij H1_p,ij, accumulated in FP64.
+ *   chi  device, nobs x n x n;  H1 device, npert x n x n
+ *   out  host, nobs * npert doubles (row-major), written
+ *   workspace  device, >= dmpt_response_workspace_bytes(nobs, npert, n)
+ * Limits: 1 <= nobs * npert <= 64. */
+dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32_t npert,
+                          int32_t n, double* out, void* stream, void* workspace,
+                          size_t workspace_bytes);
+
+/* Self-consistent susceptibility (Eq. CP_SCF) with an on-site interaction
+ * G(X) = diag(U_i * s * X_ii) and linear mixing.  Not implemented in this
+ * build: validates its arguments and returns DMPT_ERR_UNSUPPORTED. */
+typedef struct dmpt_scf_opts {
+  int32_t max_iter;
+  int32_t reserved0;
+  double mix;             /* c_mix of Eq. CP_SCF */
+  double tol;             /* stop when ||delta chi||_F <= tol */
+} dmpt_scf_opts;
+
+dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
+                              const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info);
+
+/* Host mirror of the device-side step controller (pure function, no device):
+ * given FP64 Tr X_n, ||X_n||_F^2, the idempotency errors of the two previous
+ * iterates and the number of steps taken, returns
+ *   +1 / -1  : sigma_n for the next step (Sec. II: Tr X_{n+1} closest to N_occ)
+ *    0       : stop, X_n is the result
+ *   -2       : stop, not converged (a state stuck near 1/2: no gap)
+ *   -3       : stop, bounds violation (X_n left the [0,1] spectrum envelope).
+ * e_prev2 is e_{n-2} (ignored when steps < 2). */
+int32_t dmpt_sp2_decide(double tr, double sq, double e_prev2, int32_t steps, int32_t n,
+                        double nocc, int32_t min_iter, double idem_tol);
+
+const char* dmpt_status_string(dmpt_status status);
+const char* dmpt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMPT_H */

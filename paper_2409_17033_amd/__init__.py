@@ -1,0 +1,174 @@
+"""MI355X (gfx950) recursive density-matrix perturbation theory in its
+susceptibility form (arXiv 2409.17033).
+
+Python binding over libdmpt (include/dmpt.h).  Every numerical step runs in
+the library's HIP kernels; this module only marshals torch device tensors,
+the current stream and a caller-owned workspace into the C ABI.
+
+    D, info = sp2_density(H, nocc)                              # Eq. DM0
+    chi, D, a0, info = susceptibility(H, A, nocc)               # Eq. DMSuscept / DM2
+    out = response(chi, H1)                                     # Eq. dual: Tr[chi H1]
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from ._lib import (BOUNDS, PRECISION, SWEEP, DMPTError, Info, Opts, SCFOpts, check, last_error,
+                   load)
+
+__all__ = ["sp2_density", "susceptibility", "response", "make_opts", "workspace_bytes",
+           "sp2_decide", "scf_response", "DMPTError", "load"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_matrix(t, n=None, name="matrix"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and tuple(t.shape[-2:]) != (n, n):
+        raise ValueError(f"{name} must have trailing shape ({n}, {n}), got {tuple(t.shape)}")
+
+
+def make_opts(n: int, nocc: int, *, precision: str = "fp32", bounds: str = "lanczos",
+              emin: float | None = None, emax: float | None = None, lanczos_steps: int = 0,
+              max_iter: int = 0, min_iter: int = -1, sweep: str = "forward",
+              idem_tol: float = 0.0, project: bool = True, spin: float = 2.0,
+              profile: bool = False, stream=None) -> Opts:
+    lib = load()
+    o = Opts()
+    lib.dmpt_opts_default(C.byref(o), n, nocc)
+    o.precision = PRECISION[precision]
+    o.bounds = BOUNDS[bounds]
+    if bounds == "given":
+        o.emin, o.emax = float(emin), float(emax)
+    o.lanczos_steps = lanczos_steps
+    o.max_iter = max_iter
+    o.min_iter = min_iter
+    o.sweep = SWEEP[sweep]
+    o.idem_tol = idem_tol
+    o.project = 1 if project else 0
+    o.spin = spin
+    o.profile = 1 if profile else 0
+    if stream is None:
+        torch = _torch()
+        stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+    o.stream = stream or None
+    return o
+
+
+def workspace_bytes(opts: Opts, nobs: int) -> int:
+    return int(load().dmpt_workspace_bytes(C.byref(opts), nobs))
+
+
+def _workspace(opts: Opts, nobs: int, device):
+    torch = _torch()
+    nbytes = workspace_bytes(opts, nobs)
+    if nbytes == 0:
+        check(1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = nbytes
+    return ws
+
+
+def sp2_density(H, nocc: int, *, workspace=None, raise_on_error: bool = True, **kw):
+    """Eq. DM0: D = theta(mu I - H).  Returns (D, info dict).
+
+    With raise_on_error=False a NOT_CONVERGED / BOUNDS / NONFINITE status is
+    reported in info["status"] and D holds the last iterate."""
+    torch = _torch()
+    n = H.shape[-1]
+    _check_matrix(H, n, "H")
+    o = make_opts(n, nocc, **kw)
+    ws = _workspace(o, 0, H.device) if workspace is None else workspace
+    if workspace is not None:
+        o.workspace, o.workspace_bytes = ws.data_ptr(), ws.numel()
+    D = torch.empty((n, n), dtype=torch.float32, device=H.device)
+    info = Info()
+    st = load().dmpt_sp2_density(C.c_void_p(H.data_ptr()), C.c_void_p(D.data_ptr()), C.byref(o), C.byref(info))
+    _finish(st, info, raise_on_error)
+    return D, info.as_dict()
+
+
+def _finish(st, info, raise_on_error):
+    recoverable = st in (2, 3, 4)   # NONFINITE, NOT_CONVERGED, BOUNDS: outputs written
+    if st != 0 and (raise_on_error or not recoverable):
+        check(st, info)
+
+
+def susceptibility(H, A, nocc: int, *, want_density: bool = True, workspace=None,
+                   raise_on_error: bool = True, **kw):
+    """chi^A = s dTr[A D]/dH (Eq. Suscept) by Eq. DMSuscept (or Eq. DM2 with sweep='adjoint').
+
+    A: (n, n) or (nobs, n, n).  Returns (chi, D or None, a0 [nobs], info dict).
+    """
+    torch = _torch()
+    n = H.shape[-1]
+    _check_matrix(H, n, "H")
+    _check_matrix(A, n, "A")
+    single = A.dim() == 2
+    nobs = 1 if single else A.shape[0]
+    o = make_opts(n, nocc, **kw)
+    ws = _workspace(o, nobs, H.device) if workspace is None else workspace
+    if workspace is not None:
+        o.workspace, o.workspace_bytes = ws.data_ptr(), ws.numel()
+    chi = torch.empty((nobs, n, n), dtype=torch.float32, device=H.device)
+    D = torch.empty((n, n), dtype=torch.float32, device=H.device) if want_density else None
+    a0 = (C.c_double * nobs)()
+    info = Info()
+    st = load().dmpt_susceptibility(C.c_void_p(H.data_ptr()), C.c_void_p(A.data_ptr()), nobs,
+                                    C.c_void_p(chi.data_ptr()),
+                                    C.c_void_p(D.data_ptr()) if D is not None else None,
+                                    a0, C.byref(o), C.byref(info))
+    _finish(st, info, raise_on_error)
+    return (chi[0] if single else chi), D, list(a0), info.as_dict()
+
+
+def response(chi, H1, *, stream=None):
+    """Eq. dual: out[k, p] = Tr[chi_k H1_p] (FP64).  chi: (n,n)/(K,n,n); H1: (n,n)/(P,n,n)."""
+    torch = _torch()
+    n = chi.shape[-1]
+    _check_matrix(chi, n, "chi")
+    _check_matrix(H1, n, "H1")
+    k = 1 if chi.dim() == 2 else chi.shape[0]
+    p = 1 if H1.dim() == 2 else H1.shape[0]
+    lib = load()
+    nbytes = int(lib.dmpt_response_workspace_bytes(k, p, n))
+    if nbytes == 0:
+        check(1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=chi.device)
+    out = (C.c_double * (k * p))()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = lib.dmpt_response(C.c_void_p(chi.data_ptr()), k, C.c_void_p(H1.data_ptr()), p, n, out,
+                           C.c_void_p(stream) if stream else None, C.c_void_p(ws.data_ptr()), nbytes)
+    check(st)
+    import numpy as np
+    return np.array(out[:], dtype=np.float64).reshape(k, p)
+
+
+def sp2_decide(tr, sq, e_prev2, steps, n, nocc, min_iter=10, idem_tol=0.0) -> int:
+    """Host mirror of the device step controller (see include/dmpt.h)."""
+    return int(load().dmpt_sp2_decide(tr, sq, e_prev2, steps, n, nocc, min_iter, idem_tol))
+
+
+def scf_response(H0, U, A, nocc: int, *, max_iter=50, mix=0.3, tol=1e-6, **kw):
+    """Eq. CP_SCF (not implemented in this build: raises DMPTError UNSUPPORTED)."""
+    torch = _torch()
+    n = H0.shape[-1]
+    o = make_opts(n, nocc, **kw)
+    s = SCFOpts(max_iter=max_iter, mix=mix, tol=tol)
+    chi = torch.empty((n, n), dtype=torch.float32, device=H0.device)
+    st = load().dmpt_scf_response(C.c_void_p(H0.data_ptr()), C.c_void_p(U.data_ptr()),
+                                  C.c_void_p(A.data_ptr()), C.c_void_p(chi.data_ptr()),
+                                  C.byref(s), C.byref(o), None)
+    check(st)
+    return chi

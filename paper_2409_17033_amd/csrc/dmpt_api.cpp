@@ -1,0 +1,695 @@
+// Host runtime of libdmpt: argument validation, workspace carve-up, bounds,
+// the chunked step loop with device-side sigma/stop decisions, projection,
+// outputs.  Implements the C ABI declared in include/dmpt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dmpt_internal.h"
+#include "sp2_rule.h"
+
+namespace dmpt {
+namespace {
+
+thread_local std::string g_last_error;
+
+dmpt_status fail(dmpt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define DMPT_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(DMPT_ERR_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+constexpr int kOutBlocks = 1024;
+constexpr int kChunk = 8;   // step launches between host polls of the done flag
+
+struct Opts {
+  int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile;
+  double emin, emax, idem_tol, spin;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+};
+
+dmpt_status normalise(const dmpt_opts* o, Opts* r) {
+  if (!o) return fail(DMPT_ERR_ARG, "opts is NULL");
+  if (o->n < 1 || o->n > 65536) return fail(DMPT_ERR_ARG, "n = %d out of range [1, 65536]", o->n);
+  if (o->nocc < 0 || o->nocc > o->n) return fail(DMPT_ERR_ARG, "nocc = %d out of range [0, n]", o->nocc);
+  if (o->precision < 0 || o->precision > DMPT_BF16) return fail(DMPT_ERR_ARG, "unknown precision %d", o->precision);
+  if (o->bounds < 0 || o->bounds > DMPT_BOUNDS_GIVEN) return fail(DMPT_ERR_ARG, "unknown bounds mode %d", o->bounds);
+  if (o->bounds == DMPT_BOUNDS_GIVEN && !(std::isfinite(o->emin) && std::isfinite(o->emax) && o->emax > o->emin))
+    return fail(DMPT_ERR_ARG, "given bounds need finite emin < emax");
+  if (o->lanczos_steps < 0 || o->lanczos_steps > 512) return fail(DMPT_ERR_ARG, "lanczos_steps out of range [0, 512]");
+  if (o->max_iter < 0 || o->max_iter > DMPT_MAX_STEPS) return fail(DMPT_ERR_ARG, "max_iter out of range [0, %d]", DMPT_MAX_STEPS);
+  if (o->sweep != DMPT_SWEEP_FORWARD && o->sweep != DMPT_SWEEP_ADJOINT) return fail(DMPT_ERR_ARG, "unknown sweep %d", o->sweep);
+  if (!(std::isfinite(o->idem_tol) && o->idem_tol >= 0)) return fail(DMPT_ERR_ARG, "idem_tol must be finite and >= 0");
+  if (!std::isfinite(o->spin)) return fail(DMPT_ERR_ARG, "spin must be finite");
+  if (o->project != 0 && o->project != 1) return fail(DMPT_ERR_ARG, "project must be 0 or 1");
+  if (o->profile != 0 && o->profile != 1) return fail(DMPT_ERR_ARG, "profile must be 0 or 1");
+  r->n = o->n;
+  r->nocc = o->nocc;
+  r->prec = o->precision == DMPT_FP32 ? kFP32
+          : o->precision == DMPT_SPLIT_BF16 ? kSplit2
+          : o->precision == DMPT_SPLIT3_BF16 ? kSplit3 : kBF16;
+  r->bounds = o->bounds;
+  r->lanczos_steps = o->lanczos_steps ? o->lanczos_steps : 48;
+  r->max_iter = o->max_iter ? o->max_iter : 100;
+  r->min_iter = o->min_iter < 0 ? 10 : o->min_iter;
+  r->sweep = o->sweep;
+  r->project = o->project;
+  r->profile = o->profile;
+  r->emin = o->emin;
+  r->emax = o->emax;
+  r->idem_tol = o->idem_tol;
+  r->spin = o->spin == 0.0 ? 2.0 : o->spin;
+  r->stream = (hipStream_t)o->stream;
+  r->ws = (char*)o->workspace;
+  r->ws_bytes = o->workspace_bytes;
+  return DMPT_OK;
+}
+
+// Workspace plan.  All offsets are from the workspace base.
+struct Plan {
+  int n, n_pad, nobs, prec, tile, ntile, nb64, nparts_step;
+  int xslots;
+  size_t mat_f32, mat_op;          // bytes per matrix
+  size_t off_ctl, off_part[2], off_jobs, off_jobs_proj, off_gersh, off_lz, off_a0, off_x, off_y;
+  size_t x_slot_bytes, y_obs_bytes, y_slot_bytes;
+  size_t total;
+  int njobs_max, njobs_proj_max, lz_steps;
+};
+
+// FP32 and split-3 products use 128 x 128 tiles with two-level accumulation
+// (two accumulator sets fit the register file); split-2 and plain BF16 use
+// 256 x 256 tiles with one accumulator chain.
+int main_tile(int prec) { return (prec == kFP32 || prec == kSplit3) ? 128 : 256; }
+
+// Stages between flushes of the MFMA accumulator into the running tile sum:
+// balances the inner chain (flush x MFMAs per stage) against the outer chain
+// (stages / flush), i.e. flush ~ sqrt(stages / chain).  0 = single level.
+int flush_interval(int prec, int tile, int n_pad) {
+  if (tile != 128) return 0;
+  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : prec == kSplit2 ? 3 : 4;
+  const int stages = n_pad / stage_k(prec);
+  const int f = (int)std::lround(std::sqrt((double)stages / chain));
+  return std::max(1, f);
+}
+
+void make_plan(const Opts& o, int nobs, Plan* p) {
+  p->n = o.n;
+  p->n_pad = (o.n + kPadTo - 1) / kPadTo * kPadTo;
+  p->nobs = nobs;
+  p->prec = o.prec;
+  p->tile = main_tile(o.prec);
+  p->ntile = p->n_pad / p->tile;
+  p->nb64 = p->n_pad / 64;
+  p->nparts_step = p->ntile * (p->ntile + 1) / 2;
+  const bool adjoint = nobs > 0 && o.sweep == DMPT_SWEEP_ADJOINT;
+  p->xslots = adjoint ? o.max_iter + 2 : 2;
+  const size_t np2 = (size_t)p->n_pad * p->n_pad;
+  p->mat_f32 = np2 * 4;
+  p->mat_op = o.prec == kFP32 ? 0 : np2 * operand_bytes(o.prec);
+  p->lz_steps = o.lanczos_steps;
+  const int ut = p->nparts_step;                       // upper tiles at the main tile
+  const int t128 = p->n_pad / 128;
+  const int ut128 = t128 * (t128 + 1) / 2;
+  p->njobs_max = ut * (1 + std::max(nobs, 0));
+  p->njobs_proj_max = ut128 * std::max(nobs, 1);
+  size_t off = 0;
+  p->off_ctl = off; off = align_up(off + sizeof(Ctl));
+  const size_t part_bytes = (size_t)p->nb64 * p->nb64 * sizeof(double2);
+  p->off_part[0] = off; off = align_up(off + part_bytes);
+  p->off_part[1] = off; off = align_up(off + part_bytes);
+  p->off_jobs = off; off = align_up(off + (size_t)p->njobs_max * 4);
+  p->off_jobs_proj = off; off = align_up(off + (size_t)p->njobs_proj_max * 4);
+  p->off_gersh = off; off = align_up(off + (size_t)gershgorin_blocks(o.n) * sizeof(double2));
+  p->off_lz = off; off = align_up(off + (size_t)(3 * o.n + 2 * (p->lz_steps + 2)) * sizeof(double));
+  p->off_a0 = off; off = align_up(off + (size_t)kOutBlocks * std::max(nobs, 1) * sizeof(double));
+  p->x_slot_bytes = align_up(p->mat_f32) + align_up(p->mat_op);
+  p->off_x = off; off = align_up(off + p->x_slot_bytes * p->xslots);
+  p->y_obs_bytes = p->x_slot_bytes;
+  p->y_slot_bytes = p->y_obs_bytes * std::max(nobs, 0);
+  p->off_y = off; off = align_up(off + p->y_slot_bytes * 2);
+  p->total = off;
+}
+
+MatRef x_ref(const Plan& p, char* ws, int slot) {
+  char* base = ws + p.off_x + (size_t)slot * p.x_slot_bytes;
+  MatRef m;
+  m.f32 = (float*)base;
+  m.op = p.prec == kFP32 ? (void*)base : (void*)(base + align_up(p.mat_f32));
+  m.stride_f32 = 0;
+  m.stride_op = 0;
+  return m;
+}
+
+MatRef y_ref(const Plan& p, char* ws, int slot) {
+  char* base = ws + p.off_y + (size_t)slot * p.y_slot_bytes;
+  MatRef m;
+  m.f32 = (float*)base;
+  m.op = p.prec == kFP32 ? (void*)base : (void*)(base + align_up(p.mat_f32));
+  m.stride_f32 = p.y_obs_bytes / 4;
+  m.stride_op = p.y_obs_bytes;
+  return m;
+}
+
+// FP32 view of a matrix set (the masters) for the FP32 projection sweep.
+MatRef as_fp32(MatRef m) {
+  m.op = m.f32;
+  m.stride_op = m.stride_f32 * 4;
+  return m;
+}
+
+// Job list: Z-jobs (the heavier products) first, then P-jobs.  Within a kind
+// the upper tiles are dealt round-robin to the 8 XCDs in row-major order of
+// (I, J) so that consecutive workgroups on one XCD share row panels.
+std::vector<uint32_t> build_jobs(int ntile, int nobs_z, bool with_p) {
+  std::vector<uint32_t> jobs;
+  for (int k = 0; k < nobs_z; ++k)
+    for (int i = 0; i < ntile; ++i)
+      for (int j = i; j < ntile; ++j) jobs.push_back(job_pack(kJobZ, k, i, j));
+  if (with_p)
+    for (int i = 0; i < ntile; ++i)
+      for (int j = i; j < ntile; ++j) jobs.push_back(job_pack(kJobP, 0, i, j));
+  return jobs;
+}
+
+// ---------------------------------------------------------------- Lanczos (host part)
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm count).
+int sturm_below(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+    d = a[i] - x - (i ? bb / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// k-th smallest eigenvalue (0-based) by bisection.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k) {
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi) + std::fabs(lo)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, mid) > k) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// |last component| of the unit eigenvector of T for the extreme eigenvalue
+// theta, by two steps of inverse iteration with shift just outside the
+// spectrum (T - shift I is then definite and the LDL^T solve is stable).
+double last_component(const std::vector<double>& a, const std::vector<double>& b, double theta,
+                      double shift_dir, double width) {
+  const size_t k = a.size();
+  const double sh = theta + shift_dir * 1e-10 * std::max(width, 1e-300);
+  std::vector<double> x(k, 1.0), d(k), l(k), y(k);
+  for (int it = 0; it < 3; ++it) {
+    // LDL^T of (T - sh I), forward/back solve
+    d[0] = a[0] - sh;
+    for (size_t i = 1; i < k; ++i) {
+      l[i] = b[i - 1] / d[i - 1];
+      d[i] = a[i] - sh - l[i] * b[i - 1];
+    }
+    y[0] = x[0];
+    for (size_t i = 1; i < k; ++i) y[i] = x[i] - l[i] * y[i - 1];
+    for (size_t i = 0; i < k; ++i) y[i] /= d[i];
+    for (size_t i = k - 1; i-- > 0;) y[i] -= l[i + 1] * y[i + 1];
+    double nrm = 0.0;
+    for (double v : y) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    for (size_t i = 0; i < k; ++i) x[i] = y[i] / nrm;
+  }
+  return std::fabs(x[k - 1]);
+}
+
+struct ScopedEvents {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~ScopedEvents() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+// Optional per-launch timing: event markers recorded on the call's stream.
+struct Profiler {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  ~Profiler() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  // Records a marker and returns its index (-1 when profiling is off).
+  int mark() {
+    if (!on) return -1;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    if (hipEventRecord(e, s) != hipSuccess) {
+      (void)hipEventDestroy(e);
+      return -1;
+    }
+    ev.push_back(e);
+    return (int)ev.size() - 1;
+  }
+  double ms(int a, int b) const {
+    if (a < 0 || b < 0) return 0.0;
+    float t = 0.f;
+    return hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess ? (double)t : 0.0;
+  }
+};
+
+dmpt_status decide_to_status(int code) {
+  switch (code) {
+    case kDecideStop: return DMPT_OK;
+    case kDecideNotConverged: return DMPT_ERR_NOT_CONVERGED;
+    case kDecideBounds: return DMPT_ERR_BOUNDS;
+    case kDecideNonfinite: return DMPT_ERR_NONFINITE;
+    default: return DMPT_ERR_DEVICE;
+  }
+}
+
+// Spectral bounds into ctl (alpha, beta).  Gershgorin always runs (it also
+// scans H for NaN/Inf).  Lanczos: extreme Ritz values widened by
+// max(residual, 1% of the width), clipped to the Gershgorin interval.
+dmpt_status compute_bounds(const Opts& o, const Plan& p, const float* H, Ctl* ctl, double* lz,
+                           double2* gs, hipStream_t s) {
+  DMPT_HIP(launch_gershgorin(H, o.n, gs, gershgorin_blocks(o.n), ctl, o.bounds == DMPT_BOUNDS_GERSHGORIN, s));
+  if (o.bounds == DMPT_BOUNDS_GIVEN) {
+    DMPT_HIP(launch_set_bounds(ctl, o.emin, o.emax, s));
+    return DMPT_OK;
+  }
+  if (o.bounds == DMPT_BOUNDS_GERSHGORIN) return DMPT_OK;
+  const int k = std::min(p.lz_steps, o.n);
+  double* v = lz;
+  double* vprev = lz + o.n;
+  double* w = lz + 2 * o.n;
+  double* ab = lz + 3 * o.n;
+  DMPT_HIP(launch_lanczos_start(v, vprev, o.n, s));
+  for (int j = 0; j < k; ++j) DMPT_HIP(launch_lanczos_step(H, o.n, v, vprev, w, ab, j, s));
+  std::vector<double> hab(2 * k);
+  double g[2];
+  int nonfinite = 0;
+  DMPT_HIP(hipMemcpyAsync(hab.data(), ab, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipMemcpyAsync(g, &ctl->gmin, sizeof(g), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipMemcpyAsync(&nonfinite, &ctl->nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  if (nonfinite) {
+    DMPT_HIP(launch_set_bounds(ctl, g[0], g[1], s));
+    return DMPT_OK;   // the step kernel reports DMPT_ERR_NONFINITE
+  }
+  // Truncate at breakdown (invariant subspace: the Ritz values are exact).
+  std::vector<double> a, b;
+  double scale = 0.0;
+  for (int j = 0; j < k; ++j) scale = std::max(scale, std::fabs(hab[2 * j]) + std::fabs(hab[2 * j + 1]));
+  int kk = k;
+  for (int j = 0; j < k; ++j) {
+    a.push_back(hab[2 * j]);
+    if (hab[2 * j + 1] <= 1e-12 * std::max(scale, 1e-300)) { kk = j + 1; break; }
+    if (j + 1 < k) b.push_back(hab[2 * j + 1]);
+  }
+  const double beta_last = kk < k ? 0.0 : hab[2 * k - 1];
+  b.resize(a.size() > 0 ? a.size() - 1 : 0);
+  const double tmin = tridiag_eig(a, b, 0);
+  const double tmax = tridiag_eig(a, b, (int)a.size() - 1);
+  const double width = std::max(tmax - tmin, 1e-12 * std::max(1.0, std::fabs(tmax)));
+  const double rmin = beta_last * last_component(a, b, tmin, -1.0, width);
+  const double rmax = beta_last * last_component(a, b, tmax, +1.0, width);
+  double emin = tmin - std::max(rmin, 0.01 * width);
+  double emax = tmax + std::max(rmax, 0.01 * width);
+  emin = std::max(emin, g[0]);
+  emax = std::min(emax, g[1]);
+  if (!(emax > emin)) { emin = g[0]; emax = g[1]; }
+  DMPT_HIP(launch_set_bounds(ctl, emin, emax, s));
+  return DMPT_OK;
+}
+
+// Trivial occupations: nocc = 0 -> D = 0, nocc = n -> D = I; chi = 0 either way.
+__global__ void k_trivial(float* d, float* chi, int n, int nobs, int full, const float* a, double* a0_part) {
+  const size_t n2 = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += (size_t)gridDim.x * blockDim.x) {
+    const bool dg = (e / n) == (e % n);
+    if (d) d[e] = (full && dg) ? 1.0f : 0.0f;
+    if (chi) for (int k = 0; k < nobs; ++k) chi[(size_t)k * n2 + e] = 0.0f;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a0_part) {
+    for (int k = 0; k < nobs; ++k) {
+      double t = 0.0;
+      if (full) for (int i = 0; i < n; ++i) t += a[(size_t)k * n2 + (size_t)i * n + i];
+      a0_part[k] = t;
+    }
+  }
+}
+
+// The shared driver of dmpt_sp2_density and dmpt_susceptibility.
+dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, double* a0,
+                const dmpt_opts* opts, dmpt_info* info) {
+  Opts o;
+  dmpt_status st = normalise(opts, &o);
+  if (st != DMPT_OK) return st;
+  if (!H) return fail(DMPT_ERR_ARG, "H is NULL");
+  if (nobs < 0 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [0, %d]", nobs, kMaxObs);
+  if (nobs > 0 && (!A || !chi)) return fail(DMPT_ERR_ARG, "A and chi must not be NULL");
+  if (nobs == 0 && !D) return fail(DMPT_ERR_ARG, "D is NULL");
+  const bool adjoint = nobs > 0 && o.sweep == DMPT_SWEEP_ADJOINT;
+  Plan p;
+  make_plan(o, nobs, &p);
+  if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", p.total);
+  if (o.ws_bytes < p.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, p.total);
+  if (info) std::memset(info, 0, sizeof(*info));
+
+  hipStream_t s = o.stream;
+  char* ws = o.ws;
+  Ctl* ctl = (Ctl*)(ws + p.off_ctl);
+  double* a0_part = (double*)(ws + p.off_a0);
+  ScopedEvents ev;
+  DMPT_HIP(hipEventCreate(&ev.e0));
+  DMPT_HIP(hipEventCreate(&ev.e1));
+  DMPT_HIP(hipEventRecord(ev.e0, s));
+
+  if (o.nocc == 0 || o.nocc == o.n) {
+    const bool full = o.nocc == o.n;
+    hipLaunchKernelGGL(k_trivial, dim3(256), dim3(256), 0, s, D, nobs ? chi : nullptr, o.n, nobs, full ? 1 : 0, A, a0_part);
+    DMPT_HIP(hipGetLastError());
+    std::vector<double> h(std::max(nobs, 1));
+    if (nobs) DMPT_HIP(hipMemcpyAsync(h.data(), a0_part, sizeof(double) * nobs, hipMemcpyDeviceToHost, s));
+    DMPT_HIP(hipEventRecord(ev.e1, s));
+    DMPT_HIP(hipStreamSynchronize(s));
+    if (a0) for (int k = 0; k < nobs; ++k) a0[k] = o.spin * h[k];
+    if (info) {
+      info->status = DMPT_OK;
+      info->trace_d = full ? o.n : 0;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
+      info->elapsed_ms = ms;
+    }
+    return DMPT_OK;
+  }
+
+  // job tables
+  const std::vector<uint32_t> jobs = build_jobs(p.ntile, adjoint ? 0 : nobs, true);
+  uint32_t* d_jobs = (uint32_t*)(ws + p.off_jobs);
+  DMPT_HIP(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * 4, hipMemcpyHostToDevice, s));
+  const int njobs_main = (int)jobs.size();
+
+  Profiler prof;
+  prof.on = o.profile != 0;
+  prof.s = s;
+  const int mb0 = prof.mark();
+  DMPT_HIP(launch_ctl_reset(ctl, s));
+  st = compute_bounds(o, p, H, ctl, (double*)(ws + p.off_lz), (double2*)(ws + p.off_gersh), s);
+  if (st != DMPT_OK) return st;
+
+  auto xslot = [&](int n) { return adjoint ? n : (n & 1); };
+  double2* part[2] = {(double2*)(ws + p.off_part[0]), (double2*)(ws + p.off_part[1])};
+  // X_1 (and Y_1 = beta A for the forward sweep) into slot of step 1
+  DMPT_HIP(launch_init(p.prec, p.tile, H, A, o.n, p.n_pad, adjoint ? 0 : nobs, nullptr, 0,
+                       x_ref(p, ws, xslot(1)), y_ref(p, ws, 1), 0.0, part[1], ctl, s));
+  const int mb1 = prof.mark();
+  std::vector<std::pair<int, int>> step_marks;
+
+  // SP2 steps: chunks of launches, host polls the done flag between chunks.
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = o.n;
+  a.n_pad = p.n_pad;
+  a.ntile = p.ntile;
+  a.max_iter = o.max_iter;
+  a.min_iter = o.min_iter;
+  a.nocc = o.nocc;
+  a.idem_tol = o.idem_tol;
+  a.decide = 1;
+  a.write_split = 1;
+  a.flush = flush_interval(p.prec, p.tile, p.n_pad);
+  a.jobs = adjoint ? d_jobs : d_jobs;
+  a.ctl = ctl;
+  const int njobs_step = adjoint ? p.nparts_step : njobs_main;
+  const uint32_t* step_jobs = adjoint ? d_jobs + 0 : d_jobs;
+  // adjoint X-only run uses the P-jobs only (the table holds no Z-jobs then)
+  int done = 0;
+  int launched = 0;
+  for (int n = 1; n <= o.max_iter + 1 && !done;) {
+    const int end = std::min(o.max_iter + 1, n + kChunk - 1);
+    for (; n <= end; ++n) {
+      a.step = n;
+      a.x_in = x_ref(p, ws, xslot(n));
+      a.x_out = x_ref(p, ws, xslot(n + 1));
+      a.y_in = y_ref(p, ws, n & 1);
+      a.y_out = y_ref(p, ws, (n + 1) & 1);
+      a.part_in = part[n & 1];
+      a.part_out = part[(n + 1) & 1];
+      a.nparts = n == 1 ? p.nb64 * p.nb64 : p.nparts_step;
+      a.jobs = step_jobs;
+      const int ma = prof.mark();
+      DMPT_HIP(launch_step(p.prec, p.tile, a, njobs_step, s));
+      step_marks.emplace_back(ma, prof.mark());
+      ++launched;
+    }
+    DMPT_HIP(hipMemcpyAsync(&done, &ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
+    DMPT_HIP(hipStreamSynchronize(s));
+  }
+  Ctl hctl;
+  DMPT_HIP(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  if (!hctl.done) return fail(DMPT_ERR_DEVICE, "step loop ended without a decision");
+  const int m = hctl.m;
+  st = decide_to_status(hctl.code);
+  const int xfin = xslot(m + 1);
+  int yfin = (m + 1) & 1;
+
+  const int mp0 = prof.mark();
+  if (nobs > 0 && st == DMPT_OK && adjoint) {
+    // Eq. DM2: Y_M = A; for n = M..1, Y_{n-1} from Y_n with X_n, sigma_n; chi = beta Y_0.
+    DMPT_HIP(launch_init(p.prec, p.tile, nullptr, A, o.n, p.n_pad, -nobs, nullptr, 0,
+                         x_ref(p, ws, 0), y_ref(p, ws, 0), 1.0, nullptr, ctl, s));
+    const std::vector<uint32_t> zjobs = build_jobs(p.ntile, nobs, false);
+    uint32_t* d_zjobs = d_jobs + p.nparts_step;
+    DMPT_HIP(hipMemcpyAsync(d_zjobs, zjobs.data(), zjobs.size() * 4, hipMemcpyHostToDevice, s));
+    StepArgs b = a;
+    b.decide = 0;
+    b.sigma_src = ctl->rec;
+    b.jobs = d_zjobs;
+    int ys = 0;
+    for (int n = m; n >= 1; --n) {
+      b.step = n;
+      b.x_in = x_ref(p, ws, xslot(n));
+      b.y_in = y_ref(p, ws, ys);
+      b.y_out = y_ref(p, ws, ys ^ 1);
+      DMPT_HIP(launch_step(p.prec, p.tile, b, (int)zjobs.size(), s));
+      ys ^= 1;
+    }
+    yfin = ys;
+  }
+
+  if (nobs > 0 && o.project && st == DMPT_OK) {
+    // Occupied-virtual projection: two FP32 sweep steps with X frozen at D
+    // (sigma = +1 then -1) multiply the eigenbasis blocks of Y by
+    // (f_i + f_j)(2 - f_i - f_j): 1 on occupied-virtual pairs, 0 elsewhere.
+    const int pt = 128;
+    const int ntp = p.n_pad / pt;
+    const std::vector<uint32_t> pjobs = build_jobs(ntp, nobs, false);
+    uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
+    DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));
+    StepArgs b;
+    std::memset(&b, 0, sizeof(b));
+    b.n = o.n;
+    b.n_pad = p.n_pad;
+    b.ntile = ntp;
+    b.decide = 0;
+    b.write_split = 0;
+    b.flush = flush_interval(kFP32, pt, p.n_pad);
+    b.jobs = d_pjobs;
+    b.ctl = ctl;
+    b.x_in = as_fp32(x_ref(p, ws, xfin));
+    for (int q = 0; q < 2; ++q) {
+      b.fixed_sigma = q == 0 ? 1 : -1;
+      b.y_in = as_fp32(y_ref(p, ws, yfin));
+      b.y_out = as_fp32(y_ref(p, ws, yfin ^ 1));
+      DMPT_HIP(launch_step(kFP32, pt, b, (int)pjobs.size(), s));
+      yfin ^= 1;
+    }
+  }
+
+  const int mp1 = prof.mark();
+  // outputs
+  const MatRef xf = x_ref(p, ws, xfin);
+  const MatRef yf = y_ref(p, ws, yfin);
+  DMPT_HIP(launch_output(xf.f32, nobs ? yf.f32 : nullptr, yf.stride_f32, A, o.n, p.n_pad, nobs, D,
+                         nobs ? chi : nullptr, o.spin, adjoint ? 1 : 0, nullptr, 0, 0, a0_part, ctl, s));
+  const int mo1 = prof.mark();
+  std::vector<double> hpart((size_t)kOutBlocks * std::max(nobs, 1));
+  if (nobs) DMPT_HIP(hipMemcpyAsync(hpart.data(), a0_part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipEventRecord(ev.e1, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  if (a0)
+    for (int k = 0; k < nobs; ++k) {
+      double t = 0.0;
+      for (int b = 0; b < kOutBlocks; ++b) t += hpart[(size_t)k * kOutBlocks + b];
+      a0[k] = o.spin * t;
+    }
+  if (info) {
+    info->m = m;
+    info->status = st;
+    info->emin = hctl.emin;
+    info->emax = hctl.emax;
+    info->beta = hctl.beta;
+    for (int q = 1; q <= m + 1 && q <= DMPT_MAX_STEPS + 1; ++q) {
+      info->trace_x[q - 1] = hctl.rec[q].tr;
+      info->sqnorm_x[q - 1] = hctl.rec[q].sq;
+      if (q <= m) info->sigma[q - 1] = (int8_t)hctl.rec[q].sigma;
+    }
+    info->trace_d = hctl.rec[m + 1].tr;
+    info->idem_err = hctl.rec[m + 1].tr - hctl.rec[m + 1].sq;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
+    info->elapsed_ms = ms;
+    info->step_launches = launched;
+    info->tile = p.tile;
+    if (prof.on) {
+      info->bounds_ms = prof.ms(mb0, mb1);
+      double t = 0.0;
+      for (int q = 0; q < (int)step_marks.size() && q < m; ++q) t += prof.ms(step_marks[q].first, step_marks[q].second);
+      info->step_ms = t;
+      info->project_ms = prof.ms(mp0, mp1);
+      info->output_ms = prof.ms(mp1, mo1);
+    }
+  }
+  if (st != DMPT_OK) {
+    const char* why = st == DMPT_ERR_NOT_CONVERGED ? "SP2 did not converge (step limit or no gap at nocc)"
+                    : st == DMPT_ERR_BOUNDS ? "spectral bounds do not enclose the spectrum of H"
+                    : st == DMPT_ERR_NONFINITE ? "H or A contains NaN/Inf" : "device error";
+    return fail(st, "%s (after %d steps)", why, m);
+  }
+  return DMPT_OK;
+}
+
+}  // namespace
+}  // namespace dmpt
+
+using namespace dmpt;
+
+extern "C" {
+
+int32_t dmpt_abi_version(void) { return DMPT_ABI_VERSION; }
+
+void dmpt_opts_default(dmpt_opts* o, int32_t n, int32_t nocc) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->n = n;
+  o->nocc = nocc;
+  o->precision = DMPT_FP32;
+  o->bounds = DMPT_BOUNDS_LANCZOS;
+  o->lanczos_steps = 48;
+  o->max_iter = 100;
+  o->min_iter = 10;
+  o->sweep = DMPT_SWEEP_FORWARD;
+  o->project = 1;
+  o->profile = 0;
+  o->spin = 2.0;
+}
+
+size_t dmpt_workspace_bytes(const dmpt_opts* opts, int32_t nobs) {
+  Opts o;
+  if (normalise(opts, &o) != DMPT_OK || nobs < 0 || nobs > kMaxObs) return 0;
+  Plan p;
+  make_plan(o, nobs, &p);
+  return p.total;
+}
+
+dmpt_status dmpt_sp2_density(const float* H, float* D, const dmpt_opts* opts, dmpt_info* info) {
+  return run(H, nullptr, 0, nullptr, D, nullptr, opts, info);
+}
+
+dmpt_status dmpt_susceptibility(const float* H, const float* A, int32_t nobs, float* chi, float* D,
+                                double* a0, const dmpt_opts* opts, dmpt_info* info) {
+  if (nobs < 1) return fail(DMPT_ERR_ARG, "nobs must be >= 1");
+  return run(H, A, nobs, chi, D, a0, opts, info);
+}
+
+size_t dmpt_response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n) {
+  if (nobs < 1 || nobs > 8 || npert < 1 || npert > 64 || n < 1) return 0;
+  const size_t n2 = (size_t)n * n;
+  return align_up((size_t)response_blocks(n2) * nobs * npert * sizeof(double)) +
+         align_up((size_t)nobs * npert * sizeof(double));
+}
+
+dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32_t npert, int32_t n,
+                          double* out, void* stream, void* workspace, size_t workspace_bytes) {
+  if (!chi || !H1 || !out) return fail(DMPT_ERR_ARG, "chi, H1 and out must not be NULL");
+  if (nobs < 1 || nobs > 8) return fail(DMPT_ERR_ARG, "nobs = %d out of range [1, 8]", nobs);
+  if (npert < 1 || npert > 64) return fail(DMPT_ERR_ARG, "npert = %d out of range [1, 64]", npert);
+  if (n < 1 || n > 65536) return fail(DMPT_ERR_ARG, "n = %d out of range [1, 65536]", n);
+  const size_t need = dmpt_response_workspace_bytes(nobs, npert, n);
+  if (!workspace) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (workspace_bytes < need) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", workspace_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n2 = (size_t)n * n;
+  const int nblk = response_blocks(n2);
+  double* part = (double*)workspace;
+  double* outd = (double*)((char*)workspace + align_up((size_t)nblk * nobs * npert * sizeof(double)));
+  DMPT_HIP(launch_response(chi, nobs, H1, npert, n2, part, nblk, outd, s));
+  DMPT_HIP(hipMemcpyAsync(out, outd, sizeof(double) * nobs * npert, hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
+                              const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info) {
+  (void)info;
+  Opts o;
+  dmpt_status st = normalise(opts, &o);
+  if (st != DMPT_OK) return st;
+  if (!H0 || !U || !A || !chi || !scf) return fail(DMPT_ERR_ARG, "H0, U, A, chi and scf must not be NULL");
+  if (scf->max_iter < 1 || !(scf->mix > 0 && scf->mix <= 1) || !(scf->tol > 0))
+    return fail(DMPT_ERR_ARG, "scf options out of range");
+  return fail(DMPT_ERR_UNSUPPORTED, "dmpt_scf_response is not implemented in this build");
+}
+
+int32_t dmpt_sp2_decide(double tr, double sq, double e_prev2, int32_t steps, int32_t n, double nocc,
+                        int32_t min_iter, double idem_tol) {
+  return sp2_decide(tr, sq, e_prev2, steps, n, nocc, min_iter, idem_tol);
+}
+
+const char* dmpt_status_string(dmpt_status st) {
+  switch (st) {
+    case DMPT_OK: return "DMPT_OK";
+    case DMPT_ERR_ARG: return "DMPT_ERR_ARG";
+    case DMPT_ERR_NONFINITE: return "DMPT_ERR_NONFINITE";
+    case DMPT_ERR_NOT_CONVERGED: return "DMPT_ERR_NOT_CONVERGED";
+    case DMPT_ERR_BOUNDS: return "DMPT_ERR_BOUNDS";
+    case DMPT_ERR_DEVICE: return "DMPT_ERR_DEVICE";
+    case DMPT_ERR_WORKSPACE: return "DMPT_ERR_WORKSPACE";
+    case DMPT_ERR_UNSUPPORTED: return "DMPT_ERR_UNSUPPORTED";
+  }
+  return "unknown dmpt_status";
+}
+
+const char* dmpt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal interface between the host runtime (dmpt_api.cpp) and the gfx950
+// kernels (dmpt_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dmpt.h"
+
+namespace dmpt {
+
+// Operand formats of the dense products.
+enum Prec : int {
+  kFP32 = 0,    // FP32 row-major, FP32 MFMA
+  kSplit2 = 1,  // packed (hi, lo) BF16 pairs, BF16 MFMA, FP32 accumulate
+  kSplit3 = 2,  // packed (hi, mid, lo) BF16 triples, BF16 MFMA, FP32 accumulate
+  kBF16 = 3,    // plain BF16 row-major
+};
+
+// Bytes per matrix element in the operand copy of each format.
+__host__ __device__ constexpr int operand_bytes(int prec) {
+  return prec == kFP32 ? 4 : prec == kSplit2 ? 4 : prec == kSplit3 ? 6 : prec == kBF16 ? 2 : 0;
+}
+
+constexpr int kPadTo = 256;     // n is padded (with zeros in X-space) to a multiple of this
+constexpr int kMaxObs = 64;
+
+// Per-step record written by workgroup 0 of the step kernel (step n, 1-based).
+struct StepRec {
+  double tr;    // Tr X_n
+  double sq;    // ||X_n||_F^2
+  int sigma;    // sigma_n (0 if the recursion stopped at X_n)
+  int pad;
+};
+
+// Device control block (lives at the start of the workspace).
+struct Ctl {
+  int done;        // recursion finished (stop, error or limit)
+  int code;        // DecideCode at the stop (0 = converged)
+  int m;           // steps taken (M) when done
+  int nonfinite;   // an input matrix held NaN/Inf
+  double emin, emax, alpha, beta;
+  double gmin, gmax;   // Gershgorin bounds
+  StepRec rec[DMPT_MAX_STEPS + 3];
+};
+
+// Job = one output tile (I, J), I <= J, of either the X product
+// P = X_n X_n (kind 0) or the response product Z = Y_n X_n + X_n Y_n of
+// observable `obs` (kind 1).
+enum JobKind : uint32_t { kJobP = 0, kJobZ = 1 };
+
+inline uint32_t job_pack(uint32_t kind, uint32_t obs, uint32_t ti, uint32_t tj) {
+  return kind | (obs << 1) | (ti << 8) | (tj << 20);
+}
+
+// One operand matrix set: FP32 master plus (optionally) the operand copy in
+// the product format.  `stride_*` separates observables in a batch.
+struct MatRef {
+  float* f32;
+  void* op;
+  size_t stride_f32;   // elements
+  size_t stride_op;    // bytes
+};
+
+struct StepArgs {
+  int n, n_pad, ntile;       // ntile = n_pad / TILE
+  int step;                  // n: computes X_{n+1}, Y_{n+1} from X_n, Y_n
+  int max_iter, min_iter;
+  double nocc, idem_tol;
+  int decide;                // 1: evaluate the controller on the partials of X_n
+  int fixed_sigma;           // used when decide == 0 and sigma_src == nullptr
+  const StepRec* sigma_src;  // decide == 0: sigma_n read from sigma_src[step].sigma
+  int write_split;           // also write the operand copy of the outputs
+  int flush;                 // two-level accumulation: add the pass accumulator into the
+                             // running tile sum every `flush` stages (0: single level)
+  const uint32_t* jobs;
+  MatRef x_in, x_out, y_in, y_out;
+  const double2* part_in;    // per-tile (Tr, ||.||^2) partials of X_n
+  double2* part_out;         // ... of X_{n+1}
+  int nparts;
+  Ctl* ctl;
+};
+
+// Launchers (dmpt_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_ctl_reset(Ctl* ctl, hipStream_t s);
+hipError_t launch_gershgorin(const float* h, int n, double2* scratch, int nblk, Ctl* ctl,
+                             int set_coeffs, hipStream_t s);
+int gershgorin_blocks(int n);
+hipError_t launch_lanczos_start(double* v, double* vprev, int n, hipStream_t s);
+hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, double* w,
+                               double* ab, int j, hipStream_t s);
+hipError_t launch_set_bounds(Ctl* ctl, double emin, double emax, hipStream_t s);
+hipError_t launch_init(int prec, int tile, const float* h, const float* a, int n, int n_pad,
+                       int nobs, const uint32_t* jobs, int njobs, MatRef x, MatRef y,
+                       double y_scale_mode, double2* part, Ctl* ctl, hipStream_t s);
+hipError_t launch_step(int prec, int tile, const StepArgs& args, int njobs, hipStream_t s);
+hipError_t launch_output(const float* x32, const float* y32, size_t ystride, const float* a,
+                         int n, int n_pad, int nobs, float* d_out, float* chi_out,
+                         double scale, int scale_by_beta, const uint32_t* jobs, int njobs,
+                         int tile, double* a0_part, Ctl* ctl, hipStream_t s);
+hipError_t launch_response(const float* chi, int nobs, const float* h1, int npert, size_t n2,
+                           double* part, int nblk, double* out_dev, hipStream_t s);
+int response_blocks(size_t n2);
+hipError_t launch_copy_out(const float* src, int n, int n_pad, float* dst, hipStream_t s);
+hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);
+int stage_k(int prec);   // k values per pipeline stage of the step kernel
+
+}  // namespace dmpt

@@ -1,0 +1,197 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/dmpt.h, the ctypes layouts match, argument validation
+fails before any HIP call, and the host mirror of the step controller agrees
+with the oracle's sigma / stop rule."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dmpt.h")
+LIB = os.path.join(ROOT, "paper_2409_17033_amd", "libdmpt.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdmpt.so not built")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2409_17033_amd import _lib
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmpt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_abi_version(lib):
+    assert lib.dmpt_abi_version() == 1
+
+
+def test_struct_layouts():
+    from paper_2409_17033_amd._lib import Info, Opts
+    # sizes follow from the C declarations with natural alignment
+    assert C.sizeof(Opts) == 96
+    assert Opts.spin.offset == 64 and Opts.workspace_bytes.offset == 88
+    assert Info.sigma.offset == 56
+    assert C.sizeof(Info) == 56 + 256 + 2 * 256 * 8 + 4 * 8 + 2 * 4
+    assert Opts.profile.offset == 60
+
+
+def test_opts_default(lib):
+    from paper_2409_17033_amd._lib import Opts
+    o = Opts()
+    lib.dmpt_opts_default(C.byref(o), 100, 40)
+    assert (o.n, o.nocc, o.precision, o.bounds, o.max_iter, o.min_iter, o.project, o.spin) == \
+        (100, 40, 0, 0, 100, 10, 1, 2.0)
+
+
+def _opts(lib, n=64, nocc=32, **kw):
+    from paper_2409_17033_amd._lib import Opts
+    o = Opts()
+    lib.dmpt_opts_default(C.byref(o), n, nocc)
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_workspace_bytes(lib):
+    o = _opts(lib, 1000, 500)
+    w0 = lib.dmpt_workspace_bytes(C.byref(o), 0)
+    w1 = lib.dmpt_workspace_bytes(C.byref(o), 1)
+    w2 = lib.dmpt_workspace_bytes(C.byref(o), 2)
+    n_pad = 1024
+    assert w0 > 2 * n_pad * n_pad * 4          # two FP32 iterates
+    assert w2 - w1 == w1 - w0 or w2 > w1 > w0
+    o.precision = 1                             # split adds the operand copy
+    assert lib.dmpt_workspace_bytes(C.byref(o), 1) > w1
+    o.sweep = 1                                 # adjoint stores every X_n
+    assert lib.dmpt_workspace_bytes(C.byref(o), 1) > 50 * n_pad * n_pad * 8
+    bad = _opts(lib, 0, 0)
+    assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
+
+
+FAKE = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 0), ("n", 70000), ("nocc", -1), ("nocc", 65), ("precision", 9), ("bounds", 7),
+    ("max_iter", 300), ("lanczos_steps", -2), ("sweep", 5), ("idem_tol", -1.0),
+    ("spin", float("nan")), ("project", 3),
+])
+def test_invalid_options_rejected_before_device(lib, field, value):
+    o = _opts(lib, **{field: value})
+    from paper_2409_17033_amd._lib import Info
+    info = Info()
+    assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), C.byref(info)) == 1
+    assert lib.dmpt_last_error()
+
+
+def test_null_pointers_and_workspace(lib):
+    o = _opts(lib)
+    assert lib.dmpt_sp2_density(None, FAKE, C.byref(o), None) == 1
+    assert lib.dmpt_sp2_density(FAKE, None, C.byref(o), None) == 1
+    assert lib.dmpt_sp2_density(FAKE, FAKE, None, None) == 1
+    a0 = (C.c_double * 1)()
+    assert lib.dmpt_susceptibility(FAKE, None, 1, FAKE, None, a0, C.byref(o), None) == 1
+    assert lib.dmpt_susceptibility(FAKE, FAKE, 0, FAKE, None, a0, C.byref(o), None) == 1
+    # valid arguments but no workspace -> DMPT_ERR_WORKSPACE
+    assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 6
+    o.workspace = 0x2000
+    o.workspace_bytes = 16
+    assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 6
+    assert b"need" in lib.dmpt_last_error()
+
+
+def test_given_bounds_validation(lib):
+    o = _opts(lib, bounds=2, emin=1.0, emax=1.0)
+    assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 1
+
+
+def test_split3_accepted(lib):
+    o = _opts(lib, precision=2)
+    assert lib.dmpt_workspace_bytes(C.byref(o), 1) > 0
+    assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 6   # passes validation
+
+
+def test_response_validation(lib):
+    out = (C.c_double * 4)()
+    assert lib.dmpt_response(None, 1, FAKE, 1, 8, out, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_response(FAKE, 9, FAKE, 1, 8, out, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_response(FAKE, 1, FAKE, 65, 8, out, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_response(FAKE, 1, FAKE, 1, 8, out, None, None, 0) == 6
+    assert lib.dmpt_response_workspace_bytes(1, 8, 8192) > 0
+
+
+def test_scf_response_unsupported(lib):
+    from paper_2409_17033_amd._lib import SCFOpts
+    o = _opts(lib)
+    s = SCFOpts(max_iter=10, mix=0.3, tol=1e-6)
+    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(s), C.byref(o), None) == 7
+    s.mix = 0.0
+    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(s), C.byref(o), None) == 1
+
+
+def test_status_strings(lib):
+    lib.dmpt_status_string.restype = C.c_char_p
+    assert lib.dmpt_status_string(0) == b"DMPT_OK"
+    assert lib.dmpt_status_string(4) == b"DMPT_ERR_BOUNDS"
+
+
+def test_controller_sigma_matches_oracle_rule():
+    """The library's sigma choice equals the oracle's on random traces."""
+    import paper_2409_17033_amd as dm
+    from oracle import sp2
+    rng = np.random.default_rng(0)
+    for _ in range(500):
+        n = int(rng.integers(2, 5000))
+        nocc = float(rng.integers(1, n))
+        tr = rng.uniform(0, n)
+        sq = tr * rng.uniform(0.0, 1.0)
+        got = dm.sp2_decide(tr, sq, 0.0, 0, n, nocc, min_iter=10)
+        assert got == sp2.choose_sigma(tr, sq, nocc)
+
+
+def test_controller_replays_oracle_run():
+    """Feed the FP64 oracle's trace/sqnorm sequence to the library controller:
+    it must continue with the same sigma at every step and stop at the same M."""
+    import paper_2409_17033_amd as dm
+    import workloads as W
+    from oracle import sp2
+    wl = W.dense_gapped(128)
+    h = wl.H.astype(np.float64)
+    _, tr = sp2.sp2_density(h, wl.nocc)
+    for n in range(1, tr.m + 2):
+        t, q = tr.traces[n - 1], tr.sqnorms[n - 1]
+        e2 = tr.errors[n - 3] if n >= 3 else 0.0
+        code = dm.sp2_decide(t, q, e2, n - 1, wl.n, wl.nocc, 10, 0.0)
+        if n <= tr.m:
+            assert code == tr.sigmas[n - 1], n
+        else:
+            assert code == 0
+
+
+def test_controller_error_codes():
+    import paper_2409_17033_amd as dm
+    assert dm.sp2_decide(float("nan"), 1.0, 0, 0, 10, 5) == -3
+    assert dm.sp2_decide(5.0, 12.0, 0, 0, 10, 5) == -3           # ||X||^2 > n + 1
+    assert dm.sp2_decide(-2.0, 1.0, 0, 0, 10, 5) == -3
+    # stalled at mid-gap: |e| = 0.5 >= |e_{n-2}| after min_iter steps
+    assert dm.sp2_decide(5.0, 4.5, 0.5, 20, 10, 5) == -2
+    # converged floor
+    assert dm.sp2_decide(5.0, 5.0 - 1e-9, 1e-9, 20, 10, 5) == 0
+    # before min_iter no stop even at the floor
+    assert dm.sp2_decide(5.0, 5.0 - 1e-9, 1e-9, 3, 10, 5) in (1, -1)
+    # idem_tol
+    assert dm.sp2_decide(5.0, 5.0 - 1e-7, 1.0, 20, 10, 5, 10, 1e-6) == 0

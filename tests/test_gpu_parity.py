@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative Frobenius error against the closed form):
+  FP32 products                    D <= 1e-5, chi <= 1e-5
+  split-BF16 products (hi+mid+lo)  D <= 1e-4, chi <= 1e-4
+  two-term split (hi+lo, the paper's Eq. MixPrecMult scheme) is tracked with
+  1e-4 on dense observables and 1e-3 on the site-position observable, whose
+  large occupied-occupied blocks amplify the 2^-16 truncation of lo*lo.
+Partial recursions (a fixed number of steps) are compared with the oracle's
+FP64 recursion run on the sigma sequence and bounds the GPU chose; there the
+only difference is FP32/BF16 rounding, bounded per step.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import closed_form as cf
+from oracle import sp2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "split3_bf16": 1e-4, "split_bf16": 1e-4}
+PRECS = ["fp32", "split3_bf16", "split_bf16"]
+
+
+def _tol(prec, case):
+    if prec == "split_bf16" and case.startswith("band"):
+        return 1e-3
+    return TOL[prec]
+
+
+def _dm():
+    import paper_2409_17033_amd as dm
+    dm.load()
+    return dm
+
+
+def _dev(x, gpu):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(gpu)
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _case(name):
+    if name == "c1":
+        return W.dense_gapped(128)
+    if name == "dense300":
+        return W.dense_gapped(300, nocc=117, cfg=11)
+    if name == "band1000":
+        return W.banded_gapped(1000, nocc=500, cfg=12, cache=False)
+    if name == "band2048":
+        return W.banded_gapped(2048, cfg=2, cache=False)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("case", ["c1", "dense300"])
+@pytest.mark.parametrize("steps", [1, 5])
+@pytest.mark.parametrize("prec", PRECS)
+def test_partial_recursion_matches_fp64(gpu, case, steps, prec):
+    """max_iter = k stops after k steps (NOT_CONVERGED); D = X_{k+1}, chi = s Y_{k+1}."""
+    dm = _dm()
+    wl = _case(case)
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    chi, D, _, info = dm.susceptibility(H, A, wl.nocc, precision=prec, bounds="gershgorin",
+                                        max_iter=steps, min_iter=steps + 1, project=False,
+                                        spin=1.0, raise_on_error=False)
+    assert info["status"] == "DMPT_ERR_NOT_CONVERGED" and info["m"] == steps
+    h = wl.H.astype(np.float64)
+    assert abs(info["emin"] - sp2.gershgorin_bounds(h)[0]) < 1e-9
+    xs, beta = sp2.sp2_sequence(h, info["sigma"], info["emin"], info["emax"])
+    y = sp2.forward_sweep(xs, info["sigma"], beta, wl.A[0].astype(np.float64))
+    tol = 6e-5 * steps if prec == "split_bf16" else 2e-6 * steps
+    assert cf.rel_frobenius(_np(D), xs[-1]) < tol
+    assert cf.rel_frobenius(_np(chi), y) < tol
+    # the device traces are the FP64 traces of the stored iterates
+    for n in range(steps + 1):
+        assert abs(info["trace_x"][n] - np.trace(xs[n])) < 1e-4 * wl.n
+
+
+@pytest.mark.parametrize("case", ["c1", "dense300", "band1000", "band2048"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_converged_matches_closed_form(gpu, case, prec):
+    dm = _dm()
+    wl = _case(case)
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    chi, D, a0, info = dm.susceptibility(H, A, wl.nocc, precision=prec)
+    h, a = wl.H.astype(np.float64), wl.A[0].astype(np.float64)
+    dref = cf.density_matrix(h, wl.nocc)
+    chiref = cf.susceptibility(h, a, wl.nocc, spin=2.0)
+    ed, ec = cf.rel_frobenius(_np(D), dref), cf.rel_frobenius(_np(chi), chiref)
+    print(f"{case} {prec}: M={info['m']} errD={ed:.2e} errchi={ec:.2e} {info['elapsed_ms']:.1f} ms")
+    tol = _tol(prec, case)
+    assert ed <= TOL[prec] and ec <= tol
+    a0ref = 2.0 * cf.expectation(a, dref)
+    assert abs(a0[0] - a0ref) <= TOL[prec] * max(1.0, np.abs(a).sum() / wl.n * wl.nocc)
+    c = _np(chi)
+    assert np.array_equal(c, c.T)                       # mirror store: exact symmetry
+    assert abs(np.trace(c)) <= 10 * tol * np.linalg.norm(c) * np.sqrt(wl.n)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_sp2_density(gpu, prec):
+    dm = _dm()
+    wl = _case("band1000")
+    D, info = dm.sp2_density(_dev(wl.H, gpu), wl.nocc, precision=prec)
+    dref = cf.density_matrix(wl.H.astype(np.float64), wl.nocc)
+    assert cf.rel_frobenius(_np(D), dref) <= TOL[prec]
+    assert abs(info["trace_d"] - wl.nocc) < TOL[prec] * wl.nocc
+    d = _np(D)
+    assert abs(np.trace(d) - info["trace_d"]) < 1e-3
+
+
+def test_duality_on_gpu(gpu):
+    """Tr[chi^A H1] = s Tr[A D1] with D1 from the same kernels (A := H1, s = 1)."""
+    dm = _dm()
+    wl = _case("c1")
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    H1 = _dev(wl.H1, gpu)
+    chi, _, _, _ = dm.susceptibility(H, A, wl.nocc)
+    dual = dm.response(chi, H1)[0]
+    d1, _, _, _ = dm.susceptibility(H, H1, wl.nocc, spin=1.0)   # 8 observables = 8 D1
+    direct = 2.0 * dm.response(d1, A.unsqueeze(0).contiguous())[:, 0]
+    ref = cf.response(cf.susceptibility(wl.H.astype(np.float64), wl.A[0].astype(np.float64),
+                                        wl.nocc, 2.0), wl.H1)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(dual - ref)) <= 1e-5 * scale
+    assert np.max(np.abs(direct - ref)) <= 1e-5 * scale
+
+
+def test_response_kernel(gpu):
+    dm = _dm()
+    rng = np.random.default_rng(3)
+    for n, k, p in [(1, 1, 1), (37, 2, 3), (300, 1, 8), (513, 3, 11)]:
+        chi = rng.normal(size=(k, n, n)).astype(np.float32)
+        h1 = rng.normal(size=(p, n, n)).astype(np.float32)
+        out = dm.response(_dev(chi, gpu), _dev(h1, gpu))
+        ref = np.einsum("kij,pij->kp", chi.astype(np.float64), h1.astype(np.float64))
+        assert np.allclose(out, ref, rtol=1e-12, atol=1e-9 * n)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adjoint_sweep_matches_forward(gpu, prec):
+    dm = _dm()
+    wl = _case("dense300")
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    chi_f, _, _, inf_f = dm.susceptibility(H, A, wl.nocc, precision=prec)
+    chi_b, _, _, inf_b = dm.susceptibility(H, A, wl.nocc, precision=prec, sweep="adjoint")
+    ref = cf.susceptibility(wl.H.astype(np.float64), wl.A[0].astype(np.float64), wl.nocc, 2.0)
+    assert cf.rel_frobenius(_np(chi_b), ref) <= TOL[prec]
+    assert cf.rel_frobenius(_np(chi_b), _np(chi_f)) <= 2 * TOL[prec]
+
+
+def test_multiple_observables(gpu):
+    dm = _dm()
+    wl = W.dense_gapped(200, nocc=90, nobs=3, cfg=13)
+    chi, _, a0, _ = dm.susceptibility(_dev(wl.H, gpu), _dev(wl.A, gpu), wl.nocc)
+    h = wl.H.astype(np.float64)
+    for k in range(3):
+        ref = cf.susceptibility(h, wl.A[k].astype(np.float64), wl.nocc, 2.0)
+        assert cf.rel_frobenius(_np(chi[k]), ref) <= 1e-5
+
+
+def test_trivial_occupations(gpu):
+    dm = _dm()
+    wl = _case("c1")
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    chi, D, a0, _ = dm.susceptibility(H, A, 0)
+    assert not _np(D).any() and not _np(chi).any() and a0[0] == 0.0
+    chi, D, a0, _ = dm.susceptibility(H, A, wl.n)
+    assert np.array_equal(_np(D), np.eye(wl.n)) and not _np(chi).any()
+    assert abs(a0[0] - 2.0 * np.trace(wl.A[0].astype(np.float64))) < 1e-9 * wl.n
+
+
+def test_tiny_matrices(gpu):
+    dm = _dm()
+    g = {"H": [[0.0, 1.0], [1.0, 0.0]], "A": [[1.0, 0.0], [0.0, -1.0]]}
+    chi, D, _, _ = dm.susceptibility(_dev(g["H"], gpu), _dev(g["A"], gpu), 1, spin=1.0)
+    assert np.allclose(_np(D), [[0.5, -0.5], [-0.5, 0.5]], atol=1e-6)
+    assert np.allclose(_np(chi), [[-0.5, 0.0], [0.0, 0.5]], atol=1e-5)
+    D1, _ = dm.sp2_density(_dev([[0.3]], gpu), 1)
+    assert abs(_np(D1)[0, 0] - 1.0) < 1e-6
+
+
+def test_error_statuses(gpu):
+    dm = _dm()
+    wl = _case("c1")
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    bad = wl.H.copy()
+    bad[3, 5] = np.nan
+    with pytest.raises(dm.DMPTError) as e:
+        dm.susceptibility(_dev(bad, gpu), A, wl.nocc)
+    assert e.value.status_name == "DMPT_ERR_NONFINITE"
+    w = np.linalg.eigvalsh(wl.H.astype(np.float64))
+    with pytest.raises(dm.DMPTError) as e:
+        dm.susceptibility(H, A, wl.nocc, bounds="given", emin=0.5 * (w[0] + w[-1]), emax=w[-1] + 0.1)
+    assert e.value.status_name == "DMPT_ERR_BOUNDS"
+    with pytest.raises(dm.DMPTError) as e:
+        dm.susceptibility(H, A, wl.nocc, max_iter=3)
+    assert e.value.status_name == "DMPT_ERR_NOT_CONVERGED"
+    gl = W.gapless(128, 64).astype(np.float32)
+    with pytest.raises(dm.DMPTError) as e:
+        dm.sp2_density(_dev(gl, gpu), 64)
+    assert e.value.status_name == "DMPT_ERR_NOT_CONVERGED"
+
+
+def test_deterministic(gpu):
+    dm = _dm()
+    wl = _case("dense300")
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    c1, d1, _, i1 = dm.susceptibility(H, A, wl.nocc, precision="split3_bf16")
+    c2, d2, _, i2 = dm.susceptibility(H, A, wl.nocc, precision="split3_bf16")
+    assert i1["sigma"] == i2["sigma"]
+    assert np.array_equal(_np(c1), _np(c2)) and np.array_equal(_np(d1), _np(d2))
