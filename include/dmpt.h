@@ -106,11 +106,12 @@ typedef struct dmpt_info {
   double emin, emax;                    /* bounds used */
   double beta;                          /* -1/(emax - emin), Eq. DM0 */
   double trace_d;                       /* Tr D (FP64) */
-  double idem_err;                      /* Tr D - ||D||_F^2 (FP64) */
+  double idem_err;                      /* ||D - D^2||_F^2 (FP64 sum of the step kernel's FP32 values) */
   double elapsed_ms;                    /* device time of the call (events on opts.stream) */
   int8_t sigma[DMPT_MAX_STEPS + 1];     /* sigma_n, n = 1..m */
   double trace_x[DMPT_MAX_STEPS + 1];   /* Tr X_n, n = 1..m+1 */
   double sqnorm_x[DMPT_MAX_STEPS + 1];  /* ||X_n||_F^2, n = 1..m+1 */
+  double idem_x[DMPT_MAX_STEPS + 1];    /* eps_n = ||X_n - X_n^2||_F^2, n = 1..m+1 (0 if not formed) */
   /* Filled when opts.profile = 1 (event pairs on opts.stream around each launch): */
   double bounds_ms;                     /* spectral bounds + X_1/Y_1 initialisation */
   double step_ms;                       /* sum over the m working step-kernel launches */
@@ -177,16 +178,20 @@ typedef struct dmpt_scf_opts {
 dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
                               const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info);
 
-/* Host mirror of the device-side step controller (pure function, no device):
- * given FP64 Tr X_n, ||X_n||_F^2, the idempotency errors of the two previous
- * iterates and the number of steps taken, returns
- *   +1 / -1  : sigma_n for the next step (Sec. II: Tr X_{n+1} closest to N_occ)
- *    0       : stop, X_n is the result
- *   -2       : stop, not converged (a state stuck near 1/2: no gap)
- *   -3       : stop, bounds violation (X_n left the [0,1] spectrum envelope).
- * e_prev2 is e_{n-2} (ignored when steps < 2). */
-int32_t dmpt_sp2_decide(double tr, double sq, double e_prev2, int32_t steps, int32_t n,
-                        double nocc, int32_t min_iter, double idem_tol);
+/* Host mirror of the device-side step controller (pure function, no device).
+ * Decision for iterate X_n (Sec. II) from FP64 Tr X_n, ||X_n||_F^2, its
+ * idempotency error eps = ||X_n - X_n^2||_F^2, eps_prev2 = eps_{n-2} and the
+ * number of steps taken (steps = n - 1), tested in this order:
+ *   -3       : bounds violation (X_n left the [0,1] spectrum envelope)
+ *    0       : stop, X_n is the result: steps >= min_iter and either
+ *              eps <= idem_tol, or eps >= eps_prev2 with eps < 1/64
+ *              (rounding floor reached; needs steps >= 2)
+ *   +1 / -1  : sigma_n for the next step (Tr X_{n+1} closest to N_occ).
+ * The step limit (max_iter, status NOT_CONVERGED) is applied by the caller.
+ * The device makes the same decisions, the stopping test one launch later
+ * (eps_n is a by-product of the launch that forms X_n^2). */
+int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev2, int32_t steps,
+                        int32_t n, double nocc, int32_t min_iter, double idem_tol);
 
 const char* dmpt_status_string(dmpt_status status);
 const char* dmpt_last_error(void);

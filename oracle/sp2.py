@@ -23,16 +23,19 @@ Readings where the paper defers to a reference not reproduced in it
   Tr X_{n+1} closest to N_occ.  Tr X_n^2 = ||X_n||_F^2 for symmetric X_n, so
   both candidate traces, ||X||^2 and 2 Tr X - ||X||^2, are known from Tr X_n
   and ||X_n||_F^2 without forming a product.  Ties go to X^2 (sigma = +1).
-* stop: with the idempotency error e_n = Tr X_n - ||X_n||_F^2 (= sum x(1-x)
-  over the eigenvalues), stop at X_n once at least ``min_iter`` steps were
-  taken and either |e_n| <= idem_tol or |e_n| >= |e_{n-2}| (two further steps
-  did not reduce the error: the arithmetic's rounding floor was reached).
-  Absolute values because at the floor rounding makes e_n of either sign;
-  ``min_iter`` (default 10) guards the first steps, where e_n legitimately
-  rises and falls while the spectrum is spread over [0, 1].
-* unresolved: if at the stop |e_n| > 1/4, some eigenvalue still sits near
-  1/2 (x(1-x) <= 1/4 per state), i.e. no gap separates N_occ states; this is
-  reported as not converged.
+* stop: with the idempotency error eps_n = ||X_n - X_n^2||_F^2 (= sum of
+  (x - x^2)^2 over the eigenvalues, >= 0), stop at X_n once at least
+  ``min_iter`` steps were taken and either eps_n <= idem_tol, or
+  eps_n >= eps_{n-2} while eps_n < 1/64 (every state resolved to
+  |x - x^2| < 1/8 and two further steps did not reduce the error: the
+  arithmetic's rounding floor was reached).  The squared Frobenius measure
+  cannot cancel between states above 1 and below 0 the way the trace
+  measure Tr X - ||X||_F^2 does, so it stops at the floor instead of letting
+  repeated same-sign steps amplify rounding noise.  ``min_iter`` (default 10)
+  guards the first steps, where the error rises and falls while the spectrum
+  is spread over [0, 1].
+* unresolved: without a gap at N_occ some state stays near x = 1/2, eps_n
+  never drops below 1/64 and the step limit reports not converged.
 * bounds violation: a spectrum inside [0, 1] has 0 <= ||X||_F^2 <= n and
   0 <= Tr X <= n; an X_n outside these (or non-finite) means the supplied
   [emin, emax] did not enclose the spectrum of H and the recursion diverged.
@@ -61,7 +64,7 @@ class SP2Trace:
     sigmas: list = field(default_factory=list)   # sigma_n, n = 1..M
     traces: list = field(default_factory=list)   # Tr X_n, n = 1..M+1
     sqnorms: list = field(default_factory=list)  # ||X_n||_F^2
-    errors: list = field(default_factory=list)   # e_n
+    errors: list = field(default_factory=list)   # eps_n = ||X_n - X_n^2||_F^2
 
     @property
     def m(self) -> int:
@@ -91,9 +94,9 @@ def choose_sigma(tr: float, sq: float, nocc: float) -> int:
     return 1 if abs(t_square - nocc) <= abs(t_other - nocc) else -1
 
 
-def sp2_update(x: np.ndarray, sigma: int) -> np.ndarray:
+def sp2_update(x: np.ndarray, sigma: int, x2: np.ndarray | None = None) -> np.ndarray:
     """X_{n+1} = (1 - sigma) X_n + sigma X_n^2  (Eq. DM0)."""
-    return (1 - sigma) * x + sigma * (x @ x)
+    return (1 - sigma) * x + sigma * (x @ x if x2 is None else x2)
 
 
 def response_update(y: np.ndarray, x: np.ndarray, sigma: int) -> np.ndarray:
@@ -105,13 +108,17 @@ def _stats(x: np.ndarray) -> tuple[float, float]:
     return float(np.trace(x)), float(np.sum(x * x))
 
 
-def _should_stop(errors: list, steps: int, min_iter: int, idem_tol: float) -> bool:
+UNRESOLVED = 1.0 / 64.0   # eps above this: some state still has |x - x^2| >= 1/8
+
+
+def should_stop(errors: list, steps: int, min_iter: int, idem_tol: float) -> bool:
+    """Stopping test for the newest iterate (errors[-1] = eps_n, steps = n - 1)."""
     if steps < min_iter:
         return False
-    e = abs(errors[-1])
+    e = errors[-1]
     if e <= idem_tol:
         return True
-    return len(errors) >= 3 and e >= abs(errors[-3])
+    return len(errors) >= 3 and e >= errors[-3] and e < UNRESOLVED
 
 
 def _check_bounds(tr: float, sq: float, n: int) -> None:
@@ -151,19 +158,18 @@ def sp2_merged(h: np.ndarray, ys: list, nocc: int, emin: float | None = None,
     for step in range(max_iter + 1):
         t, q = _stats(x)
         _check_bounds(t, q, n)
+        x2 = x @ x
         tr.traces.append(t)
         tr.sqnorms.append(q)
-        tr.errors.append(t - q)
-        if _should_stop(tr.errors, step, min_iter, idem_tol):
-            if abs(tr.errors[-1]) > 0.25:
-                raise NotConvergedError("SP2 stalled with an unresolved state (no gap at N_occ)")
+        tr.errors.append(float(np.sum((x - x2) ** 2)))
+        if should_stop(tr.errors, step, min_iter, idem_tol):
             return x, yv, tr
         if step == max_iter:
             break
         s = choose_sigma(t, q, nocc)
         tr.sigmas.append(s)
         yv = [response_update(y, x, s) for y in yv]
-        x = sp2_update(x, s)
+        x = sp2_update(x, s, x2)
     raise NotConvergedError(f"SP2 did not converge in {max_iter} steps")
 
 

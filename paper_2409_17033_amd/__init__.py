@@ -155,9 +155,10 @@ def response(chi, H1, *, stream=None):
     return np.array(out[:], dtype=np.float64).reshape(k, p)
 
 
-def sp2_decide(tr, sq, e_prev2, steps, n, nocc, min_iter=10, idem_tol=0.0) -> int:
-    """Host mirror of the device step controller (see include/dmpt.h)."""
-    return int(load().dmpt_sp2_decide(tr, sq, e_prev2, steps, n, nocc, min_iter, idem_tol))
+def sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter=10, idem_tol=0.0) -> int:
+    """Host mirror of the device step controller (dmpt_sp2_decide in include/dmpt.h):
+    -3 bounds violation, 0 stop, else sigma_n (+1 / -1) for iterate X_n."""
+    return int(load().dmpt_sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter, idem_tol))
 
 
 def scf_response(H0, U, A, nocc: int, *, max_iter=50, mix=0.3, tol=1e-6, **kw):

@@ -55,6 +55,7 @@ class Info(C.Structure):
         ("sigma", C.c_int8 * (DMPT_MAX_STEPS + 1)),
         ("trace_x", C.c_double * (DMPT_MAX_STEPS + 1)),
         ("sqnorm_x", C.c_double * (DMPT_MAX_STEPS + 1)),
+        ("idem_x", C.c_double * (DMPT_MAX_STEPS + 1)),
         ("bounds_ms", C.c_double), ("step_ms", C.c_double), ("project_ms", C.c_double),
         ("output_ms", C.c_double), ("step_launches", C.c_int32), ("tile", C.c_int32),
     ]
@@ -67,6 +68,7 @@ class Info(C.Structure):
             "idem_err": self.idem_err, "elapsed_ms": self.elapsed_ms,
             "sigma": list(self.sigma[:m]), "trace_x": list(self.trace_x[:m + 1]),
             "sqnorm_x": list(self.sqnorm_x[:m + 1]),
+            "idem_x": list(self.idem_x[:m + 1]),
             "bounds_ms": self.bounds_ms, "step_ms": self.step_ms, "project_ms": self.project_ms,
             "output_ms": self.output_ms, "step_launches": self.step_launches, "tile": self.tile,
         }
@@ -112,7 +114,7 @@ def load() -> C.CDLL:
     lib.dmpt_response.restype = C.c_int
     lib.dmpt_scf_response.argtypes = [P, P, P, P, C.POINTER(SCFOpts), C.POINTER(Opts), C.POINTER(Info)]
     lib.dmpt_scf_response.restype = C.c_int
-    lib.dmpt_sp2_decide.argtypes = [D, D, D, I32, I32, D, I32, D]
+    lib.dmpt_sp2_decide.argtypes = [D, D, D, D, I32, I32, D, I32, D]
     lib.dmpt_sp2_decide.restype = I32
     lib.dmpt_status_string.argtypes = [C.c_int]
     lib.dmpt_status_string.restype = C.c_char_p

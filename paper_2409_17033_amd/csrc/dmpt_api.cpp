@@ -98,20 +98,15 @@ struct Plan {
   int njobs_max, njobs_proj_max, lz_steps;
 };
 
-// FP32 and split-3 products use 128 x 128 tiles with two-level accumulation
-// (two accumulator sets fit the register file); split-2 and plain BF16 use
-// 256 x 256 tiles with one accumulator chain.
-int main_tile(int prec) { return (prec == kFP32 || prec == kSplit3) ? 128 : 256; }
-
-// Stages between flushes of the MFMA accumulator into the running tile sum:
-// balances the inner chain (flush x MFMAs per stage) against the outer chain
-// (stages / flush), i.e. flush ~ sqrt(stages / chain).  0 = single level.
-int flush_interval(int prec, int tile, int n_pad) {
-  if (tile != 128) return 0;
-  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : prec == kSplit2 ? 3 : 4;
+// Two-level accumulation: the MFMA accumulator is added into the running tile
+// sum every `flush` groups of 4 pipeline stages.  Balancing the inner chain
+// (F stages x MFMAs per stage per block) against the outer one (stages / F)
+// gives F ~ sqrt(stages / chain).
+int flush_interval(int prec, int n_pad) {
+  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : prec == kSplit2 ? 3 : 2;
   const int stages = n_pad / stage_k(prec);
-  const int f = (int)std::lround(std::sqrt((double)stages / chain));
-  return std::max(1, f);
+  const double f = std::sqrt((double)stages / chain) / 4.0;
+  return std::max(1, (int)std::lround(f));
 }
 
 void make_plan(const Opts& o, int nobs, Plan* p) {
@@ -119,24 +114,24 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   p->n_pad = (o.n + kPadTo - 1) / kPadTo * kPadTo;
   p->nobs = nobs;
   p->prec = o.prec;
-  p->tile = main_tile(o.prec);
-  p->ntile = p->n_pad / p->tile;
+  p->tile = kStepTM;
+  p->ntile = p->n_pad / kStepTN;                       // 128-column blocks
   p->nb64 = p->n_pad / 64;
-  p->nparts_step = p->ntile * (p->ntile + 1) / 2;
+  p->nparts_step = step_tile_count(p->n_pad);
   const bool adjoint = nobs > 0 && o.sweep == DMPT_SWEEP_ADJOINT;
-  p->xslots = adjoint ? o.max_iter + 2 : 2;
+  // the adjoint keeps X_1 .. X_{max_iter+2} (slot n = X_n; the last launch may
+  // write one iterate past the result before the stop is seen)
+  p->xslots = adjoint ? o.max_iter + 3 : 2;
   const size_t np2 = (size_t)p->n_pad * p->n_pad;
   p->mat_f32 = np2 * 4;
   p->mat_op = o.prec == kFP32 ? 0 : np2 * operand_bytes(o.prec);
   p->lz_steps = o.lanczos_steps;
-  const int ut = p->nparts_step;                       // upper tiles at the main tile
-  const int t128 = p->n_pad / 128;
-  const int ut128 = t128 * (t128 + 1) / 2;
+  const int ut = p->nparts_step;                       // step tiles covering the upper triangle
   p->njobs_max = ut * (1 + std::max(nobs, 0));
-  p->njobs_proj_max = ut128 * std::max(nobs, 1);
+  p->njobs_proj_max = ut * std::max(nobs, 1);
   size_t off = 0;
   p->off_ctl = off; off = align_up(off + sizeof(Ctl));
-  const size_t part_bytes = (size_t)p->nb64 * p->nb64 * sizeof(double2);
+  const size_t part_bytes = (size_t)p->nb64 * p->nb64 * sizeof(Part);
   p->off_part[0] = off; off = align_up(off + part_bytes);
   p->off_part[1] = off; off = align_up(off + part_bytes);
   p->off_jobs = off; off = align_up(off + (size_t)p->njobs_max * 4);
@@ -179,18 +174,57 @@ MatRef as_fp32(MatRef m) {
   return m;
 }
 
-// Job list: Z-jobs (the heavier products) first, then P-jobs.  Within a kind
-// the upper tiles are dealt round-robin to the 8 XCDs in row-major order of
-// (I, J) so that consecutive workgroups on one XCD share row panels.
-std::vector<uint32_t> build_jobs(int ntile, int nobs_z, bool with_p) {
-  std::vector<uint32_t> jobs;
-  for (int k = 0; k < nobs_z; ++k)
-    for (int i = 0; i < ntile; ++i)
-      for (int j = i; j < ntile; ++j) jobs.push_back(job_pack(kJobZ, k, i, j));
-  if (with_p)
-    for (int i = 0; i < ntile; ++i)
-      for (int j = i; j < ntile; ++j) jobs.push_back(job_pack(kJobP, 0, i, j));
-  return jobs;
+// Job list over the step tiles (I, J), J >= 2I.  Z-jobs (the heavier
+// products) come first, then P-jobs.  Within a kind the tiles are cut into
+// groups of kGroupI x kGroupJ neighbouring tiles (a group shares kGroupI
+// 256-row A panels and kGroupJ 128-row B panels), and whole groups are dealt
+// to the eight XCDs: workgroups are dispatched round-robin over the XCDs in
+// grid order (block b runs on XCD b % 8), so position p of the list is given
+// the next tile of the group queue of XCD p % 8.  The ~32 workgroups resident
+// on one XCD then stream the same panels through its L2.
+constexpr int kXcds = 8, kGroupI = 4, kGroupJ = 8;
+
+std::vector<std::pair<int, int>> grouped_tiles(int n_pad) {
+  const int tr = n_pad / kStepTM, tc = n_pad / kStepTN;
+  std::vector<std::pair<int, int>> t;
+  for (int gi = 0; gi < tr; gi += kGroupI)
+    for (int gj = 0; gj < tc; gj += kGroupJ)
+      for (int i = gi; i < std::min(tr, gi + kGroupI); ++i)
+        for (int j = std::max(gj, 2 * i); j < std::min(tc, gj + kGroupJ); ++j) t.emplace_back(i, j);
+  return t;
+}
+
+void append_xcd_ordered(std::vector<uint32_t>& out, const std::vector<uint32_t>& jobs) {
+  const size_t gsz = kGroupI * kGroupJ;
+  std::vector<std::vector<uint32_t>> q(kXcds);
+  for (size_t g = 0; g * gsz < jobs.size(); ++g)
+    for (size_t k = g * gsz; k < std::min(jobs.size(), (g + 1) * gsz); ++k) q[g % kXcds].push_back(jobs[k]);
+  std::vector<size_t> head(kXcds, 0);
+  for (size_t left = jobs.size(); left > 0; --left) {
+    int x = (int)(out.size() % kXcds);
+    if (head[x] == q[x].size()) {   // this XCD's queue ran dry: take from the longest one
+      size_t best = 0;
+      for (int y = 0; y < kXcds; ++y)
+        if (q[y].size() - head[y] > best) { best = q[y].size() - head[y]; x = y; }
+    }
+    out.push_back(q[x][head[x]++]);
+  }
+}
+
+std::vector<uint32_t> build_jobs(int n_pad, int nobs_z, bool with_p) {
+  const auto tiles = grouped_tiles(n_pad);
+  std::vector<uint32_t> out, kindjobs;
+  for (int k = 0; k < nobs_z; ++k) {
+    kindjobs.clear();
+    for (auto& t : tiles) kindjobs.push_back(job_pack(kJobZ, k, t.first, t.second));
+    append_xcd_ordered(out, kindjobs);
+  }
+  if (with_p) {
+    kindjobs.clear();
+    for (auto& t : tiles) kindjobs.push_back(job_pack(kJobP, 0, t.first, t.second));
+    append_xcd_ordered(out, kindjobs);
+  }
+  return out;
 }
 
 // ---------------------------------------------------------------- Lanczos (host part)
@@ -413,7 +447,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   }
 
   // job tables
-  const std::vector<uint32_t> jobs = build_jobs(p.ntile, adjoint ? 0 : nobs, true);
+  const std::vector<uint32_t> jobs = build_jobs(p.n_pad, adjoint ? 0 : nobs, true);
   uint32_t* d_jobs = (uint32_t*)(ws + p.off_jobs);
   DMPT_HIP(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * 4, hipMemcpyHostToDevice, s));
   const int njobs_main = (int)jobs.size();
@@ -427,7 +461,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   if (st != DMPT_OK) return st;
 
   auto xslot = [&](int n) { return adjoint ? n : (n & 1); };
-  double2* part[2] = {(double2*)(ws + p.off_part[0]), (double2*)(ws + p.off_part[1])};
+  Part* part[2] = {(Part*)(ws + p.off_part[0]), (Part*)(ws + p.off_part[1])};
   // X_1 (and Y_1 = beta A for the forward sweep) into slot of step 1
   DMPT_HIP(launch_init(p.prec, p.tile, H, A, o.n, p.n_pad, adjoint ? 0 : nobs, nullptr, 0,
                        x_ref(p, ws, xslot(1)), y_ref(p, ws, 1), 0.0, part[1], ctl, s));
@@ -435,6 +469,10 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   std::vector<std::pair<int, int>> step_marks;
 
   // SP2 steps: chunks of launches, host polls the done flag between chunks.
+  // Launch n decides sigma_n from X_n's traces and applies the stopping test
+  // to X_{n-1} (its idempotency error is a by-product of launch n-1), so the
+  // stop is seen one launch late; that launch returns before writing and
+  // X_{n-1}, Y_{n-1} are still in their slots.
   StepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.n = o.n;
@@ -446,7 +484,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.idem_tol = o.idem_tol;
   a.decide = 1;
   a.write_split = 1;
-  a.flush = flush_interval(p.prec, p.tile, p.n_pad);
+  a.flush = flush_interval(p.prec, p.n_pad);
   a.jobs = adjoint ? d_jobs : d_jobs;
   a.ctl = ctl;
   const int njobs_step = adjoint ? p.nparts_step : njobs_main;
@@ -454,8 +492,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   // adjoint X-only run uses the P-jobs only (the table holds no Z-jobs then)
   int done = 0;
   int launched = 0;
-  for (int n = 1; n <= o.max_iter + 1 && !done;) {
-    const int end = std::min(o.max_iter + 1, n + kChunk - 1);
+  for (int n = 1; n <= o.max_iter + 2 && !done;) {
+    const int end = std::min(o.max_iter + 2, n + kChunk - 1);
     for (; n <= end; ++n) {
       a.step = n;
       a.x_in = x_ref(p, ws, xslot(n));
@@ -467,7 +505,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       a.nparts = n == 1 ? p.nb64 * p.nb64 : p.nparts_step;
       a.jobs = step_jobs;
       const int ma = prof.mark();
-      DMPT_HIP(launch_step(p.prec, p.tile, a, njobs_step, s));
+      DMPT_HIP(launch_step(p.prec, a, njobs_step, s));
       step_marks.emplace_back(ma, prof.mark());
       ++launched;
     }
@@ -488,7 +526,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // Eq. DM2: Y_M = A; for n = M..1, Y_{n-1} from Y_n with X_n, sigma_n; chi = beta Y_0.
     DMPT_HIP(launch_init(p.prec, p.tile, nullptr, A, o.n, p.n_pad, -nobs, nullptr, 0,
                          x_ref(p, ws, 0), y_ref(p, ws, 0), 1.0, nullptr, ctl, s));
-    const std::vector<uint32_t> zjobs = build_jobs(p.ntile, nobs, false);
+    const std::vector<uint32_t> zjobs = build_jobs(p.n_pad, nobs, false);
     uint32_t* d_zjobs = d_jobs + p.nparts_step;
     DMPT_HIP(hipMemcpyAsync(d_zjobs, zjobs.data(), zjobs.size() * 4, hipMemcpyHostToDevice, s));
     StepArgs b = a;
@@ -501,7 +539,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.x_in = x_ref(p, ws, xslot(n));
       b.y_in = y_ref(p, ws, ys);
       b.y_out = y_ref(p, ws, ys ^ 1);
-      DMPT_HIP(launch_step(p.prec, p.tile, b, (int)zjobs.size(), s));
+      DMPT_HIP(launch_step(p.prec, b, (int)zjobs.size(), s));
       ys ^= 1;
     }
     yfin = ys;
@@ -511,19 +549,17 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // Occupied-virtual projection: two FP32 sweep steps with X frozen at D
     // (sigma = +1 then -1) multiply the eigenbasis blocks of Y by
     // (f_i + f_j)(2 - f_i - f_j): 1 on occupied-virtual pairs, 0 elsewhere.
-    const int pt = 128;
-    const int ntp = p.n_pad / pt;
-    const std::vector<uint32_t> pjobs = build_jobs(ntp, nobs, false);
+    const std::vector<uint32_t> pjobs = build_jobs(p.n_pad, nobs, false);
     uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
     DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));
     StepArgs b;
     std::memset(&b, 0, sizeof(b));
     b.n = o.n;
     b.n_pad = p.n_pad;
-    b.ntile = ntp;
+    b.ntile = p.ntile;
     b.decide = 0;
     b.write_split = 0;
-    b.flush = flush_interval(kFP32, pt, p.n_pad);
+    b.flush = flush_interval(kFP32, p.n_pad);
     b.jobs = d_pjobs;
     b.ctl = ctl;
     b.x_in = as_fp32(x_ref(p, ws, xfin));
@@ -531,7 +567,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.fixed_sigma = q == 0 ? 1 : -1;
       b.y_in = as_fp32(y_ref(p, ws, yfin));
       b.y_out = as_fp32(y_ref(p, ws, yfin ^ 1));
-      DMPT_HIP(launch_step(kFP32, pt, b, (int)pjobs.size(), s));
+      DMPT_HIP(launch_step(kFP32, b, (int)pjobs.size(), s));
       yfin ^= 1;
     }
   }
@@ -562,10 +598,11 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     for (int q = 1; q <= m + 1 && q <= DMPT_MAX_STEPS + 1; ++q) {
       info->trace_x[q - 1] = hctl.rec[q].tr;
       info->sqnorm_x[q - 1] = hctl.rec[q].sq;
+      info->idem_x[q - 1] = hctl.rec[q].eps;
       if (q <= m) info->sigma[q - 1] = (int8_t)hctl.rec[q].sigma;
     }
     info->trace_d = hctl.rec[m + 1].tr;
-    info->idem_err = hctl.rec[m + 1].tr - hctl.rec[m + 1].sq;
+    info->idem_err = hctl.rec[m + 1].eps;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
     info->elapsed_ms = ms;
@@ -671,9 +708,9 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
   return fail(DMPT_ERR_UNSUPPORTED, "dmpt_scf_response is not implemented in this build");
 }
 
-int32_t dmpt_sp2_decide(double tr, double sq, double e_prev2, int32_t steps, int32_t n, double nocc,
-                        int32_t min_iter, double idem_tol) {
-  return sp2_decide(tr, sq, e_prev2, steps, n, nocc, min_iter, idem_tol);
+int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev2, int32_t steps, int32_t n,
+                        double nocc, int32_t min_iter, double idem_tol) {
+  return sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter, idem_tol);
 }
 
 const char* dmpt_status_string(dmpt_status st) {

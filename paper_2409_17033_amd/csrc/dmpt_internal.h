@@ -30,8 +30,15 @@ constexpr int kMaxObs = 64;
 struct StepRec {
   double tr;    // Tr X_n
   double sq;    // ||X_n||_F^2
+  double eps;   // ||X_n - X_n^2||_F^2 (known one launch later)
   int sigma;    // sigma_n (0 if the recursion stopped at X_n)
   int pad;
+};
+
+// Per-tile FP64 partials written by the X-product jobs of step n:
+// (Tr X_{n+1}, ||X_{n+1}||_F^2, ||X_n - X_n^2||_F^2, unused).
+struct Part {
+  double tr, sq, eps, pad;
 };
 
 // Device control block (lives at the start of the workspace).
@@ -76,8 +83,8 @@ struct StepArgs {
                              // running tile sum every `flush` stages (0: single level)
   const uint32_t* jobs;
   MatRef x_in, x_out, y_in, y_out;
-  const double2* part_in;    // per-tile (Tr, ||.||^2) partials of X_n
-  double2* part_out;         // ... of X_{n+1}
+  const Part* part_in;       // partials written by the previous step (or X_1's init)
+  Part* part_out;
   int nparts;
   Ctl* ctl;
 };
@@ -93,8 +100,12 @@ hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, 
 hipError_t launch_set_bounds(Ctl* ctl, double emin, double emax, hipStream_t s);
 hipError_t launch_init(int prec, int tile, const float* h, const float* a, int n, int n_pad,
                        int nobs, const uint32_t* jobs, int njobs, MatRef x, MatRef y,
-                       double y_scale_mode, double2* part, Ctl* ctl, hipStream_t s);
-hipError_t launch_step(int prec, int tile, const StepArgs& args, int njobs, hipStream_t s);
+                       double y_scale_mode, Part* part, Ctl* ctl, hipStream_t s);
+hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s);
+// Step tiles are 256 rows x 128 columns; tile (I, J) with J >= 2I covers the
+// upper triangle.  ntile in StepArgs is the number of 128-column blocks.
+constexpr int kStepTM = 256, kStepTN = 128;
+inline int step_tile_count(int n_pad) { const int t = n_pad / kStepTM; return t * (t + 1); }
 hipError_t launch_output(const float* x32, const float* y32, size_t ystride, const float* a,
                          int n, int n_pad, int nobs, float* d_out, float* chi_out,
                          double scale, int scale_by_beta, const uint32_t* jobs, int njobs,

@@ -56,12 +56,30 @@ template <int PREC> struct Fmt {
 
 int stage_k(int prec) { return prec == kBF16 ? 32 : 16; }
 
-template <int TILE> struct Geo;
-template <> struct Geo<256> {   // 8 waves as 2 x 4, wave tile 128 x 64
-  static constexpr int WM = 2, WN = 4, NW = 8, NT = 512;
-};
-template <> struct Geo<128> {   // 4 waves as 2 x 2, wave tile 64 x 64
-  static constexpr int WM = 2, WN = 2, NW = 4, NT = 256;
+// Step-kernel geometry: output tiles of TM x TN = 256 x 128 computed by
+// eight waves (two per SIMD, 4 x 2), each owning a 64 x 64 region = 2 x 2
+// MFMA blocks of 32 x 32.  Operands stream through a ring of RING LDS slots,
+// each holding one stage (16 or 32 k values) of the 256-row A panel and the
+// 128-row B panel.
+constexpr int TM = 256, TN = 128, NW = 8, NT = 512, RING = 4;
+constexpr int BR = 2, BC = 2;
+constexpr int RBLK = 128;   // rows per chunk of the tiled operand layout
+
+// Tiled operand layout (all formats except FP32, which stays row-major): the
+// copy of an n_pad x n_pad matrix is cut into chunks of 128 rows x one stage
+// of K.  Chunk (rb, st) sits at byte ((rb * nst + st) * CHUNK) and holds its
+// rows back to back, RB bytes each, with the same XOR slot swizzle the LDS
+// ring uses, so a stage is DMA'd with contiguous 1 KB copies and lands in LDS
+// already swizzled.
+template <int PREC> struct Pipe {
+  static constexpr int RB = Fmt<PREC>::RB;             // bytes per panel row per stage
+  static constexpr int S = Fmt<PREC>::S;               // 16-byte slots per row
+  static constexpr int A_BYTES = TM * RB, B_BYTES = TN * RB;
+  static constexpr int SLOT = A_BYTES + B_BYTES;       // bytes per ring slot
+  static constexpr int CHUNK = RBLK * RB;              // bytes per 128-row stage chunk
+  static constexpr int NI = SLOT / 1024;               // 1 KB DMA instructions per stage
+  static constexpr int L = (NI + NW - 1) / NW;         // per wave (padded with dummies)
+  static constexpr bool TILED = PREC != kFP32;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -101,277 +119,277 @@ __device__ __forceinline__ int phys_slot(int r, int ls) {
 template <int S>
 __device__ __forceinline__ int swz(int r, int ls) { return r * (S * 16) + 16 * phys_slot<S>(r, ls); }
 
-// Issue the direct-to-LDS loads of one panel stage: TILE rows x S*16 bytes.
-// `src` points at row 0 of the panel at the stage's byte offset.  The panel
-// is TILE*S slots of 16 B; instruction j (of TILE*S/64) fills slots
-// [64 j, 64 j + 64), lane i slot q = 64 j + i = (row q / S, physical slot q % S)
-// and fetches the logical slot that the swizzle maps there.
-template <int TILE, int S>
-__device__ __forceinline__ void stage_panel(const char* src, size_t ldb, LDS_AS char* panel,
-                                            int wave, int lane) {
-  constexpr int NW = Geo<TILE>::NW;
-  constexpr int NI = TILE * S / 64;
-  static_assert(NI % NW == 0, "panel instructions must split evenly over the waves");
+__device__ __forceinline__ u32x4 lds16(const LDS_AS char* p) { return *(const LDS_AS u32x4*)p; }
+
+// s_waitcnt with vmcnt = V and lgkmcnt = 0 (LGKM0) or untouched.  The builtin
+// (not inline asm) lets the compiler's wait-count pass see the wait.
+template <int V, bool LGKM0>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(V >= 0 && V < 64, "vmcnt range");
+  constexpr int enc = (V & 15) | ((V >> 4) << 14) | (7 << 4) | ((LGKM0 ? 0 : 15) << 8);
+  __builtin_amdgcn_s_waitcnt(enc);
+}
+
+// Workgroup barrier without the implicit memory fence of __syncthreads (which
+// would drain every in-flight prefetch); the empty asm statements stop the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void barrier_nofence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// DMA of one stage into a ring slot, row-major operands (FP32): rows [0, TM)
+// of the A panel and [0, TN) of the B panel, `a` / `b` pointing at row 0 at
+// the stage's byte offset.  The panel is (rows x S) 16-byte slots;
+// instruction j covers slots [64 j, 64 j + 64): lane i takes slot
+// q = 64 j + i = (row q / S, physical slot q % S) and fetches the logical
+// slot the swizzle maps there (the XOR swizzle is its own inverse).
+template <int PREC>
+__device__ __forceinline__ void dma_stage_rows(LDS_AS char* slot, const char* a, const char* b, uint32_t ldb,
+                                               int wave, int lane) {
+  using P = Pipe<PREC>;
+  constexpr int NA = TM * P::S / 64;   // A instructions
 #pragma unroll
-  for (int jj = 0; jj < NI / NW; ++jj) {
+  for (int jj = 0; jj < P::L; ++jj) {
     const int j = wave + jj * NW;
-    const int q = 64 * j + lane;
-    const int r = q / S;
-    const int ls = phys_slot<S>(r, q % S);   // the XOR swizzle is an involution
-    const char* g = src + (size_t)r * ldb + ls * 16;
-    __builtin_amdgcn_global_load_lds((const GLB_AS void*)g, (LDS_AS void*)(panel + j * 1024), 16, 0, 0);
+    const bool isA = j < NA;
+    const int q = 64 * (isA ? j : j - NA) + lane;
+    const int r = q / P::S;
+    const uint32_t off = (uint32_t)r * ldb + 16u * (uint32_t)phys_slot<P::S>(r, q % P::S);
+    __builtin_amdgcn_global_load_lds((const GLB_AS void*)((isA ? a : b) + off), (LDS_AS void*)(slot + j * 1024),
+                                     16, 0, 0);
   }
 }
 
-__device__ __forceinline__ u32x4 lds16(const LDS_AS char* p) { return *(const LDS_AS u32x4*)p; }
-
-__device__ __forceinline__ void wait_vm0() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-// ---------------------------------------------------------------- mainloop
-
-template <int TILE> struct Acc {
-  static constexpr int BR = TILE / Geo<TILE>::WM / 32, BC = TILE / Geo<TILE>::WN / 32;
-};
-
-// One pass: tot[bi][bj] += A_I B_J^T over the full K range, for the wave's
-// 32 x 32 blocks.  A_I / B_J are TILE-row panels of the operand copies
-// (row-major, ldb bytes per row).  A Z-job is two passes into the same tile
-// sum (Y_I X_J^T, then X_I Y_J^T); a P-job is one pass (X_I X_J^T).
-// `same` (A and B are the same panel: diagonal P tile) stages only one panel.
-//   kSplit3: per 16-k stage, logical slot 3h + p = k-group h, part p (hi, mid,
-//            lo); products of order >= 2^-16 kept: hh, hm, mh, hl, lh, mm.
-//   kSplit2: per 16-k stage, slot 2h + p; products hh, hl, lh (lo*lo dropped,
-//            Eq. MixPrecMult).
-//   kBF16:   per 32-k stage, two k16 steps t; slot 2t + h.
-//   kFP32:   per 16-k stage, lane half h holds k in {4h..4h+3} (slot h) and
-//            {8+4h..8+4h+3} (slot h+2); the same k-permutation on A and B.
-// Two-level accumulation (TWO): the MFMA chain runs in `acc` and is added to
-// `tot` every `flush` stages, so no FP32 accumulator sees more than
-// flush x (products per stage) roundings in a row.
-template <int PREC, int TILE, bool TWO>
-__device__ __forceinline__ void mainloop_pass(const char* a, const char* b, size_t ldb, int nstages,
-                                              bool same, int flush, LDS_AS char* lds,
-                                              f32x16 (&acc)[Acc<TILE>::BR][Acc<TILE>::BC],
-                                              f32x16 (&tot)[Acc<TILE>::BR][Acc<TILE>::BC]) {
-  constexpr int WM = Geo<TILE>::WM, WN = Geo<TILE>::WN;
-  constexpr int BR = Acc<TILE>::BR, BC = Acc<TILE>::BC;
-  constexpr int S = Fmt<PREC>::S, RB = Fmt<PREC>::RB;
-  constexpr int PANEL = TILE * RB;   // bytes per panel per stage
-  constexpr int BUF = 2 * PANEL;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = wave / WN, wc = wave % WN;
-  const int h = lane >> 5;
-  const int rowA = wr * (TILE / WM) + (lane & 31);
-  const int rowB = wc * (TILE / WN) + (lane & 31);
-  const int offB = same ? 0 : PANEL;
-
-  auto issue = [&](int s, int buf) {
-    const size_t kb = (size_t)s * RB;
-    LDS_AS char* base = lds + buf * BUF;
-    stage_panel<TILE, S>(a + kb, ldb, base, wave, lane);
-    if (!same) stage_panel<TILE, S>(b + kb, ldb, base + PANEL, wave, lane);
-  };
-
-  issue(0, 0);
-  int since = 0;
-  for (int s = 0; s < nstages; ++s) {
-    const int buf = s & 1;
-    wait_vm0();
-    __syncthreads();
-    const LDS_AS char* pA = lds + buf * BUF;
-    const LDS_AS char* pB = pA + offB;
-
-    if constexpr (PREC == kSplit3 || PREC == kSplit2) {
-      constexpr int T = Terms<PREC>::T;
-      bf16x8 A[BR][T], B[BC][T];
+// DMA of one stage, tiled operands: the stage is three contiguous chunks (A
+// rows 0-127, A rows 128-255, B rows 0-127) copied 1 KB per instruction.
+// Instructions beyond the stage (when NI is not a multiple of NW) re-read the
+// first kilobyte into a scratch area nobody reads, so every wave issues L.
+template <int PREC>
+__device__ __forceinline__ void dma_stage_tiled(LDS_AS char* slot, LDS_AS char* junk, const char* a0,
+                                                const char* a1, const char* b, int wave, int lane) {
+  using P = Pipe<PREC>;
+  constexpr int NC = P::CHUNK / 1024;   // instructions per chunk
 #pragma unroll
-      for (int j = 0; j < BC; ++j)
-#pragma unroll
-        for (int p = 0; p < T; ++p)
-          B[j][p] = __builtin_bit_cast(bf16x8, lds16(pB + swz<S>(rowB + 32 * j, T * h + p)));
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int p = 0; p < T; ++p)
-          A[i][p] = __builtin_bit_cast(bf16x8, lds16(pA + swz<S>(rowA + 32 * i, T * h + p)));
-      if (s + 1 < nstages) issue(s + 1, buf ^ 1);
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int j = 0; j < BC; ++j) {
-          f32x16 c = acc[i][j];
-          // smallest terms first
-          if constexpr (T == 3) {
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][1], B[j][1], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][0], B[j][2], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][2], B[j][0], c, 0, 0, 0);
-          }
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][0], B[j][1], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][1], B[j][0], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][0], B[j][0], c, 0, 0, 0);
-          acc[i][j] = c;
-        }
-    } else if constexpr (PREC == kBF16) {
-      bf16x8 A[BR][2], B[BC][2];
-#pragma unroll
-      for (int j = 0; j < BC; ++j)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          B[j][t] = __builtin_bit_cast(bf16x8, lds16(pB + swz<S>(rowB + 32 * j, 2 * t + h)));
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          A[i][t] = __builtin_bit_cast(bf16x8, lds16(pA + swz<S>(rowA + 32 * i, 2 * t + h)));
-      if (s + 1 < nstages) issue(s + 1, buf ^ 1);
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int j = 0; j < BC; ++j) {
-          f32x16 c = acc[i][j];
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][0], B[j][0], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[i][1], B[j][1], c, 0, 0, 0);
-          acc[i][j] = c;
-        }
-    } else {  // kFP32
-      f32x4 A[BR][2], B[BC][2];
-#pragma unroll
-      for (int j = 0; j < BC; ++j)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          B[j][q] = __builtin_bit_cast(f32x4, lds16(pB + swz<S>(rowB + 32 * j, h + 2 * q)));
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          A[i][q] = __builtin_bit_cast(f32x4, lds16(pA + swz<S>(rowA + 32 * i, h + 2 * q)));
-      if (s + 1 < nstages) issue(s + 1, buf ^ 1);
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int j = 0; j < BC; ++j) {
-          f32x16 c = acc[i][j];
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              c = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][q][e], B[j][q][e], c, 0, 0, 0);
-          acc[i][j] = c;
-        }
-    }
-    if constexpr (TWO) {
-      if (++since == flush) {
-        since = 0;
-#pragma unroll
-        for (int i = 0; i < BR; ++i)
-#pragma unroll
-          for (int j = 0; j < BC; ++j) {
-            tot[i][j] += acc[i][j];
-            acc[i][j] = f32x16{0};
-          }
-      }
+  for (int jj = 0; jj < P::L; ++jj) {
+    const int j = wave + jj * NW;
+    const int region = j / NC;
+    const char* src = (region == 0 ? a0 : region == 1 ? a1 : b) + (j - region * NC) * 1024 + lane * 16;
+    if (P::NI % NW != 0 && j >= P::NI) {
+      __builtin_amdgcn_global_load_lds((const GLB_AS void*)(a0 + lane * 16), (LDS_AS void*)junk, 16, 0, 0);
+    } else {
+      __builtin_amdgcn_global_load_lds((const GLB_AS void*)src, (LDS_AS void*)(slot + j * 1024), 16, 0, 0);
     }
   }
-  if constexpr (TWO) {
+}
+
+// Byte offset of element (r, c), split term `part`, in the tiled operand copy.
+template <int PREC>
+__device__ __forceinline__ size_t op_off(int r, int c, int part, int nst) {
+  constexpr int RB = Fmt<PREC>::RB, S = Fmt<PREC>::S, K = Fmt<PREC>::K, T = Terms<PREC>::T;
+  const int rr = r & (RBLK - 1);
+  const int st = c / K, kk = c % K;
+  const int ls = PREC == kBF16 ? (kk >> 3) : T * (kk >> 3) + part;
+  return ((size_t)(r / RBLK) * nst + st) * (size_t)(RBLK * RB) + (size_t)rr * RB + 16 * phys_slot<S>(rr, ls) +
+         (kk & 7) * 2;
+}
+
+// Operand registers of one stage for one wave.
+template <int PREC> struct Ops;
+template <> struct Ops<kSplit3> { bf16x8 a[BR][3], b[BC][3]; };
+template <> struct Ops<kSplit2> { bf16x8 a[BR][2], b[BC][2]; };
+template <> struct Ops<kBF16> { bf16x8 a[BR][2], b[BC][2]; };     // [t]: k16 step
+template <> struct Ops<kFP32> { f32x4 a[BR][2], b[BC][2]; };       // [q]: slot h + 2q
+
+// Read one stage's operands from a ring slot.
+//   split: logical slot T*h + p = k-group h (8 values), part p
+//   BF16:  32-k stage, k16 step t uses slot 2t + h
+//   FP32:  lane half h holds k in {4h..4h+3} (slot h) and {8+4h..} (slot h+2);
+//          the same k-permutation on A and B leaves the contraction unchanged.
+template <int PREC>
+__device__ __forceinline__ void read_ops(const LDS_AS char* slot, Ops<PREC>& o, int rowA, int rowB, int h) {
+  constexpr int S = Pipe<PREC>::S;
+  const LDS_AS char* pA = slot;
+  const LDS_AS char* pB = slot + Pipe<PREC>::A_BYTES;
+  if constexpr (PREC == kSplit3 || PREC == kSplit2) {
+    constexpr int T = Terms<PREC>::T;
 #pragma unroll
     for (int i = 0; i < BR; ++i)
 #pragma unroll
-      for (int j = 0; j < BC; ++j) {
-        tot[i][j] += acc[i][j];
-        acc[i][j] = f32x16{0};
-      }
+      for (int p = 0; p < T; ++p) o.a[i][p] = __builtin_bit_cast(bf16x8, lds16(pA + swz<S>(rowA + 32 * i, T * h + p)));
+#pragma unroll
+    for (int j = 0; j < BC; ++j)
+#pragma unroll
+      for (int p = 0; p < T; ++p) o.b[j][p] = __builtin_bit_cast(bf16x8, lds16(pB + swz<S>(rowB + 32 * j, T * h + p)));
+  } else if constexpr (PREC == kBF16) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) o.a[i][t] = __builtin_bit_cast(bf16x8, lds16(pA + swz<S>(rowA + 32 * i, 2 * t + h)));
+#pragma unroll
+    for (int j = 0; j < BC; ++j)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) o.b[j][t] = __builtin_bit_cast(bf16x8, lds16(pB + swz<S>(rowB + 32 * j, 2 * t + h)));
+  } else {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) o.a[i][q] = __builtin_bit_cast(f32x4, lds16(pA + swz<S>(rowA + 32 * i, h + 2 * q)));
+#pragma unroll
+    for (int j = 0; j < BC; ++j)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) o.b[j][q] = __builtin_bit_cast(f32x4, lds16(pB + swz<S>(rowB + 32 * j, h + 2 * q)));
   }
-  __syncthreads();   // every wave is done with both buffers before the next pass stages
+}
+
+// acc[i][j] += A_i B_j^T for one stage.
+//   split-3: products of order >= 2^-16 (hh, hm, mh, hl, lh, mm), smallest first
+//   split-2: hh + hl + lh (lo*lo dropped, Eq. MixPrecMult)
+template <int PREC>
+__device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC]) {
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      f32x16 c = acc[i][j];
+      if constexpr (PREC == kSplit3) {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][2], o.b[j][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
+      } else if constexpr (PREC == kSplit2) {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
+      } else if constexpr (PREC == kBF16) {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][1], c, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a[i][q][e], o.b[j][q][e], c, 0, 0, 0);
+      }
+      acc[i][j] = c;
+    }
 }
 
 // ---------------------------------------------------------------- step kernel
 
-// Reduce the per-part (Tr, ||.||^2) partials in a fixed order (wave 0), then
-// evaluate the controller.  Returns the DecideCode / sigma to every thread.
+// Launch k of the step kernel: wave 0 reduces the partials the previous
+// launch (or X_1's initialisation) wrote, in a fixed order, giving
+// Tr X_k, ||X_k||_F^2 and eps_{k-1} = ||X_{k-1} - X_{k-1}^2||_F^2.  Then, in
+// order: stop at X_{k-1} (its stopping test), give up at X_{k-1} (step limit),
+// bounds check of X_k, else sigma_k.  Every workgroup evaluates the same FP64
+// numbers in the same order and reaches the same decision; workgroup 0
+// records it.  Returns sigma_k (+1 / -1) or a stop code.
 __device__ int step_controller(const StepArgs& a, int* s_code) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    double tr = 0.0, sq = 0.0;
+    double tr = 0.0, sq = 0.0, eps = 0.0;
     for (int t = lane; t < a.nparts; t += 64) {
-      const double2 p = a.part_in[t];
-      tr += p.x;
-      sq += p.y;
+      const Part p = a.part_in[t];
+      tr += p.tr;
+      sq += p.sq;
+      eps += p.eps;
     }
     tr = wave_sum(tr);
     sq = wave_sum(sq);
+    eps = wave_sum(eps);
     if (lane == 0) {
       Ctl* c = a.ctl;
-      int code;
+      const int k = a.step;
+      int code = 1, m = -1;   // m >= 0: the recursion ends with X_{m+1}
       if (c->nonfinite) {
         code = kDecideNonfinite;
+        m = k - 1;
       } else {
-        const double e2 = (a.step >= 3) ? (c->rec[a.step - 2].tr - c->rec[a.step - 2].sq) : 0.0;
-        code = sp2_decide(tr, sq, e2, a.step - 1, a.n, a.nocc, a.min_iter, a.idem_tol);
-        if ((code == 1 || code == -1) && a.step > a.max_iter) code = kDecideNotConverged;
+        if (k >= 2) {
+          const double e2 = k >= 4 ? c->rec[k - 3].eps : 0.0;
+          if (sp2_should_stop(eps, e2, k - 2, a.min_iter, a.idem_tol)) {
+            code = kDecideStop;
+            m = k - 2;
+          } else if (k - 2 >= a.max_iter) {
+            code = kDecideNotConverged;
+            m = k - 2;
+          }
+        }
+        if (m < 0) {
+          if (!sp2_bounds_ok(tr, sq, a.n)) {
+            code = kDecideBounds;
+            m = k - 1;
+          } else {
+            code = sp2_sigma(tr, sq, a.nocc);
+          }
+        }
       }
       if (blockIdx.x == 0) {
-        c->rec[a.step].tr = tr;
-        c->rec[a.step].sq = sq;
-        c->rec[a.step].sigma = (code == 1 || code == -1) ? code : 0;
-        if (!(code == 1 || code == -1)) {
-          c->m = a.step - 1;
+        c->rec[k].tr = tr;
+        c->rec[k].sq = sq;
+        if (k >= 2) c->rec[k - 1].eps = eps;
+        c->rec[k].sigma = m < 0 ? code : 0;
+        if (m >= 0) {
+          c->m = m;
           c->code = code;
           __threadfence();
           c->done = 1;
         }
       }
-      *s_code = code;
+      *s_code = m < 0 ? code : (code == kDecideStop ? 2 : code);
     }
   }
   __syncthreads();
   return *s_code;
 }
 
-// Store the operand copy (split terms) of 4 values at rows row0..row0+3,
-// column col, and of their mirror (row col, columns row0..row0+3).
+// Operand copy (split terms) of 4 values at rows row0..row0+3, column col,
+// and of their mirror (row col, columns row0..row0+3; row0 % 4 == 0, so the
+// four mirror values of one term are 8 contiguous bytes).
 template <int PREC>
-__device__ __forceinline__ void store_split4(char* oop, size_t oldb, int row0, int col, const float (&v)[4],
-                                             bool mirror) {
+__device__ __forceinline__ void store_split4(char* oop, int nst, int row0, int col, const float (&v)[4]) {
   constexpr int T = Terms<PREC>::T;
-  constexpr int GB = 16 * T;   // bytes per group of 8 columns
   unsigned short part[4][T];
 #pragma unroll
   for (int e = 0; e < 4; ++e) split_terms<T>(v[e], part[e]);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    char* rp = oop + (size_t)(row0 + e) * oldb + (col >> 3) * GB + (col & 7) * 2;
+  for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int t = 0; t < T; ++t) *(unsigned short*)(rp + 16 * t) = part[e][t];
-  }
-  if (mirror) {
-    char* mp = oop + (size_t)col * oldb + (row0 >> 3) * GB + (row0 & 7) * 2;
+    for (int t = 0; t < T; ++t) *(unsigned short*)(oop + op_off<PREC>(row0 + e, col, t, nst)) = part[e][t];
 #pragma unroll
-    for (int t = 0; t < T; ++t)
-      *(u32x2*)(mp + 16 * t) = u32x2{part[0][t] | ((unsigned)part[1][t] << 16),
-                                     part[2][t] | ((unsigned)part[3][t] << 16)};
-  }
+  for (int t = 0; t < T; ++t)
+    *(u32x2*)(oop + op_off<PREC>(col, row0, t, nst)) = u32x2{part[0][t] | ((unsigned)part[1][t] << 16),
+                                                             part[2][t] | ((unsigned)part[3][t] << 16)};
 }
 
 template <int PREC>
-__device__ __forceinline__ void store_split1(char* oop, size_t oldb, int r, int c, float v) {
+__device__ __forceinline__ void store_split1(char* oop, int nst, int r, int c, float v) {
   constexpr int T = Terms<PREC>::T;
-  constexpr int GB = 16 * T;
   unsigned short part[T];
   split_terms<T>(v, part);
-  char* rp = oop + (size_t)r * oldb + (c >> 3) * GB + (c & 7) * 2;
 #pragma unroll
-  for (int t = 0; t < T; ++t) *(unsigned short*)(rp + 16 * t) = part[t];
+  for (int t = 0; t < T; ++t) *(unsigned short*)(oop + op_off<PREC>(r, c, t, nst)) = part[t];
 }
 
-template <int PREC, int TILE, bool TWO>
-__global__ __launch_bounds__(Geo<TILE>::NT) __attribute__((amdgpu_waves_per_eu(2))) void k_step(StepArgs a) {
-  constexpr int WM = Geo<TILE>::WM, WN = Geo<TILE>::WN, NW = Geo<TILE>::NW;
-  constexpr int BR = Acc<TILE>::BR, BC = Acc<TILE>::BC;
-  __shared__ __attribute__((aligned(1024))) char lds_raw[2 * 2 * TILE * Fmt<PREC>::RB];
+// Index of step tile (I, J) among the tiles that cover the upper triangle:
+// row block I (256 rows), column block J >= 2I (128 columns), tcols = n_pad/128.
+__device__ __forceinline__ int tile_index(int ti, int tj, int tcols) {
+  return ti * tcols - ti * (ti - 1) + (tj - 2 * ti);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(StepArgs a) {
+  using P = Pipe<PREC>;
+  __shared__ __attribute__((aligned(1024))) char ring0[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char ring1[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char ring2[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char ring3[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char junk[P::NI % NW ? 1024 : 16];
   __shared__ int s_code;
-  __shared__ double s_red[2 * NW];
-  LDS_AS char* lds = (LDS_AS char*)lds_raw;
+  __shared__ double s_red[3 * NW];
 
   if (a.decide && a.ctl->done) return;
   int sigma;
@@ -386,16 +404,28 @@ __global__ __launch_bounds__(Geo<TILE>::NT) __attribute__((amdgpu_waves_per_eu(2
   const uint32_t job = a.jobs[blockIdx.x];
   const int kind = job & 1;
   const int obs = (job >> 1) & 127;
-  const int ti = (job >> 8) & 4095;
-  const int tj = (job >> 20) & 4095;
-  const bool diag = ti == tj;
+  const int ti = (job >> 8) & 4095;    // 256-row block
+  const int tj = (job >> 20) & 4095;   // 128-column block
   constexpr int opb = operand_bytes(PREC);
   const size_t ldb = (size_t)a.n_pad * opb;
-  const int nstages = a.n_pad / Fmt<PREC>::K;
+  const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
+  const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
 
   const char* xop = (const char*)a.x_in.op;
   const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
-  const size_t rowI = (size_t)ti * TILE * ldb, rowJ = (size_t)tj * TILE * ldb;
+  // row block I / J starts at the same byte offset in both layouts:
+  // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
+  const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
+  const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
+  const char* b0 = xop + rowJ;
+  const char* a1 = xop + rowI;
+  const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
+  const int h = lane >> 5, l32 = lane & 31;
+  const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
 
   f32x16 acc[BR][BC], tot[BR][BC];
 #pragma unroll
@@ -405,61 +435,121 @@ __global__ __launch_bounds__(Geo<TILE>::NT) __attribute__((amdgpu_waves_per_eu(2
       acc[i][j] = f32x16{0};
       tot[i][j] = f32x16{0};
     }
-  if (kind == kJobZ) {
-    // Z = Y_I X_J^T + X_I Y_J^T  (both products accumulate into one tile)
-    mainloop_pass<PREC, TILE, TWO>(yop + rowI, xop + rowJ, ldb, nstages, false, a.flush, lds, acc, tot);
-    mainloop_pass<PREC, TILE, TWO>(xop + rowI, yop + rowJ, ldb, nstages, false, a.flush, lds, acc, tot);
-  } else {
-    mainloop_pass<PREC, TILE, TWO>(xop + rowI, xop + rowJ, ldb, nstages, diag, a.flush, lds, acc, tot);
+
+  // Stage s of the job's K stream; stages past the end re-fetch stage 0 into
+  // a slot that is never read again, which keeps the vmcnt bookkeeping uniform.
+  const uint32_t ldb32 = (uint32_t)ldb;
+  const size_t chunkb = (size_t)P::CHUNK;
+  auto dma = [&](LDS_AS char* slot, int s) {
+    const int sc = s < nst ? s : 0;
+    const bool second = sc >= spass;
+    const int st = second ? sc - spass : sc;
+    const char* pa = second ? a1 : a0;
+    const char* pb = second ? b1 : b0;
+    if constexpr (P::TILED) {
+      // panel bases are the first chunk of their row block; stage st is chunk st
+      const char* ca = pa + (size_t)st * chunkb;
+      dma_stage_tiled<PREC>(slot, (LDS_AS char*)junk, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb,
+                            wave, lane);
+    } else {
+      const size_t kb = (size_t)st * P::RB;
+      dma_stage_rows<PREC>(slot, pa + kb, pb + kb, ldb32, wave, lane);
+    }
+  };
+  LDS_AS char* R0 = (LDS_AS char*)ring0;
+  LDS_AS char* R1 = (LDS_AS char*)ring1;
+  LDS_AS char* R2 = (LDS_AS char*)ring2;
+  LDS_AS char* R3 = (LDS_AS char*)ring3;
+
+  Ops<PREC> o;
+  dma(R0, 0);
+  dma(R1, 1);
+  dma(R2, 2);
+
+  // Iteration s: wait until this wave's DMA of stage s landed (stages s+1 and
+  // s+2 may still be in flight), barrier (so has every wave's), refill the
+  // slot of stage s-1 with stage s+3, then read stage s and multiply.
+#define DMPT_ITER(S_, CUR, REFILL)                       \
+  {                                                       \
+    wait_vm<2 * P::L, false>();                           \
+    barrier_nofence();                                    \
+    dma(REFILL, (S_) + 3);                                \
+    read_ops<PREC>(CUR, o, rowA, rowB, h);                \
+    mma_ops<PREC>(o, acc);                                \
   }
-  if constexpr (!TWO) {
+  const int fl4 = a.flush > 0 ? a.flush : 1 << 30;   // flush every fl4 groups of 4 stages
+  int since = 0;
+  for (int s = 0; s < nst; s += 4) {
+    DMPT_ITER(s + 0, R0, R3)
+    DMPT_ITER(s + 1, R1, R0)
+    DMPT_ITER(s + 2, R2, R1)
+    DMPT_ITER(s + 3, R3, R2)
+    if (++since == fl4) {
+      since = 0;
 #pragma unroll
-    for (int i = 0; i < BR; ++i)
+      for (int i = 0; i < BR; ++i)
 #pragma unroll
-      for (int j = 0; j < BC; ++j) tot[i][j] = acc[i][j];
+        for (int j = 0; j < BC; ++j) {
+          tot[i][j] += acc[i][j];
+          acc[i][j] = f32x16{0};
+        }
+    }
   }
+#undef DMPT_ITER
+  wait_vm<0, true>();
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
 
   // ------------------------------------------------------------ epilogue
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int wr = wave / WN, wc = wave % WN;
-  const int h = lane >> 5, l32 = lane & 31;
   const size_t np = a.n_pad;
   const MatRef& in = kind == kJobZ ? a.y_in : a.x_in;
   const MatRef& out = kind == kJobZ ? a.y_out : a.x_out;
   const float* cur = in.f32 + (kind == kJobZ ? obs * in.stride_f32 : 0);
   float* o32 = out.f32 + (kind == kJobZ ? obs * out.stride_f32 : 0);
   char* oop = (char*)out.op + (kind == kJobZ ? obs * out.stride_op : 0);
-  const size_t oldb = (size_t)a.n_pad * opb;
+  const int nstp = a.n_pad / Fmt<PREC>::K;   // stages per row (tiled layout)
   const bool wsplit = a.write_split && PREC != kFP32;
-  double tr = 0.0, sq = 0.0;
+  const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
+  double tr = 0.0, sq = 0.0, ep = 0.0;
 
   // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
 #pragma unroll
   for (int bi = 0; bi < BR; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BC; ++bj) {
-      const int col = tj * TILE + wc * (TILE / WN) + bj * 32 + l32;
+      const int col = tj * TN + wc * 64 + bj * 32 + l32;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int row0 = ti * TILE + wr * (TILE / WM) + bi * 32 + 8 * g + 4 * h;
-        float v[4];
+        const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
+        float v[4], dx[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float p = tot[bi][bj][4 * g + e];
-          v[e] = sigma > 0 ? p : 2.0f * cur[(size_t)(row0 + e) * np + col] - p;
+          if (kind == kJobP || sigma < 0) {
+            const float c0 = cur[(size_t)(row0 + e) * np + col];
+            v[e] = sigma > 0 ? p : 2.0f * c0 - p;
+            dx[e] = c0 - p;                      // X_n - X_n^2 (P-jobs)
+          } else {
+            v[e] = p;
+            dx[e] = 0.0f;
+          }
         }
-        if (!diag) {
+        if (!onDiag) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) o32[(size_t)(row0 + e) * np + col] = v[e];
           *(f32x4*)(o32 + (size_t)col * np + row0) = f32x4{v[0], v[1], v[2], v[3]};
-          if (wsplit) store_split4<PREC>(oop, oldb, row0, col, v, true);
+          if (wsplit) store_split4<PREC>(oop, nstp, row0, col, v);
           if (kind == kJobP) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sq += 2.0 * (double)v[e] * (double)v[e];
+            for (int e = 0; e < 4; ++e) {
+              sq += 2.0 * (double)v[e] * (double)v[e];
+              ep += 2.0 * (double)dx[e] * (double)dx[e];
+            }
           }
         } else {
-          // diagonal tile: keep the upper triangle and mirror it (exact symmetry)
+          // keep the upper triangle (row <= col) and mirror it: exact symmetry
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int r = row0 + e;
@@ -467,16 +557,18 @@ __global__ __launch_bounds__(Geo<TILE>::NT) __attribute__((amdgpu_waves_per_eu(2
             o32[(size_t)r * np + col] = v[e];
             o32[(size_t)col * np + r] = v[e];
             if (wsplit) {
-              store_split1<PREC>(oop, oldb, r, col, v[e]);
-              if (r != col) store_split1<PREC>(oop, oldb, col, r, v[e]);
+              store_split1<PREC>(oop, nstp, r, col, v[e]);
+              if (r != col) store_split1<PREC>(oop, nstp, col, r, v[e]);
             }
             if (kind == kJobP) {
-              const double d = v[e];
+              const double d = v[e], dd = dx[e];
               if (r == col) {
                 tr += d;
                 sq += d * d;
+                ep += dd * dd;
               } else {
                 sq += 2.0 * d * d;
+                ep += 2.0 * dd * dd;
               }
             }
           }
@@ -487,43 +579,35 @@ __global__ __launch_bounds__(Geo<TILE>::NT) __attribute__((amdgpu_waves_per_eu(2
   if (kind == kJobP) {
     tr = wave_sum(tr);
     sq = wave_sum(sq);
+    ep = wave_sum(ep);
     if (lane == 0) {
-      s_red[2 * wave] = tr;
-      s_red[2 * wave + 1] = sq;
+      s_red[3 * wave] = tr;
+      s_red[3 * wave + 1] = sq;
+      s_red[3 * wave + 2] = ep;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double t = 0.0, q = 0.0;
+      Part p = {0.0, 0.0, 0.0, 0.0};
       for (int w = 0; w < NW; ++w) {
-        t += s_red[2 * w];
-        q += s_red[2 * w + 1];
+        p.tr += s_red[3 * w];
+        p.sq += s_red[3 * w + 1];
+        p.eps += s_red[3 * w + 2];
       }
-      // part index = upper-triangle tile index (row-major over I <= J)
-      const int T = a.ntile;
-      const int pidx = ti * T - ti * (ti - 1) / 2 + (tj - ti);
-      a.part_out[pidx] = double2{t, q};
+      a.part_out[tile_index(ti, tj, a.ntile)] = p;
     }
   }
 }
 
-hipError_t launch_step(int prec, int tile, const StepArgs& args, int njobs, hipStream_t s) {
+hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  const bool two = args.flush > 0;
-#define DMPT_LAUNCH_STEP(P, T, W)                                                  \
-  if (prec == P && tile == T && two == W) {                                        \
-    hipLaunchKernelGGL((k_step<P, T, W>), dim3(njobs), dim3(Geo<T>::NT), 0, s, args); \
-    return hipGetLastError();                                                      \
+  switch (prec) {
+    case kFP32: hipLaunchKernelGGL(k_step<kFP32>, dim3(njobs), dim3(NT), 0, s, args); break;
+    case kSplit2: hipLaunchKernelGGL(k_step<kSplit2>, dim3(njobs), dim3(NT), 0, s, args); break;
+    case kSplit3: hipLaunchKernelGGL(k_step<kSplit3>, dim3(njobs), dim3(NT), 0, s, args); break;
+    case kBF16: hipLaunchKernelGGL(k_step<kBF16>, dim3(njobs), dim3(NT), 0, s, args); break;
+    default: return hipErrorInvalidValue;
   }
-  DMPT_LAUNCH_STEP(kFP32, 128, true)
-  DMPT_LAUNCH_STEP(kFP32, 128, false)
-  DMPT_LAUNCH_STEP(kSplit3, 128, true)
-  DMPT_LAUNCH_STEP(kSplit3, 128, false)
-  DMPT_LAUNCH_STEP(kSplit2, 256, false)
-  DMPT_LAUNCH_STEP(kSplit2, 128, true)
-  DMPT_LAUNCH_STEP(kBF16, 256, false)
-  DMPT_LAUNCH_STEP(kBF16, 128, true)
-#undef DMPT_LAUNCH_STEP
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- control
@@ -732,32 +816,27 @@ hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, 
 
 // ---------------------------------------------------------------- operand copies
 
-// Operand copy of 8 consecutive columns c0..c0+7 (c0 % 8 == 0) of one row:
-// packed split groups [8 x part_0][8 x part_1]... or plain BF16.
-template <int T>
-__device__ __forceinline__ void store_group8_t(char* row, int c0, const float (&v)[8]) {
+// Operand copy of 8 consecutive columns c0..c0+7 (c0 % 8 == 0) of row r, in
+// the tiled layout: each split term of the group is one 16-byte slot.
+template <int PREC>
+__device__ __forceinline__ void store_group8_t(char* op, int nst, int r, int c0, const float (&v)[8]) {
+  constexpr int T = Terms<PREC>::T;
   unsigned short part[8][T];
 #pragma unroll
   for (int e = 0; e < 8; ++e) split_terms<T>(v[e], part[e]);
-  char* p = row + (c0 >> 3) * (16 * T);
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     u32x4 w;
 #pragma unroll
     for (int e = 0; e < 4; ++e) w[e] = part[2 * e][t] | ((unsigned)part[2 * e + 1][t] << 16);
-    *(u32x4*)(p + 16 * t) = w;
+    *(u32x4*)(op + op_off<PREC>(r, c0, t, nst)) = w;
   }
 }
 
-__device__ __forceinline__ void store_group8(int prec, char* row, int c0, const float (&v)[8]) {
-  if (prec == kSplit2) store_group8_t<2>(row, c0, v);
-  else if (prec == kSplit3) store_group8_t<3>(row, c0, v);
-  else if (prec == kBF16) {
-    u32x4 w;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) w[e] = bf16_bits(v[2 * e]) | ((unsigned)bf16_bits(v[2 * e + 1]) << 16);
-    *(u32x4*)(row + c0 * 2) = w;
-  }
+__device__ __forceinline__ void store_group8(int prec, char* op, int n_pad, int r, int c0, const float (&v)[8]) {
+  if (prec == kSplit2) store_group8_t<kSplit2>(op, n_pad / Fmt<kSplit2>::K, r, c0, v);
+  else if (prec == kSplit3) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v);
+  else if (prec == kBF16) store_group8_t<kBF16>(op, n_pad / Fmt<kBF16>::K, r, c0, v);
 }
 
 // Rebuild the operand copy of nmat matrices from their FP32 masters.
@@ -765,7 +844,6 @@ __global__ __launch_bounds__(256) void k_resplit(int prec, MatRef m, int n_pad) 
   const int z = blockIdx.y;
   const float* src = m.f32 + (size_t)z * m.stride_f32;
   char* dst = (char*)m.op + (size_t)z * m.stride_op;
-  const size_t ldb = (size_t)n_pad * operand_bytes(prec);
   const size_t ngroups = (size_t)n_pad * n_pad / 8;
   for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < ngroups; g += (size_t)gridDim.x * 256) {
     const size_t r = g / (n_pad / 8);
@@ -773,7 +851,7 @@ __global__ __launch_bounds__(256) void k_resplit(int prec, MatRef m, int n_pad) 
     const f32x4 a = *(const f32x4*)(src + r * n_pad + c0);
     const f32x4 b = *(const f32x4*)(src + r * n_pad + c0 + 4);
     const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-    store_group8(prec, dst + r * ldb, c0, v);
+    store_group8(prec, dst, n_pad, (int)r, c0, v);
   }
 }
 
@@ -792,7 +870,7 @@ hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s
 // global access is row-contiguous.  Blocks of X emit (Tr, ||.||^2) partials.
 __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const float* a, int n,
                                               int n_pad, int zoff, MatRef x, MatRef y,
-                                              double y_scale_mode, double2* part, Ctl* ctl) {
+                                              double y_scale_mode, Part* part, Ctl* ctl) {
   __shared__ float tile[64][65];
   __shared__ double s_red[8];
   const int bi = blockIdx.y, bj = blockIdx.x;   // output block (row, col)
@@ -850,7 +928,7 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
     float* dst = o32 + (size_t)gi * n_pad + bj * 64 + cg;
     *(f32x4*)dst = f32x4{v[0], v[1], v[2], v[3]};
     *(f32x4*)(dst + 4) = f32x4{v[4], v[5], v[6], v[7]};
-    store_group8(prec, oop + (size_t)gi * ldb, bj * 64 + cg, v);
+    store_group8(prec, oop, n_pad, gi, bj * 64 + cg, v);
   }
   if (z == 0) {
     tr = wave_sum(tr);
@@ -866,7 +944,7 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
         tt += s_red[2 * w];
         qq += s_red[2 * w + 1];
       }
-      part[bi * gridDim.x + bj] = double2{tt, qq};
+      part[bi * gridDim.x + bj] = Part{tt, qq, 0.0, 0.0};
     }
   }
 }
@@ -874,7 +952,7 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
 // nobs >= 0: X_1 and nobs observables; nobs < 0: only the -nobs observables.
 hipError_t launch_init(int prec, int /*tile*/, const float* h, const float* a, int n, int n_pad,
                        int nobs, const uint32_t* /*jobs*/, int /*njobs*/, MatRef x, MatRef y,
-                       double y_scale_mode, double2* part, Ctl* ctl, hipStream_t s) {
+                       double y_scale_mode, Part* part, Ctl* ctl, hipStream_t s) {
   const int nb = n_pad / 64;
   const int zoff = nobs < 0 ? 1 : 0;
   const int nz = nobs < 0 ? -nobs : 1 + nobs;

@@ -8,12 +8,13 @@
 //   Tr X^2 = ||X||_F^2 for symmetric X, the two candidates are ||X||_F^2
 //   (sigma = +1, X <- X^2) and 2 Tr X - ||X||_F^2 (sigma = -1, X <- 2X - X^2).
 //   Ties choose X^2.
-// stop: with e_n = Tr X_n - ||X_n||_F^2 (the sum of x(1-x) over the spectrum
-//   of X_n), stop at X_n once at least min_iter steps were taken and either
-//   |e_n| <= idem_tol or |e_n| >= |e_{n-2}|: two more steps did not reduce the
-//   idempotency error, so the rounding floor of the arithmetic is reached.
-// unresolved: |e_n| > 1/4 at the stop means a state is stuck near x = 1/2,
-//   i.e. no gap separates the N_occ lowest states (not converged).
+// stop: with the idempotency error eps_n = ||X_n - X_n^2||_F^2 (the sum of
+//   (x - x^2)^2 over the spectrum of X_n, >= 0), stop at X_n once at least
+//   min_iter steps were taken and either eps_n <= idem_tol, or
+//   eps_n >= eps_{n-2} while eps_n < 1/64: every state is resolved
+//   (|x - x^2| < 1/8) and two more steps did not reduce the error, so the
+//   rounding floor of the arithmetic is reached.  Without a gap at N_occ a
+//   state stays near x = 1/2 and only the step limit ends the recursion.
 // bounds: a spectrum inside [0, 1] keeps 0 <= ||X||_F^2 <= n and
 //   0 <= Tr X <= n; leaving that envelope (or non-finite traces) means the
 //   spectral bounds did not enclose H and the recursion diverges.
@@ -36,19 +37,34 @@ enum DecideCode : int {
   kDecideNonfinite = -4,   // set by the device when an input held NaN/Inf
 };
 
-DMPT_HD inline int sp2_decide(double tr, double sq, double e_prev2, int steps, int n,
-                              double nocc, int min_iter, double idem_tol) {
-  if (!(isfinite(tr) && isfinite(sq))) return kDecideBounds;
-  if (sq > n + 1.0 || tr < -1.0 || tr > n + 1.0) return kDecideBounds;
-  const double e = tr - sq;
-  if (steps >= min_iter) {
-    const double ae = fabs(e);
-    if (ae <= idem_tol || (steps >= 2 && ae >= fabs(e_prev2)))
-      return ae > 0.25 ? kDecideNotConverged : kDecideStop;
-  }
+constexpr double kUnresolved = 1.0 / 64.0;
+
+DMPT_HD inline bool sp2_bounds_ok(double tr, double sq, int n) {
+  if (!(isfinite(tr) && isfinite(sq))) return false;
+  return !(sq > n + 1.0 || tr < -1.0 || tr > n + 1.0);
+}
+
+// Stopping test for X_n: steps = n - 1, eps = eps_n, eps_prev2 = eps_{n-2}.
+DMPT_HD inline bool sp2_should_stop(double eps, double eps_prev2, int steps, int min_iter,
+                                    double idem_tol) {
+  if (steps < min_iter) return false;
+  if (eps <= idem_tol) return true;
+  return steps >= 2 && eps >= eps_prev2 && eps < kUnresolved;
+}
+
+DMPT_HD inline int sp2_sigma(double tr, double sq, double nocc) {
   const double t_square = sq;
   const double t_other = 2.0 * tr - sq;
   return fabs(t_square - nocc) <= fabs(t_other - nocc) ? 1 : -1;
+}
+
+// Decision for iterate X_n given its traces and idempotency errors (the
+// oracle's order: bounds, stop, sigma).
+DMPT_HD inline int sp2_decide(double tr, double sq, double eps, double eps_prev2, int steps, int n,
+                              double nocc, int min_iter, double idem_tol) {
+  if (!sp2_bounds_ok(tr, sq, n)) return kDecideBounds;
+  if (sp2_should_stop(eps, eps_prev2, steps, min_iter, idem_tol)) return kDecideStop;
+  return sp2_sigma(tr, sq, nocc);
 }
 
 }  // namespace dmpt

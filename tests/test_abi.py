@@ -45,7 +45,8 @@ def test_struct_layouts():
     assert C.sizeof(Opts) == 96
     assert Opts.spin.offset == 64 and Opts.workspace_bytes.offset == 88
     assert Info.sigma.offset == 56
-    assert C.sizeof(Info) == 56 + 256 + 2 * 256 * 8 + 4 * 8 + 2 * 4
+    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4
+    assert Info.idem_x.offset == 56 + 256 + 2 * 256 * 8
     assert Opts.profile.offset == 60
 
 
@@ -159,39 +160,46 @@ def test_controller_sigma_matches_oracle_rule():
         nocc = float(rng.integers(1, n))
         tr = rng.uniform(0, n)
         sq = tr * rng.uniform(0.0, 1.0)
-        got = dm.sp2_decide(tr, sq, 0.0, 0, n, nocc, min_iter=10)
+        got = dm.sp2_decide(tr, sq, 0.5, 0.0, 0, n, nocc, min_iter=10)
         assert got == sp2.choose_sigma(tr, sq, nocc)
 
 
 def test_controller_replays_oracle_run():
-    """Feed the FP64 oracle's trace/sqnorm sequence to the library controller:
-    it must continue with the same sigma at every step and stop at the same M."""
+    """Feed the FP64 oracle's traces and idempotency errors to the library
+    controller: it must continue with the same sigma at every step and stop
+    at the same M."""
     import paper_2409_17033_amd as dm
     import workloads as W
     from oracle import sp2
-    wl = W.dense_gapped(128)
-    h = wl.H.astype(np.float64)
-    _, tr = sp2.sp2_density(h, wl.nocc)
-    for n in range(1, tr.m + 2):
-        t, q = tr.traces[n - 1], tr.sqnorms[n - 1]
-        e2 = tr.errors[n - 3] if n >= 3 else 0.0
-        code = dm.sp2_decide(t, q, e2, n - 1, wl.n, wl.nocc, 10, 0.0)
-        if n <= tr.m:
-            assert code == tr.sigmas[n - 1], n
-        else:
-            assert code == 0
+    for wl in (W.dense_gapped(128), W.dense_gapped(96, nocc=20, gap=0.05)):
+        h = wl.H.astype(np.float64)
+        _, tr = sp2.sp2_density(h, wl.nocc)
+        for n in range(1, tr.m + 2):
+            t, q, e = tr.traces[n - 1], tr.sqnorms[n - 1], tr.errors[n - 1]
+            e2 = tr.errors[n - 3] if n >= 3 else 0.0
+            code = dm.sp2_decide(t, q, e, e2, n - 1, wl.n, wl.nocc, 10, 0.0)
+            if n <= tr.m:
+                assert code == tr.sigmas[n - 1], n
+            else:
+                assert code == 0
 
 
 def test_controller_error_codes():
     import paper_2409_17033_amd as dm
-    assert dm.sp2_decide(float("nan"), 1.0, 0, 0, 10, 5) == -3
-    assert dm.sp2_decide(5.0, 12.0, 0, 0, 10, 5) == -3           # ||X||^2 > n + 1
-    assert dm.sp2_decide(-2.0, 1.0, 0, 0, 10, 5) == -3
-    # stalled at mid-gap: |e| = 0.5 >= |e_{n-2}| after min_iter steps
-    assert dm.sp2_decide(5.0, 4.5, 0.5, 20, 10, 5) == -2
-    # converged floor
-    assert dm.sp2_decide(5.0, 5.0 - 1e-9, 1e-9, 20, 10, 5) == 0
+    # bounds violations come first
+    assert dm.sp2_decide(float("nan"), 1.0, 0.0, 0.0, 0, 10, 5) == -3
+    assert dm.sp2_decide(5.0, 12.0, 0.0, 0.0, 0, 10, 5) == -3        # ||X||^2 > n + 1
+    assert dm.sp2_decide(-2.0, 1.0, 0.0, 0.0, 0, 10, 5) == -3
+    assert dm.sp2_decide(5.0, float("inf"), 0.0, 0.0, 20, 10, 5) == -3
+    # a state at x = 1/2 ((x - x^2)^2 = 1/16 >= 1/64) never stops, even stalled
+    assert dm.sp2_decide(5.0, 4.75, 1 / 16, 1 / 16, 20, 10, 5) in (1, -1)
+    # floor reached: eps stopped falling over two steps and is resolved
+    assert dm.sp2_decide(5.0, 5.0, 1e-12, 1e-12, 20, 10, 5) == 0
+    assert dm.sp2_decide(5.0, 5.0, 2e-12, 1e-12, 20, 10, 5) == 0
+    # still falling: continue
+    assert dm.sp2_decide(5.0, 5.0, 1e-12, 1e-9, 20, 10, 5) in (1, -1)
     # before min_iter no stop even at the floor
-    assert dm.sp2_decide(5.0, 5.0 - 1e-9, 1e-9, 3, 10, 5) in (1, -1)
-    # idem_tol
-    assert dm.sp2_decide(5.0, 5.0 - 1e-7, 1.0, 20, 10, 5, 10, 1e-6) == 0
+    assert dm.sp2_decide(5.0, 5.0, 1e-12, 1e-12, 3, 10, 5) in (1, -1)
+    # exactly idempotent / idem_tol
+    assert dm.sp2_decide(5.0, 5.0, 0.0, 0.0, 10, 10, 5) == 0
+    assert dm.sp2_decide(5.0, 5.0, 5e-7, 1e-9, 20, 10, 5, 10, 1e-6) == 0

@@ -133,9 +133,22 @@ def test_bounds_not_enclosing_raises(c1):
 
 
 def test_gapless_not_converged():
+    """Without a gap a state stays near x = 1/2 (eps >= 1/64), so the stopping
+    test never fires; only rounding, ~log2(width / 1e-16) steps later, would
+    split the degenerate pair.  A 40-step limit (ample for any real gap)
+    reports it."""
     h = W.gapless(24, 12)
     with pytest.raises(sp2.NotConvergedError):
-        sp2.sp2_density(h, 12)
+        sp2.sp2_density(h, 12, max_iter=40)
+
+
+def test_stop_is_at_rounding_floor():
+    """The idempotency error at the stop is at the FP64 floor, far below the
+    unresolved threshold, and the stop fired on stagnation or the tolerance."""
+    wl = W.dense_gapped(128)
+    _, tr = sp2.sp2_density(wl.H.astype(np.float64), wl.nocc)
+    assert tr.errors[-1] < 1e-20
+    assert tr.errors[-1] >= tr.errors[-3] or tr.errors[-1] == 0.0
 
 
 def test_max_iter_not_converged(c1):
