@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--compare", default="fp32,split_bf16", help="other precisions timed for context")
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=1, help="FP64 oracle SP2+chi steps in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=5, help="FP64 oracle SP2+chi steps in the CPU sample")
     return ap.parse_args()
 
 
@@ -112,6 +112,28 @@ def cpu_baseline(wl, m_steps, steps):
     }
 
 
+def measured_traffic(prec, n):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), used only
+    while the kernel sources still hash to the value recorded with it."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_step_{prec}_n{n}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in ("paper_2409_17033_amd/csrc/dmpt_kernels.hip", "paper_2409_17033_amd/csrc/dmpt_internal.h"):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -167,7 +189,7 @@ def main():
         "peak": PEAK[dtype],
         "unit": "TFLOP/s",
         "frac": r["mfma_tflops"] / PEAK[dtype] if r["mfma_tflops"] else None,
-        "traffic": None,
+        "traffic": measured_traffic(main_prec, args.n),
     }
     cpu = None
     if not args.no_cpu:

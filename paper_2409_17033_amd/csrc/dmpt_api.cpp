@@ -177,30 +177,43 @@ MatRef as_fp32(MatRef m) {
 // Job list over the step tiles (I, J), J >= 2I.  Z-jobs (the heavier
 // products) come first, then P-jobs.  Within a kind the tiles are cut into
 // groups of kGroupI x kGroupJ neighbouring tiles (a group shares kGroupI
-// 256-row A panels and kGroupJ 128-row B panels), and whole groups are dealt
-// to the eight XCDs: workgroups are dispatched round-robin over the XCDs in
-// grid order (block b runs on XCD b % 8), so position p of the list is given
-// the next tile of the group queue of XCD p % 8.  The ~32 workgroups resident
-// on one XCD then stream the same panels through its L2.
+// 256-row A panels and kGroupJ 128-row B panels; groups on the diagonal are
+// the upper-triangle part of their square, 20 tiles), and whole groups are
+// dealt to the eight XCDs: workgroups are dispatched round-robin over the
+// XCDs in grid order (block b runs on XCD b % 8), so position p of the list
+// is given the next tile of the queue of XCD p % 8.  One XCD holds 32
+// resident workgroups, so a full group keeps them streaming the same panels
+// through its L2.  Full groups go first in every queue and are dealt to the
+// queue with the fewest tiles; the partial diagonal groups close the queues.
 constexpr int kXcds = 8, kGroupI = 4, kGroupJ = 8;
 
-std::vector<std::pair<int, int>> grouped_tiles(int n_pad) {
+std::vector<std::vector<std::pair<int, int>>> tile_groups(int n_pad) {
   const int tr = n_pad / kStepTM, tc = n_pad / kStepTN;
-  std::vector<std::pair<int, int>> t;
+  std::vector<std::vector<std::pair<int, int>>> full, part;
   for (int gi = 0; gi < tr; gi += kGroupI)
-    for (int gj = 0; gj < tc; gj += kGroupJ)
+    for (int gj = 0; gj < tc; gj += kGroupJ) {
+      std::vector<std::pair<int, int>> g;
       for (int i = gi; i < std::min(tr, gi + kGroupI); ++i)
-        for (int j = std::max(gj, 2 * i); j < std::min(tc, gj + kGroupJ); ++j) t.emplace_back(i, j);
-  return t;
+        for (int j = std::max(gj, 2 * i); j < std::min(tc, gj + kGroupJ); ++j) g.emplace_back(i, j);
+      if (g.empty()) continue;
+      (g.size() == (size_t)(kGroupI * kGroupJ) ? full : part).push_back(std::move(g));
+    }
+  full.insert(full.end(), part.begin(), part.end());
+  return full;
 }
 
-void append_xcd_ordered(std::vector<uint32_t>& out, const std::vector<uint32_t>& jobs) {
-  const size_t gsz = kGroupI * kGroupJ;
+void append_xcd_ordered(std::vector<uint32_t>& out, const std::vector<std::vector<uint32_t>>& groups) {
   std::vector<std::vector<uint32_t>> q(kXcds);
-  for (size_t g = 0; g * gsz < jobs.size(); ++g)
-    for (size_t k = g * gsz; k < std::min(jobs.size(), (g + 1) * gsz); ++k) q[g % kXcds].push_back(jobs[k]);
+  size_t total = 0;
+  for (const auto& g : groups) {
+    int x = 0;
+    for (int y = 1; y < kXcds; ++y)
+      if (q[y].size() < q[x].size()) x = y;
+    q[x].insert(q[x].end(), g.begin(), g.end());
+    total += g.size();
+  }
   std::vector<size_t> head(kXcds, 0);
-  for (size_t left = jobs.size(); left > 0; --left) {
+  for (size_t left = total; left > 0; --left) {
     int x = (int)(out.size() % kXcds);
     if (head[x] == q[x].size()) {   // this XCD's queue ran dry: take from the longest one
       size_t best = 0;
@@ -212,18 +225,18 @@ void append_xcd_ordered(std::vector<uint32_t>& out, const std::vector<uint32_t>&
 }
 
 std::vector<uint32_t> build_jobs(int n_pad, int nobs_z, bool with_p) {
-  const auto tiles = grouped_tiles(n_pad);
-  std::vector<uint32_t> out, kindjobs;
-  for (int k = 0; k < nobs_z; ++k) {
-    kindjobs.clear();
-    for (auto& t : tiles) kindjobs.push_back(job_pack(kJobZ, k, t.first, t.second));
-    append_xcd_ordered(out, kindjobs);
-  }
-  if (with_p) {
-    kindjobs.clear();
-    for (auto& t : tiles) kindjobs.push_back(job_pack(kJobP, 0, t.first, t.second));
-    append_xcd_ordered(out, kindjobs);
-  }
+  const auto groups = tile_groups(n_pad);
+  std::vector<uint32_t> out;
+  std::vector<std::vector<uint32_t>> kg(groups.size());
+  auto add_kind = [&](int kind, int obs) {
+    for (size_t g = 0; g < groups.size(); ++g) {
+      kg[g].clear();
+      for (const auto& t : groups[g]) kg[g].push_back(job_pack(kind, obs, t.first, t.second));
+    }
+    append_xcd_ordered(out, kg);
+  };
+  for (int k = 0; k < nobs_z; ++k) add_kind(kJobZ, k);
+  if (with_p) add_kind(kJobP, 0);
   return out;
 }
 

@@ -164,23 +164,22 @@ __device__ __forceinline__ void dma_stage_rows(LDS_AS char* slot, const char* a,
 
 // DMA of one stage, tiled operands: the stage is three contiguous chunks (A
 // rows 0-127, A rows 128-255, B rows 0-127) copied 1 KB per instruction.
-// Instructions beyond the stage (when NI is not a multiple of NW) re-read the
-// first kilobyte into a scratch area nobody reads, so every wave issues L.
+// When NI is not a multiple of NW the last round has more instructions than
+// kilobytes; the surplus ones repeat an earlier copy (same source, same
+// destination, same bytes), so every wave issues L and the control flow stays
+// branch-free.
 template <int PREC>
-__device__ __forceinline__ void dma_stage_tiled(LDS_AS char* slot, LDS_AS char* junk, const char* a0,
-                                                const char* a1, const char* b, int wave, int lane) {
+__device__ __forceinline__ void dma_stage_tiled(LDS_AS char* slot, const char* a0, const char* a1, const char* b,
+                                                int wave, int lane) {
   using P = Pipe<PREC>;
   constexpr int NC = P::CHUNK / 1024;   // instructions per chunk
 #pragma unroll
   for (int jj = 0; jj < P::L; ++jj) {
-    const int j = wave + jj * NW;
+    const int jv = wave + jj * NW;
+    const int j = (P::NI % NW != 0 && jv >= P::NI) ? jv - P::NI : jv;
     const int region = j / NC;
     const char* src = (region == 0 ? a0 : region == 1 ? a1 : b) + (j - region * NC) * 1024 + lane * 16;
-    if (P::NI % NW != 0 && j >= P::NI) {
-      __builtin_amdgcn_global_load_lds((const GLB_AS void*)(a0 + lane * 16), (LDS_AS void*)junk, 16, 0, 0);
-    } else {
-      __builtin_amdgcn_global_load_lds((const GLB_AS void*)src, (LDS_AS void*)(slot + j * 1024), 16, 0, 0);
-    }
+    __builtin_amdgcn_global_load_lds((const GLB_AS void*)src, (LDS_AS void*)(slot + j * 1024), 16, 0, 0);
   }
 }
 
@@ -387,7 +386,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   __shared__ __attribute__((aligned(1024))) char ring1[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring2[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring3[P::SLOT];
-  __shared__ __attribute__((aligned(1024))) char junk[P::NI % NW ? 1024 : 16];
   __shared__ int s_code;
   __shared__ double s_red[3 * NW];
 
@@ -449,8 +447,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     if constexpr (P::TILED) {
       // panel bases are the first chunk of their row block; stage st is chunk st
       const char* ca = pa + (size_t)st * chunkb;
-      dma_stage_tiled<PREC>(slot, (LDS_AS char*)junk, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb,
-                            wave, lane);
+      dma_stage_tiled<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
     } else {
       const size_t kb = (size_t)st * P::RB;
       dma_stage_rows<PREC>(slot, pa + kb, pb + kb, ldb32, wave, lane);
@@ -461,29 +458,38 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   LDS_AS char* R2 = (LDS_AS char*)ring2;
   LDS_AS char* R3 = (LDS_AS char*)ring3;
 
-  Ops<PREC> o;
+  Ops<PREC> o0, o1;
   dma(R0, 0);
   dma(R1, 1);
   dma(R2, 2);
+  wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
+  barrier_nofence();
+  dma(R3, 3);
+  __builtin_amdgcn_sched_barrier(0);
+  read_ops<PREC>(R0, o0, rowA, rowB, h);
 
-  // Iteration s: wait until this wave's DMA of stage s landed (stages s+1 and
-  // s+2 may still be in flight), barrier (so has every wave's), refill the
-  // slot of stage s-1 with stage s+3, then read stage s and multiply.
-#define DMPT_ITER(S_, CUR, REFILL)                       \
+  // Iteration s: the operands of stage s are in registers (OC).  Wait until
+  // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
+  // LDS reads of stage s are done, barrier (so has every wave), refill the
+  // slot of stage s with stage s+4, read stage s+1 into the other register
+  // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
+  // of the previous one.
+#define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
   {                                                       \
-    wait_vm<2 * P::L, false>();                           \
+    wait_vm<2 * P::L, true>();                            \
     barrier_nofence();                                    \
-    dma(REFILL, (S_) + 3);                                \
-    read_ops<PREC>(CUR, o, rowA, rowB, h);                \
-    mma_ops<PREC>(o, acc);                                \
+    dma(REFILL, (S_) + 4);                                \
+    __builtin_amdgcn_sched_barrier(0);                    \
+    read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
+    mma_ops<PREC>(OC, acc);                               \
   }
   const int fl4 = a.flush > 0 ? a.flush : 1 << 30;   // flush every fl4 groups of 4 stages
   int since = 0;
   for (int s = 0; s < nst; s += 4) {
-    DMPT_ITER(s + 0, R0, R3)
-    DMPT_ITER(s + 1, R1, R0)
-    DMPT_ITER(s + 2, R2, R1)
-    DMPT_ITER(s + 3, R3, R2)
+    DMPT_ITER(s + 0, R1, R0, o0, o1)
+    DMPT_ITER(s + 1, R2, R1, o1, o0)
+    DMPT_ITER(s + 2, R3, R2, o0, o1)
+    DMPT_ITER(s + 3, R0, R3, o1, o0)
     if (++since == fl4) {
       since = 0;
 #pragma unroll

@@ -153,8 +153,12 @@ def banded_gapped(n: int = 4096, nocc: int | None = None, gap: float = 0.1,
                   np.stack([_as32(x) for x in a]), np.stack([_as32(x) for x in h1]),
                   {"gap": gap, "cfg": cfg, "half_bandwidth": half_bandwidth})
     if path:
-        os.makedirs(cdir, exist_ok=True)
-        np.savez(path, H=wl.H, A=wl.A, H1=wl.H1)
+        try:                       # the cache is an optimisation only
+            os.makedirs(cdir, exist_ok=True)
+            np.savez(path + ".tmp.npz", H=wl.H, A=wl.A, H1=wl.H1)
+            os.replace(path + ".tmp.npz", path)
+        except OSError:
+            pass
     return wl
 
 
