@@ -86,11 +86,11 @@ typedef struct dmpt_opts {
   int32_t precision;      /* dmpt_precision */
   int32_t bounds;         /* dmpt_bounds_mode */
   double emin, emax;      /* spectral bounds, read iff bounds == DMPT_BOUNDS_GIVEN */
-  int32_t lanczos_steps;  /* Lanczos iterations for DMPT_BOUNDS_LANCZOS; 0 -> 64 */
+  int32_t lanczos_steps;  /* Lanczos iterations for DMPT_BOUNDS_LANCZOS; 0 -> 48 */
   int32_t max_iter;       /* SP2 step limit, <= DMPT_MAX_STEPS; 0 -> 100 */
   int32_t min_iter;       /* steps before the stopping test may fire; < 0 -> 10 */
   int32_t sweep;          /* dmpt_sweep (susceptibility only) */
-  double idem_tol;        /* also stop when |Tr X - ||X||_F^2| <= idem_tol; 0 -> parameter-free test only */
+  double idem_tol;        /* also stop when ||X_n - X_n^2||_F^2 <= idem_tol; 0 -> parameter-free test only */
   int32_t project;        /* susceptibility only: 1 -> finish with the occupied-virtual projection
                              (two FP32 sweep steps with X frozen at D: sigma = +1 then -1) */
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */

@@ -2,33 +2,34 @@
 // (arXiv 2409.17033, Eq. DM0, DM2, DM3, DMSuscept, doubleHalf, MixPrecMult).
 //
 // Data layout (device workspace)
-//   X_n, Y_n   n_pad x n_pad, row-major, full symmetric storage.  Each matrix
-//              has an FP32 master copy and, for the low-precision products,
-//              an operand copy:
-//                kSplit2: per row, groups of 8 consecutive columns stored as
-//                         [8 x bf16 hi][8 x bf16 lo]  (hi = RNE_bf16(x),
-//                         lo = RNE_bf16(x - hi), Eq. doubleHalf with BF16)
-//                kBF16:   plain bf16 row-major.
+//   X_n, Y_n   n_pad x n_pad FP32 masters, row-major, full symmetric storage,
+//              plus (all formats but FP32) an operand copy in a tiled layout:
+//              chunks of 128 rows x one K-stage, each chunk contiguous, each
+//              row's 16-byte slots holding one split term of 8 consecutive
+//              columns and XOR-swizzled the way the LDS ring expects them
+//              (Eq. doubleHalf with BF16 terms: hi = RNE(x), lo = RNE(x - hi),
+//              and a middle term for the three-term split).
 //   Padding rows/columns (n <= i < n_pad) are zero in X- and Y-space: 0 is a
 //   fixed point of x^2 and 2x - x^2 and contributes nothing to any trace.
 //
 // Step kernel (one launch per SP2 step n)
-//   grid = list of jobs; a job is one TILE x TILE output tile (I <= J) of
+//   grid = list of jobs; a job is one 256 x 128 output tile (I, J >= 2I) of
 //     P = X_n X_n                    (kind P; symmetric, so X_n rows serve as
 //                                      both operands: P_IJ = X_I X_J^T)
-//     Z = Y_n X_n + X_n Y_n          (kind Z; = Y_I X_J^T + X_I Y_J^T)
-//   Operands are staged HBM -> LDS with global_load_lds_dwordx4 (no VGPR
-//   staging), double-buffered, 64 bytes per row per stage, the four 16-byte
-//   slots of a row XOR-swizzled by (row/4)&3 so MFMA operand reads are free of
-//   bank conflicts.  Products run on v_mfma_f32_32x32x16_bf16 (split / plain
-//   BF16) or v_mfma_f32_32x32x2_f32 (FP32) with FP32 accumulation.
+//     Z = Y_n X_n + X_n Y_n          (kind Z; = Y_I X_J^T + X_I Y_J^T, the two
+//                                      products K-concatenated)
+//   Operands stream HBM -> LDS with global_load_lds_dwordx4 (no VGPR staging)
+//   through a ring of four stages, three in flight; the next stage's
+//   operands are read into a second register set while the current stage's
+//   MFMAs run.  Products run on v_mfma_f32_32x32x16_bf16 (split / plain
+//   BF16) or v_mfma_f32_32x32x2f32 (FP32) with two-level FP32 accumulation.
 //   Epilogue: X_{n+1} = P (sigma=+1) or 2 X_n - P (sigma=-1), likewise Y;
 //   the tile and its mirror are stored (exact symmetry), the operand copy is
-//   re-split, and P-jobs emit FP64 partials of Tr X_{n+1} and ||X_{n+1}||_F^2.
-//   sigma_n and the stop test are evaluated at kernel start by every
-//   workgroup from the FP64 partials of the previous step (fixed reduction
-//   order, so every workgroup reaches the same decision); workgroup 0 records
-//   it in the control block.  No host round trip per step.
+//   re-split, and P-jobs emit FP64 partials of Tr X_{n+1}, ||X_{n+1}||_F^2
+//   and ||X_n - X_n^2||_F^2.  sigma_n and the stopping test are evaluated at
+//   kernel start by every workgroup from the previous launch's partials
+//   (fixed reduction order, so every workgroup reaches the same decision);
+//   workgroup 0 records it in the control block.  No host round trip per step.
 #include <hip/hip_runtime.h>
 
 #include "dmpt_internal.h"

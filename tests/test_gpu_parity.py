@@ -184,6 +184,24 @@ def test_tiny_matrices(gpu):
     assert abs(_np(D1)[0, 0] - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("n", [3, 17, 129, 257])
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_sizes(gpu, n, prec):
+    """Sizes that leave a ragged tail in the 256-padded tiles (and tiny ones)."""
+    dm = _dm()
+    nocc = max(1, n // 3)
+    h, _, _ = W.known_spectrum(n, nocc, gap=0.3, seed=n)
+    a = W.random_perturbations(n, 1, seed=n)[0] * n
+    h32, a32 = h.astype(np.float32), a.astype(np.float32)
+    chi, D, a0, info = dm.susceptibility(_dev(h32, gpu), _dev(a32, gpu), nocc, precision=prec)
+    h64, a64 = h32.astype(np.float64), a32.astype(np.float64)
+    dref = cf.density_matrix(h64, nocc)
+    chiref = cf.susceptibility(h64, a64, nocc, spin=2.0)
+    assert cf.rel_frobenius(_np(D), dref) <= TOL[prec]
+    assert cf.rel_frobenius(_np(chi), chiref) <= TOL[prec]
+    assert abs(a0[0] - 2.0 * cf.expectation(a64, dref)) <= 2 * TOL[prec] * np.linalg.norm(a64) * np.linalg.norm(dref)
+
+
 def test_error_statuses(gpu):
     dm = _dm()
     wl = _case("c1")
