@@ -65,6 +65,10 @@ int stage_k(int prec) { return prec == kBF16 ? 32 : 16; }
 constexpr int TM = 256, TN = 128, NW = 8, NT = 512, RING = 4;
 constexpr int BR = 2, BC = 2;
 constexpr int RBLK = 128;   // rows per chunk of the tiled operand layout
+// Epilogue staging of one wave's 64 x 64 output region: row stride 65 floats,
+// so both a row walk and a column walk over 64 lanes hit 64 distinct banks.
+constexpr int kLS = 65;
+constexpr int kStageBytes = 64 * kLS * 4;
 
 // Tiled operand layout (all formats except FP32, which stays row-major): the
 // copy of an n_pad x n_pad matrix is cut into chunks of 128 rows x one stage
@@ -346,25 +350,6 @@ __device__ int step_controller(const StepArgs& a, int* s_code) {
   return *s_code;
 }
 
-// Operand copy (split terms) of 4 values at rows row0..row0+3, column col,
-// and of their mirror (row col, columns row0..row0+3; row0 % 4 == 0, so the
-// four mirror values of one term are 8 contiguous bytes).
-template <int PREC>
-__device__ __forceinline__ void store_split4(char* oop, int nst, int row0, int col, const float (&v)[4]) {
-  constexpr int T = Terms<PREC>::T;
-  unsigned short part[4][T];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) split_terms<T>(v[e], part[e]);
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-#pragma unroll
-    for (int t = 0; t < T; ++t) *(unsigned short*)(oop + op_off<PREC>(row0 + e, col, t, nst)) = part[e][t];
-#pragma unroll
-  for (int t = 0; t < T; ++t)
-    *(u32x2*)(oop + op_off<PREC>(col, row0, t, nst)) = u32x2{part[0][t] | ((unsigned)part[1][t] << 16),
-                                                             part[2][t] | ((unsigned)part[3][t] << 16)};
-}
-
 template <int PREC>
 __device__ __forceinline__ void store_split1(char* oop, int nst, int r, int c, float v) {
   constexpr int T = Terms<PREC>::T;
@@ -372,6 +357,23 @@ __device__ __forceinline__ void store_split1(char* oop, int nst, int r, int c, f
   split_terms<T>(v, part);
 #pragma unroll
   for (int t = 0; t < T; ++t) *(unsigned short*)(oop + op_off<PREC>(r, c, t, nst)) = part[t];
+}
+
+// Operand copy of 8 consecutive columns c0..c0+7 (c0 % 8 == 0) of row r, in
+// the tiled layout: each split term of the group is one 16-byte slot.
+template <int PREC>
+__device__ __forceinline__ void store_group8_t(char* op, int nst, int r, int c0, const float (&v)[8]) {
+  constexpr int T = Terms<PREC>::T;
+  unsigned short part[8][T];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) split_terms<T>(v[e], part[e]);
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    u32x4 w;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w[e] = part[2 * e][t] | ((unsigned)part[2 * e + 1][t] << 16);
+    *(u32x4*)(op + op_off<PREC>(r, c0, t, nst)) = w;
+  }
 }
 
 // Index of step tile (I, J) among the tiles that cover the upper triangle:
@@ -383,10 +385,13 @@ __device__ __forceinline__ int tile_index(int ti, int tj, int tcols) {
 template <int PREC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(StepArgs a) {
   using P = Pipe<PREC>;
-  __shared__ __attribute__((aligned(1024))) char ring0[P::SLOT];
-  __shared__ __attribute__((aligned(1024))) char ring1[P::SLOT];
-  __shared__ __attribute__((aligned(1024))) char ring2[P::SLOT];
-  __shared__ __attribute__((aligned(1024))) char ring3[P::SLOT];
+  // Ring slots; after the main loop each holds the 64 x 65 FP32 staging
+  // areas of two waves for the epilogue.
+  constexpr int RSZ = P::SLOT > 2 * kStageBytes ? P::SLOT : 2 * kStageBytes;
+  __shared__ __attribute__((aligned(1024))) char ring0[RSZ];
+  __shared__ __attribute__((aligned(1024))) char ring1[RSZ];
+  __shared__ __attribute__((aligned(1024))) char ring2[RSZ];
+  __shared__ __attribute__((aligned(1024))) char ring3[RSZ];
   __shared__ int s_code;
   __shared__ double s_red[3 * NW];
 
@@ -521,67 +526,119 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
   double tr = 0.0, sq = 0.0, ep = 0.0;
 
-  // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+  const bool need_cur = kind == kJobP || sigma < 0;
+  if (!onDiag) {
+    // Off-diagonal tile: every element is stored twice (direct and mirror).
+    // Each wave stages its 64 x 64 region in LDS (private area, no cross-wave
+    // traffic) and writes rows of 16-byte vectors: direct rows, mirror rows,
+    // and 16-byte split-term slots of 8 consecutive columns in both
+    // orientations.  The barrier makes sure every wave is past its last ring
+    // read and every ring DMA has landed.
+    barrier_nofence();
+    LDS_AS char* rb = (wave >> 1) == 0 ? R0 : (wave >> 1) == 1 ? R1 : (wave >> 1) == 2 ? R2 : R3;
+    LDS_AS float* T = (LDS_AS float*)(rb + (wave & 1) * kStageBytes);
+    // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
 #pragma unroll
-  for (int bi = 0; bi < BR; ++bi)
+    for (int bi = 0; bi < BR; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < BC; ++bj) {
-      const int col = tj * TN + wc * 64 + bj * 32 + l32;
+      for (int bj = 0; bj < BC; ++bj)
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
-        float v[4], dx[4];
+        for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float p = tot[bi][bj][4 * g + e];
-          if (kind == kJobP || sigma < 0) {
-            const float c0 = cur[(size_t)(row0 + e) * np + col];
-            v[e] = sigma > 0 ? p : 2.0f * c0 - p;
-            dx[e] = c0 - p;                      // X_n - X_n^2 (P-jobs)
-          } else {
-            v[e] = p;
-            dx[e] = 0.0f;
+          for (int e = 0; e < 4; ++e) T[(bi * 32 + 8 * g + 4 * h + e) * kLS + bj * 32 + l32] = tot[bi][bj][4 * g + e];
+    wait_vm<63, true>();
+    const int gr0 = ti * TM + wr * 64, gc0 = tj * TN + wc * 64;   // global origin of the region
+    // direct rows: 4 rows x 64 columns per round, 4 columns per lane
+#pragma unroll 4
+    for (int rd = 0; rd < 16; ++rd) {
+      const int r = 4 * rd + (lane >> 4), c = 4 * (lane & 15);
+      f32x4 v = f32x4{T[r * kLS + c], T[r * kLS + c + 1], T[r * kLS + c + 2], T[r * kLS + c + 3]};
+      if (need_cur) {
+        const f32x4 x = *(const f32x4*)(cur + (size_t)(gr0 + r) * np + gc0 + c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float p = v[k];
+          v[k] = sigma > 0 ? p : 2.0f * x[k] - p;
+          if (kind == kJobP) {
+            const double d = x[k] - p;                // X_n - X_n^2
+            sq += 2.0 * (double)v[k] * (double)v[k];
+            ep += 2.0 * d * d;
           }
         }
-        if (!onDiag) {
+        if (sigma < 0) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) o32[(size_t)(row0 + e) * np + col] = v[e];
-          *(f32x4*)(o32 + (size_t)col * np + row0) = f32x4{v[0], v[1], v[2], v[3]};
-          if (wsplit) store_split4<PREC>(oop, nstp, row0, col, v);
-          if (kind == kJobP) {
+          for (int k = 0; k < 4; ++k) T[r * kLS + c + k] = v[k];
+        }
+      }
+      *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
+    }
+    wait_vm<63, true>();
+    // mirror rows: 4 mirror rows x 64 columns per round
+#pragma unroll 4
+    for (int rd = 0; rd < 16; ++rd) {
+      const int c = 4 * rd + (lane >> 4), q = 4 * (lane & 15);
+      *(f32x4*)(o32 + (size_t)(gc0 + c) * np + gr0 + q) =
+          f32x4{T[q * kLS + c], T[(q + 1) * kLS + c], T[(q + 2) * kLS + c], T[(q + 3) * kLS + c]};
+    }
+    if constexpr (PREC != kFP32) {
+      if (wsplit) {
+        // split-term slots: 8 rows x 8 groups of 8 columns per round, both orientations
+#pragma unroll 2
+        for (int rd = 0; rd < 8; ++rd) {
+          const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
+          float v[8];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              sq += 2.0 * (double)v[e] * (double)v[e];
-              ep += 2.0 * (double)dx[e] * (double)dx[e];
-            }
-          }
-        } else {
-          // keep the upper triangle (row <= col) and mirror it: exact symmetry
+          for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
+          store_group8_t<PREC>(oop, nstp, gr0 + r, gc0 + c, v);
+        }
+#pragma unroll 2
+        for (int rd = 0; rd < 8; ++rd) {
+          const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
+          float v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
+          store_group8_t<PREC>(oop, nstp, gc0 + c, gr0 + q, v);
+        }
+      }
+    }
+  } else {
+    // Diagonal tile: keep the upper triangle (row <= col) and mirror it.
+    // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+#pragma unroll
+    for (int bi = 0; bi < BR; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BC; ++bj) {
+        const int col = tj * TN + wc * 64 + bj * 32 + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int r = row0 + e;
             if (r > col) continue;
-            o32[(size_t)r * np + col] = v[e];
-            o32[(size_t)col * np + r] = v[e];
+            const float p = tot[bi][bj][4 * g + e];
+            float v = p, dd = 0.0f;
+            if (need_cur) {
+              const float c0 = cur[(size_t)r * np + col];
+              v = sigma > 0 ? p : 2.0f * c0 - p;
+              dd = c0 - p;                               // X_n - X_n^2 (P-jobs)
+            }
+            o32[(size_t)r * np + col] = v;
+            o32[(size_t)col * np + r] = v;
             if (wsplit) {
-              store_split1<PREC>(oop, nstp, r, col, v[e]);
-              if (r != col) store_split1<PREC>(oop, nstp, col, r, v[e]);
+              store_split1<PREC>(oop, nstp, r, col, v);
+              if (r != col) store_split1<PREC>(oop, nstp, col, r, v);
             }
             if (kind == kJobP) {
-              const double d = v[e], dd = dx[e];
-              if (r == col) {
-                tr += d;
-                sq += d * d;
-                ep += dd * dd;
-              } else {
-                sq += 2.0 * d * d;
-                ep += 2.0 * dd * dd;
-              }
+              const double w = r == col ? 1.0 : 2.0;
+              if (r == col) tr += v;
+              sq += w * (double)v * (double)v;
+              ep += w * (double)dd * (double)dd;
             }
           }
         }
       }
-    }
+  }
 
   if (kind == kJobP) {
     tr = wave_sum(tr);
@@ -822,23 +879,6 @@ hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, 
 }
 
 // ---------------------------------------------------------------- operand copies
-
-// Operand copy of 8 consecutive columns c0..c0+7 (c0 % 8 == 0) of row r, in
-// the tiled layout: each split term of the group is one 16-byte slot.
-template <int PREC>
-__device__ __forceinline__ void store_group8_t(char* op, int nst, int r, int c0, const float (&v)[8]) {
-  constexpr int T = Terms<PREC>::T;
-  unsigned short part[8][T];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) split_terms<T>(v[e], part[e]);
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    u32x4 w;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) w[e] = part[2 * e][t] | ((unsigned)part[2 * e + 1][t] << 16);
-    *(u32x4*)(op + op_off<PREC>(r, c0, t, nst)) = w;
-  }
-}
 
 __device__ __forceinline__ void store_group8(int prec, char* op, int n_pad, int r, int c0, const float (&v)[8]) {
   if (prec == kSplit2) store_group8_t<kSplit2>(op, n_pad / Fmt<kSplit2>::K, r, c0, v);
