@@ -92,7 +92,8 @@ typedef struct dmpt_opts {
   int32_t sweep;          /* dmpt_sweep (susceptibility only) */
   double idem_tol;        /* also stop when ||X_n - X_n^2||_F^2 <= idem_tol; 0 -> parameter-free test only */
   int32_t project;        /* susceptibility only: 1 -> finish with the occupied-virtual projection
-                             (two FP32 sweep steps with X frozen at D: sigma = +1 then -1) */
+                             (two sweep steps with X frozen at D: sigma = +1 then -1, in the
+                             precision of the recursion; FP32 when it is plain BF16) */
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
   double spin;            /* s; 0 -> 2 */
   void* stream;           /* hipStream_t */

@@ -559,9 +559,12 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   }
 
   if (nobs > 0 && o.project && st == DMPT_OK) {
-    // Occupied-virtual projection: two FP32 sweep steps with X frozen at D
+    // Occupied-virtual projection: two sweep steps with X frozen at D
     // (sigma = +1 then -1) multiply the eigenbasis blocks of Y by
     // (f_i + f_j)(2 - f_i - f_j): 1 on occupied-virtual pairs, 0 elsewhere.
+    // They run in the precision of the recursion (FP32 for plain BF16), on
+    // the operand copies of D and Y the last step wrote.
+    const int pprec = p.prec == kBF16 ? kFP32 : p.prec;
     const std::vector<uint32_t> pjobs = build_jobs(p.n_pad, nobs, false);
     uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
     DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));
@@ -571,16 +574,17 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.n_pad = p.n_pad;
     b.ntile = p.ntile;
     b.decide = 0;
-    b.write_split = 0;
-    b.flush = flush_interval(kFP32, p.n_pad);
+    b.flush = flush_interval(pprec, p.n_pad);
     b.jobs = d_pjobs;
     b.ctl = ctl;
-    b.x_in = as_fp32(x_ref(p, ws, xfin));
+    auto view = [&](MatRef m) { return pprec == kFP32 ? as_fp32(m) : m; };
+    b.x_in = view(x_ref(p, ws, xfin));
     for (int q = 0; q < 2; ++q) {
       b.fixed_sigma = q == 0 ? 1 : -1;
-      b.y_in = as_fp32(y_ref(p, ws, yfin));
-      b.y_out = as_fp32(y_ref(p, ws, yfin ^ 1));
-      DMPT_HIP(launch_step(kFP32, b, (int)pjobs.size(), s));
+      b.write_split = q == 0 && pprec != kFP32;   // the second step reads it
+      b.y_in = view(y_ref(p, ws, yfin));
+      b.y_out = view(y_ref(p, ws, yfin ^ 1));
+      DMPT_HIP(launch_step(pprec, b, (int)pjobs.size(), s));
       yfin ^= 1;
     }
   }
