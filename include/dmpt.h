@@ -66,7 +66,12 @@ typedef enum dmpt_precision {
                            (lo*lo dropped, Eq. MixPrecMult), FP32 accumulate */
   DMPT_SPLIT3_BF16 = 2, /* three BF16 terms hi+mid+lo (FP32-equivalent operands); the six
                            products of order >= 2^-16 (hh, hm, mh, hl, lh, mm) are kept */
-  DMPT_BF16 = 3         /* one BF16 term (plain BF16 operands), FP32 accumulate */
+  DMPT_BF16 = 3,        /* one BF16 term (plain BF16 operands), FP32 accumulate */
+  DMPT_SPLIT3X_BF16 = 4 /* three BF16 terms stored; the SP2 products X_n^2 keep the six split-3
+                           products, the sweep products Y_n X_n + X_n Y_n the two-term ones
+                           (hh + hm + mh; mid is the two-term lo).  The SP2 products set the
+                           accuracy of D and, through it, of chi; the sweep products tolerate
+                           the two-term split. */
 } dmpt_precision;
 
 typedef enum dmpt_bounds_mode {

@@ -23,7 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
-PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3}
+PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
 

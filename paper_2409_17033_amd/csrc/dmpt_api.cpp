@@ -54,7 +54,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (!o) return fail(DMPT_ERR_ARG, "opts is NULL");
   if (o->n < 1 || o->n > 65536) return fail(DMPT_ERR_ARG, "n = %d out of range [1, 65536]", o->n);
   if (o->nocc < 0 || o->nocc > o->n) return fail(DMPT_ERR_ARG, "nocc = %d out of range [0, n]", o->nocc);
-  if (o->precision < 0 || o->precision > DMPT_BF16) return fail(DMPT_ERR_ARG, "unknown precision %d", o->precision);
+  if (o->precision < 0 || o->precision > DMPT_SPLIT3X_BF16) return fail(DMPT_ERR_ARG, "unknown precision %d", o->precision);
   if (o->bounds < 0 || o->bounds > DMPT_BOUNDS_GIVEN) return fail(DMPT_ERR_ARG, "unknown bounds mode %d", o->bounds);
   if (o->bounds == DMPT_BOUNDS_GIVEN && !(std::isfinite(o->emin) && std::isfinite(o->emax) && o->emax > o->emin))
     return fail(DMPT_ERR_ARG, "given bounds need finite emin < emax");
@@ -69,7 +69,8 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   r->nocc = o->nocc;
   r->prec = o->precision == DMPT_FP32 ? kFP32
           : o->precision == DMPT_SPLIT_BF16 ? kSplit2
-          : o->precision == DMPT_SPLIT3_BF16 ? kSplit3 : kBF16;
+          : o->precision == DMPT_SPLIT3_BF16 ? kSplit3
+          : o->precision == DMPT_SPLIT3X_BF16 ? kSplit32 : kBF16;
   r->bounds = o->bounds;
   r->lanczos_steps = o->lanczos_steps ? o->lanczos_steps : 48;
   r->max_iter = o->max_iter ? o->max_iter : 100;
@@ -103,7 +104,7 @@ struct Plan {
 // (F stages x MFMAs per stage per block) against the outer one (stages / F)
 // gives F ~ sqrt(stages / chain).
 int flush_interval(int prec, int n_pad) {
-  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : prec == kSplit2 ? 3 : 2;
+  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : (prec == kSplit2 || prec == kSplit32) ? 3 : 2;
   const int stages = n_pad / stage_k(prec);
   const double f = std::sqrt((double)stages / chain) / 4.0;
   return std::max(1, (int)std::lround(f));
@@ -459,8 +460,25 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     return DMPT_OK;
   }
 
-  // job tables
-  const std::vector<uint32_t> jobs = build_jobs(p.n_pad, adjoint ? 0 : nobs, true);
+  // Precision of the SP2 products (P-jobs) and of the sweep products
+  // (Z-jobs).  When they differ the step is two launches over the same
+  // control state: Z-jobs first, then P-jobs (which write the partials the
+  // next step's controller reads).
+  const int xprec = p.prec == kSplit32 ? kSplit3 : p.prec;
+  const int yprec = p.prec;
+  const bool split_launch = xprec != yprec && nobs > 0 && !adjoint;
+
+  // job tables: [Z-jobs][P-jobs] (one combined table when the step is one launch)
+  std::vector<uint32_t> jobs;
+  int njobs_z = 0;
+  if (split_launch) {
+    jobs = build_jobs(p.n_pad, nobs, false);
+    njobs_z = (int)jobs.size();
+    const std::vector<uint32_t> pj = build_jobs(p.n_pad, 0, true);
+    jobs.insert(jobs.end(), pj.begin(), pj.end());
+  } else {
+    jobs = build_jobs(p.n_pad, adjoint ? 0 : nobs, true);
+  }
   uint32_t* d_jobs = (uint32_t*)(ws + p.off_jobs);
   DMPT_HIP(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * 4, hipMemcpyHostToDevice, s));
   const int njobs_main = (int)jobs.size();
@@ -497,8 +515,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.idem_tol = o.idem_tol;
   a.decide = 1;
   a.write_split = 1;
-  a.flush = flush_interval(p.prec, p.n_pad);
-  a.jobs = adjoint ? d_jobs : d_jobs;
+  a.flush = flush_interval(xprec, p.n_pad);
+  a.jobs = d_jobs;
   a.ctl = ctl;
   const int njobs_step = adjoint ? p.nparts_step : njobs_main;
   const uint32_t* step_jobs = adjoint ? d_jobs + 0 : d_jobs;
@@ -516,9 +534,18 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       a.part_in = part[n & 1];
       a.part_out = part[(n + 1) & 1];
       a.nparts = n == 1 ? p.nb64 * p.nb64 : p.nparts_step;
-      a.jobs = step_jobs;
       const int ma = prof.mark();
-      DMPT_HIP(launch_step(p.prec, a, njobs_step, s));
+      if (split_launch) {
+        a.jobs = d_jobs;
+        a.flush = flush_interval(yprec, p.n_pad);
+        DMPT_HIP(launch_step(yprec, a, njobs_z, s));
+        a.jobs = d_jobs + njobs_z;
+        a.flush = flush_interval(xprec, p.n_pad);
+        DMPT_HIP(launch_step(xprec, a, njobs_main - njobs_z, s));
+      } else {
+        a.jobs = step_jobs;
+        DMPT_HIP(launch_step(xprec, a, njobs_step, s));
+      }
       step_marks.emplace_back(ma, prof.mark());
       ++launched;
     }
@@ -544,6 +571,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     DMPT_HIP(hipMemcpyAsync(d_zjobs, zjobs.data(), zjobs.size() * 4, hipMemcpyHostToDevice, s));
     StepArgs b = a;
     b.decide = 0;
+    b.flush = flush_interval(yprec, p.n_pad);
     b.sigma_src = ctl->rec;
     b.jobs = d_zjobs;
     int ys = 0;
@@ -552,7 +580,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.x_in = x_ref(p, ws, xslot(n));
       b.y_in = y_ref(p, ws, ys);
       b.y_out = y_ref(p, ws, ys ^ 1);
-      DMPT_HIP(launch_step(p.prec, b, (int)zjobs.size(), s));
+      DMPT_HIP(launch_step(yprec, b, (int)zjobs.size(), s));
       ys ^= 1;
     }
     yfin = ys;
@@ -564,7 +592,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // (f_i + f_j)(2 - f_i - f_j): 1 on occupied-virtual pairs, 0 elsewhere.
     // They run in the precision of the recursion (FP32 for plain BF16), on
     // the operand copies of D and Y the last step wrote.
-    const int pprec = p.prec == kBF16 ? kFP32 : p.prec;
+    const int pprec = p.prec == kBF16 ? kFP32 : xprec;
     const std::vector<uint32_t> pjobs = build_jobs(p.n_pad, nobs, false);
     uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
     DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));

@@ -16,11 +16,13 @@ enum Prec : int {
   kSplit2 = 1,  // packed (hi, lo) BF16 pairs, BF16 MFMA, FP32 accumulate
   kSplit3 = 2,  // packed (hi, mid, lo) BF16 triples, BF16 MFMA, FP32 accumulate
   kBF16 = 3,    // plain BF16 row-major
+  kSplit32 = 4, // (hi, mid, lo) triples stored as for kSplit3; products use (hi, mid) only,
+                // i.e. the two-term split hh + hm + mh (mid = RNE(x - hi) is the two-term lo)
 };
 
 // Bytes per matrix element in the operand copy of each format.
 __host__ __device__ constexpr int operand_bytes(int prec) {
-  return prec == kFP32 ? 4 : prec == kSplit2 ? 4 : prec == kSplit3 ? 6 : prec == kBF16 ? 2 : 0;
+  return prec == kFP32 ? 4 : prec == kSplit2 ? 4 : (prec == kSplit3 || prec == kSplit32) ? 6 : prec == kBF16 ? 2 : 0;
 }
 
 constexpr int kPadTo = 256;     // n is padded (with zeros in X-space) to a multiple of this

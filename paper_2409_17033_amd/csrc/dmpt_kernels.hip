@@ -48,12 +48,15 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Bytes per LDS row per pipeline stage: 16 k values of FP32 / packed split-2
 // (64 B = 4 slots of 16 B), 32 k values of plain BF16 (64 B), 16 k values of
-// packed split-3 (96 B = 6 slots).
+// packed split-3 (96 B = 6 slots); kSplit32 stages split-2-shaped rows.
 template <int PREC> struct Fmt {
   static constexpr int RB = PREC == kSplit3 ? 96 : 64;
   static constexpr int S = RB / 16;
   static constexpr int K = PREC == kBF16 ? 32 : 16;
 };
+// Format of the operand copy in HBM: kSplit32 keeps the three-term copy and
+// stages only its (hi, mid) slots.
+template <int PREC> struct Store { static constexpr int F = PREC == kSplit32 ? kSplit3 : PREC; };
 
 int stage_k(int prec) { return prec == kBF16 ? 32 : 16; }
 
@@ -81,7 +84,7 @@ template <int PREC> struct Pipe {
   static constexpr int S = Fmt<PREC>::S;               // 16-byte slots per row
   static constexpr int A_BYTES = TM * RB, B_BYTES = TN * RB;
   static constexpr int SLOT = A_BYTES + B_BYTES;       // bytes per ring slot
-  static constexpr int CHUNK = RBLK * RB;              // bytes per 128-row stage chunk
+  static constexpr int CHUNK = RBLK * Fmt<Store<PREC>::F>::RB;   // bytes per 128-row stage chunk in HBM
   static constexpr int NI = SLOT / 1024;               // 1 KB DMA instructions per stage
   static constexpr int L = (NI + NW - 1) / NW;         // per wave (padded with dummies)
   static constexpr bool TILED = PREC != kFP32;
@@ -105,7 +108,9 @@ __device__ __forceinline__ void split_terms(float x, unsigned short (&p)[T]) {
     r = r - bf16_val(p[t]);
   }
 }
-template <int PREC> struct Terms { static constexpr int T = PREC == kSplit3 ? 3 : PREC == kSplit2 ? 2 : 1; };
+template <int PREC> struct Terms {
+  static constexpr int T = PREC == kSplit3 ? 3 : (PREC == kSplit2 || PREC == kSplit32) ? 2 : 1;
+};
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -188,6 +193,29 @@ __device__ __forceinline__ void dma_stage_tiled(LDS_AS char* slot, const char* a
   }
 }
 
+// DMA of one stage for kSplit32: LDS gets split-2-shaped rows (4 slots of
+// 16 B: hi and mid of the two 8-column k-groups, swizzled for 4 slots) gathered
+// from the three-term copy in HBM (6 slots per row, swizzled for 6).  Lane i of
+// instruction j fills LDS bytes j*1024 + 16 i: panel row 16 (j mod 8) + i/4 of
+// region j/8 (A rows 0-127, A rows 128-255, B rows 0-127), physical slot i mod 4.
+template <int PREC>
+__device__ __forceinline__ void dma_stage_t32(LDS_AS char* slot, const char* a0, const char* a1, const char* b,
+                                              int wave, int lane) {
+  using P = Pipe<PREC>;
+  static_assert(P::NI % NW == 0, "kSplit32 stage is a whole number of rounds");
+#pragma unroll
+  for (int jj = 0; jj < P::L; ++jj) {
+    const int j = wave + jj * NW;
+    const int region = j >> 3;
+    const int rr = ((j & 7) << 4) + (lane >> 2);                 // row within the 128-row chunk
+    const int ls4 = (lane & 3) ^ ((rr >> 2) & 3);                // logical split-2 slot at this position
+    const int ls6 = 3 * (ls4 >> 1) + (ls4 & 1);                  // same k-group and term in the 6-slot row
+    const int ph6 = ls6 ^ ((rr >> 3) & 1);
+    const char* src = (region == 0 ? a0 : region == 1 ? a1 : b) + rr * 96 + 16 * ph6;
+    __builtin_amdgcn_global_load_lds((const GLB_AS void*)src, (LDS_AS void*)(slot + j * 1024), 16, 0, 0);
+  }
+}
+
 // Byte offset of element (r, c), split term `part`, in the tiled operand copy.
 template <int PREC>
 __device__ __forceinline__ size_t op_off(int r, int c, int part, int nst) {
@@ -203,6 +231,7 @@ __device__ __forceinline__ size_t op_off(int r, int c, int part, int nst) {
 template <int PREC> struct Ops;
 template <> struct Ops<kSplit3> { bf16x8 a[BR][3], b[BC][3]; };
 template <> struct Ops<kSplit2> { bf16x8 a[BR][2], b[BC][2]; };
+template <> struct Ops<kSplit32> { bf16x8 a[BR][2], b[BC][2]; };
 template <> struct Ops<kBF16> { bf16x8 a[BR][2], b[BC][2]; };     // [t]: k16 step
 template <> struct Ops<kFP32> { f32x4 a[BR][2], b[BC][2]; };       // [q]: slot h + 2q
 
@@ -216,7 +245,7 @@ __device__ __forceinline__ void read_ops(const LDS_AS char* slot, Ops<PREC>& o, 
   constexpr int S = Pipe<PREC>::S;
   const LDS_AS char* pA = slot;
   const LDS_AS char* pB = slot + Pipe<PREC>::A_BYTES;
-  if constexpr (PREC == kSplit3 || PREC == kSplit2) {
+  if constexpr (PREC == kSplit3 || PREC == kSplit2 || PREC == kSplit32) {
     constexpr int T = Terms<PREC>::T;
 #pragma unroll
     for (int i = 0; i < BR; ++i)
@@ -264,7 +293,7 @@ __device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
-      } else if constexpr (PREC == kSplit2) {
+      } else if constexpr (PREC == kSplit2 || PREC == kSplit32) {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
@@ -450,7 +479,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const int st = second ? sc - spass : sc;
     const char* pa = second ? a1 : a0;
     const char* pb = second ? b1 : b0;
-    if constexpr (P::TILED) {
+    if constexpr (PREC == kSplit32) {
+      const char* ca = pa + (size_t)st * chunkb;
+      dma_stage_t32<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
+    } else if constexpr (P::TILED) {
       // panel bases are the first chunk of their row block; stage st is chunk st
       const char* ca = pa + (size_t)st * chunkb;
       dma_stage_tiled<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
@@ -589,7 +621,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           float v[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
-          store_group8_t<PREC>(oop, nstp, gr0 + r, gc0 + c, v);
+          store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v);
         }
 #pragma unroll 2
         for (int rd = 0; rd < 8; ++rd) {
@@ -597,7 +629,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           float v[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
-          store_group8_t<PREC>(oop, nstp, gc0 + c, gr0 + q, v);
+          store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v);
         }
       }
     }
@@ -626,8 +658,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             o32[(size_t)r * np + col] = v;
             o32[(size_t)col * np + r] = v;
             if (wsplit) {
-              store_split1<PREC>(oop, nstp, r, col, v);
-              if (r != col) store_split1<PREC>(oop, nstp, col, r, v);
+              store_split1<Store<PREC>::F>(oop, nstp, r, col, v);
+              if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v);
             }
             if (kind == kJobP) {
               const double w = r == col ? 1.0 : 2.0;
@@ -668,6 +700,7 @@ hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s)
     case kFP32: hipLaunchKernelGGL(k_step<kFP32>, dim3(njobs), dim3(NT), 0, s, args); break;
     case kSplit2: hipLaunchKernelGGL(k_step<kSplit2>, dim3(njobs), dim3(NT), 0, s, args); break;
     case kSplit3: hipLaunchKernelGGL(k_step<kSplit3>, dim3(njobs), dim3(NT), 0, s, args); break;
+    case kSplit32: hipLaunchKernelGGL(k_step<kSplit32>, dim3(njobs), dim3(NT), 0, s, args); break;
     case kBF16: hipLaunchKernelGGL(k_step<kBF16>, dim3(njobs), dim3(NT), 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
@@ -882,7 +915,7 @@ hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, 
 
 __device__ __forceinline__ void store_group8(int prec, char* op, int n_pad, int r, int c0, const float (&v)[8]) {
   if (prec == kSplit2) store_group8_t<kSplit2>(op, n_pad / Fmt<kSplit2>::K, r, c0, v);
-  else if (prec == kSplit3) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v);
+  else if (prec == kSplit3 || prec == kSplit32) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v);
   else if (prec == kBF16) store_group8_t<kBF16>(op, n_pad / Fmt<kBF16>::K, r, c0, v);
 }
 

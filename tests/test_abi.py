@@ -120,10 +120,17 @@ def test_given_bounds_validation(lib):
     assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 1
 
 
-def test_split3_accepted(lib):
-    o = _opts(lib, precision=2)
+@pytest.mark.parametrize("prec", [2, 4])
+def test_split3_accepted(lib, prec):
+    o = _opts(lib, precision=prec)
     assert lib.dmpt_workspace_bytes(C.byref(o), 1) > 0
     assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 6   # passes validation
+
+
+def test_split3x_workspace_matches_split3(lib):
+    """The mixed mode keeps three-term operand copies: same workspace as split-3."""
+    a, b = _opts(lib, 1000, 500, precision=2), _opts(lib, 1000, 500, precision=4)
+    assert lib.dmpt_workspace_bytes(C.byref(a), 2) == lib.dmpt_workspace_bytes(C.byref(b), 2)
 
 
 def test_response_validation(lib):
