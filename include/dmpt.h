@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 1
+#define DMPT_ABI_VERSION 2
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -100,6 +100,9 @@ typedef struct dmpt_opts {
                              (two sweep steps with X frozen at D: sigma = +1 then -1, in the
                              precision of the recursion; FP32 when it is plain BF16) */
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
+  int32_t ckpt_interval;  /* ADJOINT sweep only: keep X_n every ckpt_interval steps and recompute
+                             the steps in between during the backward sweep; 0 -> keep every X_n */
+  int32_t reserved;       /* must be 0 */
   double spin;            /* s; 0 -> 2 */
   void* stream;           /* hipStream_t */
   void* workspace;        /* device memory owned by the caller */
@@ -155,7 +158,9 @@ dmpt_status dmpt_sp2_density(const float* H, float* D, const dmpt_opts* opts, dm
  *   D    device, n x n, written if not NULL
  *   a0   host, nobs doubles, a0_k = s * Tr[A_k D] (Eq. expectation), written if not NULL
  *   info host, optional.
- * The adjoint sweep supports nobs == 1 and stores every X_n in the workspace. */
+ * The adjoint sweep stores every X_n in the workspace, or with opts.ckpt_interval = k
+ * every k-th one plus k - 1 recomputation slots (the steps between checkpoints
+ * are recomputed with the recorded sigma sequence before they are swept). */
 dmpt_status dmpt_susceptibility(const float* H, const float* A, int32_t nobs, float* chi,
                                 float* D, double* a0, const dmpt_opts* opts, dmpt_info* info);
 
@@ -166,7 +171,8 @@ size_t dmpt_response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n);
  *   chi  device, nobs x n x n;  H1 device, npert x n x n
  *   out  host, nobs * npert doubles (row-major), written
  *   workspace  device, >= dmpt_response_workspace_bytes(nobs, npert, n)
- * Limits: 1 <= nobs * npert <= 64. */
+ * Limits: nobs, npert >= 1, nobs * npert <= 2^20; formed in groups of up to 8 observables
+ * x 64 perturbations (one pass over the group's chi and H1 each). */
 dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32_t npert,
                           int32_t n, double* out, void* stream, void* workspace,
                           size_t workspace_bytes);

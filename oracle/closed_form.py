@@ -103,6 +103,20 @@ def first_order_response(h: np.ndarray, pert: np.ndarray, nocc: int) -> np.ndarr
     return v @ (lmat * pt) @ v.T
 
 
+def first_order_responses(h: np.ndarray, perts: np.ndarray, nocc: int) -> np.ndarray:
+    """first_order_response for a stack of perturbations (one eigendecomposition)."""
+    h = _check(h, nocc)
+    n = h.shape[0]
+    perts = np.asarray(perts, dtype=np.float64)
+    if nocc in (0, n):
+        return np.zeros_like(perts)
+    w, v = eigensystem(h)
+    if w[nocc] - w[nocc - 1] <= 1e-12 * max(1.0, np.abs(w).max()):
+        raise GaplessError("no gap at nocc: the response is not defined")
+    lmat = loewner_step(w, nocc)
+    return np.stack([v @ (lmat * (v.T @ p @ v)) @ v.T for p in perts])
+
+
 def susceptibility(h: np.ndarray, a: np.ndarray, nocc: int, spin: float = 1.0) -> np.ndarray:
     """chi^A = s * dTr[A D]/dH (Eq. Suscept), via Daleckii-Krein."""
     return spin * first_order_response(h, a, nocc)

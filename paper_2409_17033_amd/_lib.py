@@ -23,6 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
+ABI_VERSION = 2   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
 PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
@@ -42,6 +43,7 @@ class Opts(C.Structure):
         ("sweep", C.c_int32),
         ("idem_tol", C.c_double),
         ("project", C.c_int32), ("profile", C.c_int32),
+        ("ckpt_interval", C.c_int32), ("reserved", C.c_int32),
         ("spin", C.c_double),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
     ]
@@ -100,6 +102,9 @@ def load() -> C.CDLL:
     lib = C.CDLL(LIB_PATH)
     P, I32, D, SZ = C.c_void_p, C.c_int32, C.c_double, C.c_size_t
     lib.dmpt_abi_version.restype = I32
+    if lib.dmpt_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {lib.dmpt_abi_version()}, this binding expects "
+                          f"{ABI_VERSION}: rebuild it with `python -m paper_2409_17033_amd.build`")
     lib.dmpt_opts_default.argtypes = [C.POINTER(Opts), I32, I32]
     lib.dmpt_opts_default.restype = None
     lib.dmpt_workspace_bytes.argtypes = [C.POINTER(Opts), I32]

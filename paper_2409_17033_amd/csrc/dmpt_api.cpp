@@ -43,7 +43,7 @@ constexpr int kOutBlocks = 1024;
 constexpr int kChunk = 8;   // step launches between host polls of the done flag
 
 struct Opts {
-  int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile;
+  int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile, ckpt;
   double emin, emax, idem_tol, spin;
   hipStream_t stream;
   char* ws;
@@ -65,6 +65,9 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (!std::isfinite(o->spin)) return fail(DMPT_ERR_ARG, "spin must be finite");
   if (o->project != 0 && o->project != 1) return fail(DMPT_ERR_ARG, "project must be 0 or 1");
   if (o->profile != 0 && o->profile != 1) return fail(DMPT_ERR_ARG, "profile must be 0 or 1");
+  if (o->ckpt_interval < 0 || o->ckpt_interval > DMPT_MAX_STEPS)
+    return fail(DMPT_ERR_ARG, "ckpt_interval out of range [0, %d]", DMPT_MAX_STEPS);
+  if (o->reserved != 0) return fail(DMPT_ERR_ARG, "reserved must be 0");
   r->n = o->n;
   r->nocc = o->nocc;
   r->prec = o->precision == DMPT_FP32 ? kFP32
@@ -78,6 +81,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   r->sweep = o->sweep;
   r->project = o->project;
   r->profile = o->profile;
+  r->ckpt = o->ckpt_interval;
   r->emin = o->emin;
   r->emax = o->emax;
   r->idem_tol = o->idem_tol;
@@ -92,6 +96,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
 struct Plan {
   int n, n_pad, nobs, prec, tile, ntile, nb64, nparts_step;
   int xslots;
+  int ckpt, nckpt;                 // adjoint checkpoint interval (0: every X_n kept) and slot count
   size_t mat_f32, mat_op;          // bytes per matrix
   size_t off_ctl, off_part[2], off_jobs, off_jobs_proj, off_gersh, off_lz, off_a0, off_x, off_y;
   size_t x_slot_bytes, y_obs_bytes, y_slot_bytes;
@@ -120,9 +125,13 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   p->nb64 = p->n_pad / 64;
   p->nparts_step = step_tile_count(p->n_pad);
   const bool adjoint = nobs > 0 && o.sweep == DMPT_SWEEP_ADJOINT;
-  // the adjoint keeps X_1 .. X_{max_iter+2} (slot n = X_n; the last launch may
-  // write one iterate past the result before the stop is seen)
-  p->xslots = adjoint ? o.max_iter + 3 : 2;
+  // The adjoint keeps X_1 .. X_{max_iter+2} (slot n = X_n; the last launch may
+  // write one iterate past the result before the stop is seen), or with a
+  // checkpoint interval k: two working slots, one slot per X_n with
+  // (n - 1) % k == 0, and k - 1 slots to recompute a segment.
+  p->ckpt = adjoint ? o.ckpt : 0;
+  p->nckpt = p->ckpt ? (o.max_iter + 1) / p->ckpt + 1 : 0;
+  p->xslots = !adjoint ? 2 : p->ckpt ? 2 + p->nckpt + (p->ckpt - 1) : o.max_iter + 3;
   const size_t np2 = (size_t)p->n_pad * p->n_pad;
   p->mat_f32 = np2 * 4;
   p->mat_op = o.prec == kFP32 ? 0 : np2 * operand_bytes(o.prec);
@@ -491,7 +500,20 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   st = compute_bounds(o, p, H, ctl, (double*)(ws + p.off_lz), (double2*)(ws + p.off_gersh), s);
   if (st != DMPT_OK) return st;
 
-  auto xslot = [&](int n) { return adjoint ? n : (n & 1); };
+  // Slot of X_n: forward sweep 2 ping-pong slots; adjoint slot n, or with
+  // checkpoints the checkpoint slot / a working slot (forward run) and the
+  // recomputation ring (backward sweep).
+  const int k_ck = p.ckpt;
+  auto is_ckpt = [&](int n) { return (n - 1) % k_ck == 0; };
+  auto xslot = [&](int n) {
+    if (!adjoint) return n & 1;
+    if (!k_ck) return n;
+    return is_ckpt(n) ? 2 + (n - 1) / k_ck : (n & 1);
+  };
+  auto xslot_bwd = [&](int n) {
+    if (!k_ck) return n;
+    return is_ckpt(n) ? 2 + (n - 1) / k_ck : 2 + p.nckpt + ((n - 1) % k_ck - 1);
+  };
   Part* part[2] = {(Part*)(ws + p.off_part[0]), (Part*)(ws + p.off_part[1])};
   // X_1 (and Y_1 = beta A for the forward sweep) into slot of step 1
   DMPT_HIP(launch_init(p.prec, p.tile, H, A, o.n, p.n_pad, adjoint ? 0 : nobs, nullptr, 0,
@@ -574,14 +596,33 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.flush = flush_interval(yprec, p.n_pad);
     b.sigma_src = ctl->rec;
     b.jobs = d_zjobs;
+    // recomputation launches: P-jobs with the recorded sigma_n (same kernel
+    // and inputs as the forward run, so X_n is reproduced bit for bit)
+    StepArgs r = a;
+    r.decide = 0;
+    r.sigma_src = ctl->rec;
+    r.jobs = d_jobs;
+    r.part_in = part[0];
+    r.part_out = part[1];
+    r.nparts = p.nparts_step;
     int ys = 0;
-    for (int n = m; n >= 1; --n) {
-      b.step = n;
-      b.x_in = x_ref(p, ws, xslot(n));
-      b.y_in = y_ref(p, ws, ys);
-      b.y_out = y_ref(p, ws, ys ^ 1);
-      DMPT_HIP(launch_step(yprec, b, (int)zjobs.size(), s));
-      ys ^= 1;
+    for (int n1 = m; n1 >= 1;) {
+      const int n0 = k_ck ? ((n1 - 1) / k_ck) * k_ck + 1 : 1;   // first step of the segment
+      for (int n = n0; k_ck && n < n1; ++n) {
+        r.step = n;
+        r.x_in = x_ref(p, ws, xslot_bwd(n));
+        r.x_out = x_ref(p, ws, xslot_bwd(n + 1));
+        DMPT_HIP(launch_step(xprec, r, p.nparts_step, s));
+      }
+      for (int n = n1; n >= n0; --n) {
+        b.step = n;
+        b.x_in = x_ref(p, ws, xslot_bwd(n));
+        b.y_in = y_ref(p, ws, ys);
+        b.y_out = y_ref(p, ws, ys ^ 1);
+        DMPT_HIP(launch_step(yprec, b, (int)zjobs.size(), s));
+        ys ^= 1;
+      }
+      n1 = n0 - 1;
     }
     yfin = ys;
   }
@@ -714,28 +755,41 @@ dmpt_status dmpt_susceptibility(const float* H, const float* A, int32_t nobs, fl
   return run(H, A, nobs, chi, D, a0, opts, info);
 }
 
+// Responses are formed in groups of up to kRespObs observables x kRespPert
+// perturbations (one pass over the group's chi and H1 per group).
+constexpr int kRespObs = 8, kRespPert = 64, kRespMax = 1 << 20;
+
 size_t dmpt_response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n) {
-  if (nobs < 1 || nobs > 8 || npert < 1 || npert > 64 || n < 1) return 0;
+  if (nobs < 1 || npert < 1 || (int64_t)nobs * npert > kRespMax || n < 1 || n > 65536) {
+    fail(DMPT_ERR_ARG, "response sizes out of range (nobs, npert >= 1, nobs * npert <= %d, 1 <= n <= 65536)",
+         kRespMax);
+    return 0;
+  }
   const size_t n2 = (size_t)n * n;
-  return align_up((size_t)response_blocks(n2) * nobs * npert * sizeof(double)) +
+  const int ko = std::min(nobs, kRespObs), kp = std::min(npert, kRespPert);
+  return align_up((size_t)response_blocks(n2) * ko * kp * sizeof(double)) +
          align_up((size_t)nobs * npert * sizeof(double));
 }
 
 dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32_t npert, int32_t n,
                           double* out, void* stream, void* workspace, size_t workspace_bytes) {
   if (!chi || !H1 || !out) return fail(DMPT_ERR_ARG, "chi, H1 and out must not be NULL");
-  if (nobs < 1 || nobs > 8) return fail(DMPT_ERR_ARG, "nobs = %d out of range [1, 8]", nobs);
-  if (npert < 1 || npert > 64) return fail(DMPT_ERR_ARG, "npert = %d out of range [1, 64]", npert);
-  if (n < 1 || n > 65536) return fail(DMPT_ERR_ARG, "n = %d out of range [1, 65536]", n);
   const size_t need = dmpt_response_workspace_bytes(nobs, npert, n);
+  if (need == 0) return DMPT_ERR_ARG;   // message set by dmpt_response_workspace_bytes
   if (!workspace) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
   if (workspace_bytes < need) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", workspace_bytes, need);
   hipStream_t s = (hipStream_t)stream;
   const size_t n2 = (size_t)n * n;
   const int nblk = response_blocks(n2);
+  const int ko = std::min(nobs, kRespObs), kp = std::min(npert, kRespPert);
   double* part = (double*)workspace;
-  double* outd = (double*)((char*)workspace + align_up((size_t)nblk * nobs * npert * sizeof(double)));
-  DMPT_HIP(launch_response(chi, nobs, H1, npert, n2, part, nblk, outd, s));
+  double* outd = (double*)((char*)workspace + align_up((size_t)nblk * ko * kp * sizeof(double)));
+  for (int k0 = 0; k0 < nobs; k0 += kRespObs)
+    for (int p0 = 0; p0 < npert; p0 += kRespPert) {
+      const int kc = std::min(kRespObs, nobs - k0), pc = std::min(kRespPert, npert - p0);
+      DMPT_HIP(launch_response(chi + (size_t)k0 * n2, kc, H1 + (size_t)p0 * n2, pc, n2, part, nblk,
+                               outd + (size_t)k0 * npert + p0, npert, s));
+    }
   DMPT_HIP(hipMemcpyAsync(out, outd, sizeof(double) * nobs * npert, hipMemcpyDeviceToHost, s));
   DMPT_HIP(hipStreamSynchronize(s));
   return DMPT_OK;

@@ -113,7 +113,7 @@ hipError_t launch_output(const float* x32, const float* y32, size_t ystride, con
                          double scale, int scale_by_beta, const uint32_t* jobs, int njobs,
                          int tile, double* a0_part, Ctl* ctl, hipStream_t s);
 hipError_t launch_response(const float* chi, int nobs, const float* h1, int npert, size_t n2,
-                           double* part, int nblk, double* out_dev, hipStream_t s);
+                           double* part, int nblk, double* out_dev, int ld, hipStream_t s);
 int response_blocks(size_t n2);
 hipError_t launch_copy_out(const float* src, int n, int n_pad, float* dst, hipStream_t s);
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);

@@ -944,34 +944,39 @@ hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s
 // ---------------------------------------------------------------- init
 
 // X_1 = alpha I + beta H (Eq. DM0) and Y_1 = c A_k (c = beta for Eq. DM3 /
-// DMSuscept, c = 1 for the start Y_M = A of Eq. DM2), built from the upper
-// triangle of H and A.  One 64 x 64 block per workgroup over the full n_pad
-// square; lower blocks read the transposed upper block through LDS so every
-// global access is row-contiguous.  Blocks of X emit (Tr, ||.||^2) partials.
+// DMSuscept, c = 1 for the start Y_M = A of Eq. DM2), built from the
+// symmetric parts (S + S^T)/2 of H and A (exactly symmetric in FP32).  One
+// 64 x 64 block per workgroup over the full n_pad square; the block and its
+// transpose are both read row-wise and combined through LDS.  Blocks of X
+// emit (Tr, ||.||^2) partials.
 __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const float* a, int n,
                                               int n_pad, int zoff, MatRef x, MatRef y,
                                               double y_scale_mode, Part* part, Ctl* ctl) {
-  __shared__ float tile[64][65];
+  __shared__ float tile[64][65];    // block (bi, bj) of the source
+  __shared__ float tileT[64][65];   // block (bj, bi) of the source
   __shared__ double s_red[8];
   const int bi = blockIdx.y, bj = blockIdx.x;   // output block (row, col)
   const int z = blockIdx.z + zoff;               // 0: X from H; k >= 1: Y_{k-1} from A_{k-1}
-  const bool lower = bi > bj;
-  const int sbi = lower ? bj : bi, sbj = lower ? bi : bj;
   const float* src = z == 0 ? h : a + (size_t)(z - 1) * n * n;
   const int t = threadIdx.x;
   int bad = 0;
-  // stage the source block (sbi, sbj) row-wise
+  // stage both blocks row-wise (coalesced); the symmetric part is
+  // (S_ij + S_ji) / 2, formed below from tile[r][c] and tileT[c][r]
   for (int e = t; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
-    const int gi = sbi * 64 + r, gj = sbj * 64 + c;
-    float v = 0.0f;
+    const int gi = bi * 64 + r, gj = bj * 64 + c;
+    const int ti_ = bj * 64 + r, tj_ = bi * 64 + c;
+    float v = 0.0f, w = 0.0f;
     if (gi < n && gj < n) {
-      // upper triangle only: inside a diagonal block take (min, max)
-      const int ui = gi <= gj ? gi : gj, uj = gi <= gj ? gj : gi;
-      v = src[(size_t)ui * n + uj];
+      v = src[(size_t)gi * n + gj];
       if (!isfinite(v)) bad = 1;
     }
+    if (ti_ < n && tj_ < n) {
+      w = src[(size_t)ti_ * n + tj_];
+      if (!isfinite(w)) bad = 1;
+    }
     tile[r][c] = v;
+    tileT[r][c] = w;
   }
   if (bad) ctl->nonfinite = 1;
   __syncthreads();
@@ -991,7 +996,7 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int c = cg + e, gj = bj * 64 + c;
-      const float s = lower ? tile[c][r] : tile[r][c];
+      const double s = 0.5 * ((double)tile[r][c] + (double)tileT[c][r]);
       double val;
       if (z == 0) {
         val = beta * (double)s + ((gi == gj && gi < n) ? alpha : 0.0);
@@ -1166,16 +1171,19 @@ __global__ __launch_bounds__(kRespThreads) void k_response(const float* chi, con
   }
 }
 
-__global__ __launch_bounds__(64) void k_response_final(const double* part, int nblk, int kp, double* out) {
-  const int idx = blockIdx.x;   // one output per block, fixed summation order
+// out[k * ld + p] = sum over blocks of part[b][k][p] (one output per block,
+// fixed summation order).
+__global__ __launch_bounds__(64) void k_response_final(const double* part, int nblk, int npert, int kp,
+                                                       double* out, int ld) {
+  const int idx = blockIdx.x;
   double acc = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 64) acc += part[(size_t)b * kp + idx];
   acc = wave_sum(acc);
-  if (threadIdx.x == 0) out[idx] = acc;
+  if (threadIdx.x == 0) out[(size_t)(idx / npert) * ld + idx % npert] = acc;
 }
 
 hipError_t launch_response(const float* chi, int nobs, const float* h1, int npert, size_t n2,
-                           double* part, int nblk, double* out_dev, hipStream_t s) {
+                           double* part, int nblk, double* out_dev, int ld, hipStream_t s) {
   switch (nobs) {
 #define DMPT_RESP(K)                                                                      \
   case K:                                                                                 \
@@ -1193,7 +1201,8 @@ hipError_t launch_response(const float* chi, int nobs, const float* h1, int nper
     default:
       return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_response_final, dim3(nobs * npert), dim3(64), 0, s, part, nblk, nobs * npert, out_dev);
+  hipLaunchKernelGGL(k_response_final, dim3(nobs * npert), dim3(64), 0, s, part, nblk, npert, nobs * npert,
+                     out_dev, ld);
   return hipGetLastError();
 }
 

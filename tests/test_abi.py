@@ -36,14 +36,15 @@ def test_exports_every_declared_function(lib):
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 1
+    assert lib.dmpt_abi_version() == 2
 
 
 def test_struct_layouts():
     from paper_2409_17033_amd._lib import Info, Opts
     # sizes follow from the C declarations with natural alignment
-    assert C.sizeof(Opts) == 96
-    assert Opts.spin.offset == 64 and Opts.workspace_bytes.offset == 88
+    assert C.sizeof(Opts) == 104
+    assert Opts.spin.offset == 72 and Opts.workspace_bytes.offset == 96
+    assert Opts.ckpt_interval.offset == 64
     assert Info.sigma.offset == 56
     assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4
     assert Info.idem_x.offset == 56 + 256 + 2 * 256 * 8
@@ -65,6 +66,23 @@ def _opts(lib, n=64, nocc=32, **kw):
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def test_checkpoint_workspace(lib):
+    """Adjoint with checkpoints every k steps: 2 working + ceil slots + k - 1 ring
+    instead of max_iter + 3 slots."""
+    full = _opts(lib, 1000, 500, sweep=1)
+    w_full = lib.dmpt_workspace_bytes(C.byref(full), 1)
+    slot = 1024 * 1024 * 4
+    for k in (1, 4, 8, 16):
+        ck = _opts(lib, 1000, 500, sweep=1, ckpt_interval=k)
+        w = lib.dmpt_workspace_bytes(C.byref(ck), 1)
+        nslots = 2 + (100 + 1) // k + 1 + (k - 1)
+        assert w_full - w == (103 - nslots) * slot, k
+    bad = _opts(lib, 1000, 500, sweep=1, ckpt_interval=-1)
+    assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
+    bad = _opts(lib, 1000, 500, reserved=3)
+    assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
 
 
 def test_workspace_bytes(lib):
@@ -136,10 +154,15 @@ def test_split3x_workspace_matches_split3(lib):
 def test_response_validation(lib):
     out = (C.c_double * 4)()
     assert lib.dmpt_response(None, 1, FAKE, 1, 8, out, None, FAKE, 1 << 20) == 1
-    assert lib.dmpt_response(FAKE, 9, FAKE, 1, 8, out, None, FAKE, 1 << 20) == 1
-    assert lib.dmpt_response(FAKE, 1, FAKE, 65, 8, out, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_response(FAKE, 0, FAKE, 1, 8, out, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_response(FAKE, 1, FAKE, 0, 8, out, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_response(FAKE, 2048, FAKE, 1024, 8, out, None, FAKE, 1 << 20) == 1   # > 2^20 outputs
+    assert lib.dmpt_response(FAKE, 1, FAKE, 1, 0, out, None, FAKE, 1 << 20) == 1
     assert lib.dmpt_response(FAKE, 1, FAKE, 1, 8, out, None, None, 0) == 6
+    assert lib.dmpt_response(FAKE, 16, FAKE, 32, 8, out, None, FAKE, 64) == 6   # too small
     assert lib.dmpt_response_workspace_bytes(1, 8, 8192) > 0
+    # groups of 8 x 64: partials sized for one group, outputs for all
+    assert lib.dmpt_response_workspace_bytes(16, 32, 8192) > lib.dmpt_response_workspace_bytes(8, 32, 8192)
 
 
 def test_scf_response_unsupported(lib):

@@ -182,3 +182,13 @@ def test_gapless_raises():
         cf.density_matrix(h, 6)
     with pytest.raises(cf.GaplessError):
         cf.susceptibility(h, np.eye(12), 6)
+
+
+def test_batched_responses_equal_single():
+    """The stacked form is the single-perturbation definition applied per matrix."""
+    wl = W.dense_gapped(64, nocc=20)
+    h = wl.H.astype(np.float64)
+    ps = np.stack([wl.A[0], wl.H1[0], wl.H1[1]]).astype(np.float64)
+    out = cf.first_order_responses(h, ps, wl.nocc)
+    for k in range(3):
+        np.testing.assert_allclose(out[k], cf.first_order_response(h, ps[k], wl.nocc), rtol=0, atol=1e-13)
