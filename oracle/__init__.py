@@ -18,6 +18,10 @@ sp2           The SP2 recursion (Eq. DM0), its first-order response (Eq. DM1),
               (Eq. DMSuscept, Eq. DMPert), all in FP64 with full GEMMs.
 finite_diff   Brute-force central differences of <A> = Tr[A D(H)] (definition
               of chi in Eq. Suscept) for tiny N.
+scf           Self-consistent susceptibility (Eq. CP_SCF) and density response
+              (Eq. DM_CP_SCF) for an on-site interaction, iterated with linear
+              mixing as the paper writes them; the SCF ground state for FD.
+mlp           The learned mixer network (forward, MSE loss gradient, Adam) in FP64.
 
 Pins (tests/test_oracle_*.py): hand-derived 2x2 closed forms, textbook
 Rayleigh-Schroedinger first-order theory for diagonal H, brute-force finite
@@ -25,4 +29,4 @@ differences, exact-spectrum constructions, projector identities, the
 commutator identity [H, chi] = [D, A], the duality identity for unconverged
 recursions and the forward/backward equivalence.
 """
-from . import closed_form, sp2, finite_diff  # noqa: F401
+from . import closed_form, sp2, finite_diff, scf, mlp  # noqa: F401
