@@ -177,18 +177,107 @@ dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32
                           int32_t n, double* out, void* stream, void* workspace,
                           size_t workspace_bytes);
 
-/* Self-consistent susceptibility (Eq. CP_SCF) with an on-site interaction
- * G(X) = diag(U_i * s * X_ii) and linear mixing.  Not implemented in this
- * build: validates its arguments and returns DMPT_ERR_UNSUPPORTED. */
+/* ---------------------------------------------------------------------------
+ * Self-consistent susceptibility (Eq. CP_SCF; Sec. V.C and the Appendix) at
+ * zero temperature in an orthonormal basis (Z = I, mu_1 = 0), for an on-site
+ * self-consistent field: H = H0 + diag(U_i (n_i - n0_i)), n = s diag(D),
+ * n0 = s diag(D(H0)), whose linearised field of a density-matrix change X is
+ * G(X) = diag(U_i s X_ii) (self-adjoint, as the dual formulation needs).
+ * The susceptibility of A solves chi' = L[A + G(chi')] with L the
+ * non-interacting response of H0; the result is chi = s chi'.  G reads only
+ * the diagonal, so the iteration state is v = diag(chi'):
+ *   F(v) = diag(L[A + diag(U s v)]),  r = F(v) - v,
+ *   stop when ||r||_2 <= tol ||F(v)||_2.
+ * The SP2 recursion of H0 runs once (X_n stored, adjoint sweep); every
+ * iteration is one backward sweep (Eq. DM2) of the diagonal observable
+ * diag(U s v), plus the occupied-virtual projection.  Mixers:
+ *   LINEAR    v <- v + mix r                           (the paper's c_mix)
+ *   ANDERSON  Anderson/Pulay extrapolation over the last anderson_depth
+ *             iterates with step mix
+ *   LEARNED   v <- v + mix r + (||r|| / sqrt(n)) net(sqrt(n) r / ||r||), net
+ *             the BF16 site-local network of dmpt_mixer_*; a step whose
+ *             residual does not decrease is rejected and replaced by the
+ *             linear step (linear mixing is the fallback and the judge).
+ * Inputs: H0, A device n x n; U device n floats; chi device n x n (written).
+ * opts: as for dmpt_susceptibility (sweep, spin, workspace are taken from it;
+ * the sweep is forced to ADJOINT); workspace >= dmpt_scf_workspace_bytes.
+ * info (optional) describes the SP2 recursion of H0; sinfo (optional) the
+ * self-consistent loop.  NOT_CONVERGED when max_iter is reached (chi then
+ * holds the last iterate). */
+typedef enum dmpt_mixer { DMPT_MIX_LINEAR = 0, DMPT_MIX_ANDERSON = 1, DMPT_MIX_LEARNED = 2 } dmpt_mixer;
+
+#define DMPT_MAX_SCF 1024
+
 typedef struct dmpt_scf_opts {
-  int32_t max_iter;
-  int32_t reserved0;
-  double mix;             /* c_mix of Eq. CP_SCF */
-  double tol;             /* stop when ||delta chi||_F <= tol */
+  int32_t max_iter;           /* F evaluations, 1 .. DMPT_MAX_SCF */
+  int32_t mixer;              /* dmpt_mixer */
+  double mix;                 /* c_mix, 0 < mix <= 1 */
+  double tol;                 /* relative residual target, > 0 */
+  int32_t anderson_depth;     /* ANDERSON: 1 .. 16 */
+  int32_t mlp_hidden;         /* LEARNED: hidden width of the network */
+  int32_t mlp_window;         /* LEARNED: half-width w of the site window */
+  int32_t reserved;           /* must be 0 */
+  const uint16_t* mlp_params; /* LEARNED: device, BF16 parameters (dmpt_mixer layout) */
+  float* record_v;            /* optional, device, max_iter x n: v of every accepted state */
+  float* record_r;            /* optional, device, max_iter x n: r = F(v) - v of every accepted state */
 } dmpt_scf_opts;
 
+typedef struct dmpt_scf_info {
+  int32_t iters;                   /* F evaluations done (the cost: one backward sweep each, but the first) */
+  int32_t converged;               /* 1 if the residual target was met */
+  int32_t rejected;                /* ANDERSON / LEARNED steps replaced by the linear step */
+  int32_t states;                  /* accepted states, v_0 = 0 included (rows of record_v / record_r) */
+  double residual[DMPT_MAX_SCF];   /* ||r|| / ||F(v)|| of every accepted state */
+} dmpt_scf_info;
+
+size_t dmpt_scf_workspace_bytes(const dmpt_opts* opts, const dmpt_scf_opts* scf);
+
 dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
-                              const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info);
+                              const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info,
+                              dmpt_scf_info* sinfo);
+
+/* ---------------------------------------------------------------------------
+ * Learned mixer network (the LEARNED mixer of dmpt_scf_response; not from the
+ * paper, which mixes linearly).  It is applied site by site with shared
+ * weights: for a state vector x in R^n, site i sees
+ *   z_i = [x_{i-w}, ..., x_{i+w}, U_i]       (k = 2w + 2 features; x_j = 0
+ *                                             outside 0..n-1)
+ * and outputs y_i = w2 . tanh(W1 z_i + b1) + b2 (hidden width h).  The
+ * response of a gapped system is near-sighted, so a window of sites carries
+ * the information a preconditioner of the self-consistent loop needs.
+ * BF16 parameters in one vector [W1 (h x k, row-major) | b1 (h) | w2 (h) |
+ * b2 (1)]; training minimises the mean squared error over all B n outputs,
+ * (1 / (B n)) sum (y - t)^2, with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on
+ * FP32 master parameters.  Arrays are device arrays; batches are row-major
+ * B x n; U is the n on-site interactions.  Training pairs of the
+ * self-consistent loop: x = sqrt(n) r / ||r||, t = sqrt(n) (v* - v - mix r) / ||r||
+ * from linear-mixing runs (v* their converged state). */
+size_t dmpt_mixer_param_count(int32_t window, int32_t hidden);
+/* Scratch for batches of up to `batch` states of size n.  Limits: n <= 65536,
+ * window <= 512, hidden <= 4096, batch * n <= 2^20 site rows; 0 (with the
+ * error message set) when out of range.  Every mixer call with sizes out of
+ * range returns DMPT_ERR_ARG; a workspace smaller than this returns
+ * DMPT_ERR_WORKSPACE. */
+size_t dmpt_mixer_workspace_bytes(int32_t n, int32_t window, int32_t hidden, int32_t batch);
+/* Glorot-uniform weights from a counter-based generator (splitmix64 of seed
+ * and index), zero biases; writes the FP32 masters and the BF16 copy. */
+dmpt_status dmpt_mixer_init(float* master, uint16_t* params, int32_t window, int32_t hidden, uint64_t seed,
+                            void* stream);
+dmpt_status dmpt_mixer_forward(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+                               const float* x, int32_t batch, float* y, void* stream, void* workspace,
+                               size_t workspace_bytes);
+/* loss (host) and its gradient (device, FP32, parameter layout) for one batch. */
+dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+                                 const float* x, const float* t, int32_t batch, float* grad, double* loss,
+                                 void* stream, void* workspace, size_t workspace_bytes);
+/* steps Adam steps (step counter starting at 1) over minibatches of `batch`
+ * consecutive states cycling through the npairs pairs; adam_m and adam_v
+ * start at zero (caller-owned, parameter-count floats); loss_history (host,
+ * optional) receives the loss of every step. */
+dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, float* adam_v, int32_t window,
+                             int32_t hidden, const float* U, int32_t n, const float* x, const float* t,
+                             int32_t npairs, int32_t batch, int32_t steps, double lr, double* loss_history,
+                             void* stream, void* workspace, size_t workspace_bytes);
 
 /* Host mirror of the device-side step controller (pure function, no device).
  * Decision for iterate X_n (Sec. II) from FP64 Tr X_n, ||X_n||_F^2, its

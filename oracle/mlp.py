@@ -2,56 +2,80 @@
 self-consistent response loop).  TEST INFRASTRUCTURE ONLY (see
 oracle/__init__.py).
 
-Network: x in R^n -> y = W2 tanh(W1 x + b1) + b2 in R^n, hidden width h.
-Parameters are one vector [W1 (h x n, row-major), b1 (h), W2 (n x h,
-row-major), b2 (n)].  Loss over a batch of B pairs (x_b, t_b): the mean
-squared error L = (1 / (B n)) sum_b ||y_b - t_b||^2.  Training uses Adam
-(Kingma & Ba, 2015): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
-p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+The network is applied site by site with shared weights: for a residual
+vector x in R^n (one self-consistent state) the input of site i is
+    z_i = [x_{i-w}, ..., x_{i+w}, U_i]          (k = 2w + 2 features;
+                                                 x_j = 0 outside 0..n-1)
+and the output is the scalar
+    y_i = w2 . tanh(W1 z_i + b1) + b2,
+a two-layer network of hidden width h.  Parameters are one vector
+[W1 (h x k, row-major), b1 (h), w2 (h), b2 (1)].  Loss over a batch of B
+states: the mean squared error L = (1 / (B n)) sum_{b,i} (y_bi - t_bi)^2.
+Training uses Adam (Kingma & Ba, 2015): m = b1 m + (1 - b1) g,
+v = b2 v + (1 - b2) g^2, p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def param_count(n: int, h: int) -> int:
-    return h * n + h + n * h + n
+def features(window: int) -> int:
+    return 2 * window + 2
 
 
-def unpack(p: np.ndarray, n: int, h: int):
+def param_count(window: int, h: int) -> int:
+    k = features(window)
+    return h * k + h + h + 1
+
+
+def unpack(p: np.ndarray, window: int, h: int):
     p = np.asarray(p, np.float64)
+    k = features(window)
     o = 0
-    w1 = p[o:o + h * n].reshape(h, n); o += h * n
+    w1 = p[o:o + h * k].reshape(h, k); o += h * k
     b1 = p[o:o + h]; o += h
-    w2 = p[o:o + n * h].reshape(n, h); o += n * h
-    b2 = p[o:o + n]
+    w2 = p[o:o + h]; o += h
+    b2 = p[o]
     return w1, b1, w2, b2
 
 
-def forward(p, x, n: int, h: int):
-    """x: (B, n) -> (y (B, n), hidden activations (B, h))."""
-    w1, b1, w2, b2 = unpack(p, n, h)
-    a = np.tanh(np.asarray(x, np.float64) @ w1.T + b1)
-    return a @ w2.T + b2, a
-
-
-def loss_grad(p, x, t, n: int, h: int):
-    """(loss, gradient with respect to the packed parameters)."""
+def site_inputs(x: np.ndarray, u: np.ndarray, window: int) -> np.ndarray:
+    """(B, n) states -> (B * n, k) site inputs, rows ordered (b, i)."""
     x = np.asarray(x, np.float64)
-    t = np.asarray(t, np.float64)
-    w1, b1, w2, b2 = unpack(p, n, h)
-    y, a = forward(p, x, n, h)
-    bsz = x.shape[0]
-    r = y - t
-    loss = float(np.sum(r * r) / (bsz * n))
-    dy = 2.0 * r / (bsz * n)                 # dL/dy
-    gw2 = dy.T @ a
-    gb2 = dy.sum(axis=0)
-    da = dy @ w2
-    dz = da * (1.0 - a * a)                  # tanh'
-    gw1 = dz.T @ x
+    bsz, n = x.shape
+    k = features(window)
+    z = np.zeros((bsz, n, k))
+    for d in range(-window, window + 1):
+        lo, hi = max(0, -d), min(n, n - d)          # sites i with 0 <= i + d < n
+        if lo < hi:                                 # none when |d| >= n
+            z[:, lo:hi, d + window] = x[:, lo + d:hi + d]
+    z[:, :, k - 1] = np.asarray(u, np.float64)[None, :]
+    return z.reshape(bsz * n, k)
+
+
+def forward(p, x, u, window: int, h: int):
+    """x: (B, n) -> (y (B, n), site inputs, hidden activations)."""
+    w1, b1, w2, b2 = unpack(p, window, h)
+    bsz, n = np.asarray(x).shape
+    z = site_inputs(x, u, window)
+    a = np.tanh(z @ w1.T + b1)
+    return (a @ w2 + b2).reshape(bsz, n), z, a
+
+
+def loss_grad(p, x, t, u, window: int, h: int):
+    """(loss, gradient with respect to the packed parameters)."""
+    w1, b1, w2, b2 = unpack(p, window, h)
+    y, z, a = forward(p, x, u, window, h)
+    r = (y - np.asarray(t, np.float64)).ravel()
+    m = r.size
+    loss = float(r @ r / m)
+    dy = 2.0 * r / m
+    gw2 = a.T @ dy
+    gb2 = dy.sum()
+    dz = np.outer(dy, w2) * (1.0 - a * a)
+    gw1 = dz.T @ z
     gb1 = dz.sum(axis=0)
-    return loss, np.concatenate([gw1.ravel(), gb1, gw2.ravel(), gb2])
+    return loss, np.concatenate([gw1.ravel(), gb1, gw2, [gb2]])
 
 
 def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,

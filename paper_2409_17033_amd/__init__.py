@@ -162,15 +162,46 @@ def sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter=10, idem_tol=0.0
     return int(load().dmpt_sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter, idem_tol))
 
 
-def scf_response(H0, U, A, nocc: int, *, max_iter=50, mix=0.3, tol=1e-6, **kw):
-    """Eq. CP_SCF (not implemented in this build: raises DMPTError UNSUPPORTED)."""
+def scf_response(H0, U, A, nocc: int, *, mixer: str = "linear", max_iter: int = 200, mix: float = 0.3,
+                 tol: float = 1e-6, anderson_depth: int = 5, net=None, record: bool = False,
+                 raise_on_error: bool = True, **kw):
+    """Eq. CP_SCF: self-consistent chi = s chi', chi' = L[A + G(chi')], G(X) = diag(U s diag X).
+
+    mixer: "linear" (c_mix = mix), "anderson" or "learned" (net: a mixer.Mixer).
+    Returns (chi, scf_info dict, info dict of the SP2 recursion); with
+    record=True also (v, r) of every accepted state, each (states, n).
+    """
     torch = _torch()
+    from ._lib import MIXER, SCFInfo, SCFOpts
     n = H0.shape[-1]
-    o = make_opts(n, nocc, **kw)
-    s = SCFOpts(max_iter=max_iter, mix=mix, tol=tol)
+    _check_matrix(H0, n, "H0")
+    _check_matrix(A, n, "A")
+    o = make_opts(n, nocc, sweep="adjoint", **kw)
+    sopt = SCFOpts(max_iter=max_iter, mixer=MIXER[mixer], mix=mix, tol=tol, anderson_depth=anderson_depth)
+    if mixer == "learned":
+        if net is None:
+            raise ValueError("the learned mixer needs net=Mixer(...)")
+        sopt.mlp_hidden, sopt.mlp_window = net.hidden, net.window
+        sopt.mlp_params = net.params.data_ptr()
+    rec_v = rec_r = None
+    if record:
+        rec_v = torch.zeros((max_iter, n), dtype=torch.float32, device=H0.device)
+        rec_r = torch.zeros((max_iter, n), dtype=torch.float32, device=H0.device)
+        sopt.record_v, sopt.record_r = rec_v.data_ptr(), rec_r.data_ptr()
+    lib = load()
+    nbytes = int(lib.dmpt_scf_workspace_bytes(C.byref(o), C.byref(sopt)))
+    if nbytes == 0:
+        check(1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=H0.device)
+    o.workspace, o.workspace_bytes = ws.data_ptr(), nbytes
     chi = torch.empty((n, n), dtype=torch.float32, device=H0.device)
-    st = load().dmpt_scf_response(C.c_void_p(H0.data_ptr()), C.c_void_p(U.data_ptr()),
-                                  C.c_void_p(A.data_ptr()), C.c_void_p(chi.data_ptr()),
-                                  C.byref(s), C.byref(o), None)
-    check(st)
-    return chi
+    info, sinfo = Info(), SCFInfo()
+    st = lib.dmpt_scf_response(C.c_void_p(H0.data_ptr()), C.c_void_p(U.data_ptr()), C.c_void_p(A.data_ptr()),
+                               C.c_void_p(chi.data_ptr()), C.byref(sopt), C.byref(o), C.byref(info),
+                               C.byref(sinfo))
+    if st != 0 and (raise_on_error or st != 3):
+        check(st, info)
+    out = (chi, sinfo.as_dict(), info.as_dict())
+    if record:
+        out = out + (rec_v[:sinfo.states], rec_r[:sinfo.states])
+    return out

@@ -31,7 +31,9 @@ SWEEP = {"forward": 0, "adjoint": 1}
 EXPORTS = [
     "dmpt_abi_version", "dmpt_opts_default", "dmpt_workspace_bytes", "dmpt_sp2_density",
     "dmpt_susceptibility", "dmpt_response_workspace_bytes", "dmpt_response",
-    "dmpt_scf_response", "dmpt_sp2_decide", "dmpt_status_string", "dmpt_last_error",
+    "dmpt_scf_response", "dmpt_scf_workspace_bytes", "dmpt_mixer_param_count", "dmpt_mixer_workspace_bytes",
+    "dmpt_mixer_init", "dmpt_mixer_forward", "dmpt_mixer_loss_grad", "dmpt_mixer_train",
+    "dmpt_sp2_decide", "dmpt_status_string", "dmpt_last_error",
 ]
 
 
@@ -76,9 +78,24 @@ class Info(C.Structure):
         }
 
 
+MIXER = {"linear": 0, "anderson": 1, "learned": 2}
+DMPT_MAX_SCF = 1024
+
+
 class SCFOpts(C.Structure):
-    _fields_ = [("max_iter", C.c_int32), ("reserved0", C.c_int32), ("mix", C.c_double),
-                ("tol", C.c_double)]
+    _fields_ = [("max_iter", C.c_int32), ("mixer", C.c_int32), ("mix", C.c_double), ("tol", C.c_double),
+                ("anderson_depth", C.c_int32), ("mlp_hidden", C.c_int32), ("mlp_window", C.c_int32),
+                ("reserved", C.c_int32), ("mlp_params", C.c_void_p),
+                ("record_v", C.c_void_p), ("record_r", C.c_void_p)]
+
+
+class SCFInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rejected", C.c_int32),
+                ("states", C.c_int32), ("residual", C.c_double * DMPT_MAX_SCF)]
+
+    def as_dict(self) -> dict:
+        return {"iters": self.iters, "converged": bool(self.converged), "rejected": self.rejected,
+                "states": self.states, "residual": list(self.residual[:self.states])}
 
 
 class DMPTError(RuntimeError):
@@ -117,8 +134,23 @@ def load() -> C.CDLL:
     lib.dmpt_response_workspace_bytes.restype = SZ
     lib.dmpt_response.argtypes = [P, I32, P, I32, I32, C.POINTER(D), P, P, SZ]
     lib.dmpt_response.restype = C.c_int
-    lib.dmpt_scf_response.argtypes = [P, P, P, P, C.POINTER(SCFOpts), C.POINTER(Opts), C.POINTER(Info)]
+    lib.dmpt_scf_response.argtypes = [P, P, P, P, C.POINTER(SCFOpts), C.POINTER(Opts), C.POINTER(Info),
+                                      C.POINTER(SCFInfo)]
     lib.dmpt_scf_response.restype = C.c_int
+    lib.dmpt_scf_workspace_bytes.argtypes = [C.POINTER(Opts), C.POINTER(SCFOpts)]
+    lib.dmpt_scf_workspace_bytes.restype = SZ
+    lib.dmpt_mixer_param_count.argtypes = [I32, I32]
+    lib.dmpt_mixer_param_count.restype = SZ
+    lib.dmpt_mixer_workspace_bytes.argtypes = [I32, I32, I32, I32]
+    lib.dmpt_mixer_workspace_bytes.restype = SZ
+    lib.dmpt_mixer_init.argtypes = [P, P, I32, I32, C.c_uint64, P]
+    lib.dmpt_mixer_init.restype = C.c_int
+    lib.dmpt_mixer_forward.argtypes = [P, I32, I32, P, I32, P, I32, P, P, P, SZ]
+    lib.dmpt_mixer_forward.restype = C.c_int
+    lib.dmpt_mixer_loss_grad.argtypes = [P, I32, I32, P, I32, P, P, I32, P, C.POINTER(D), P, P, SZ]
+    lib.dmpt_mixer_loss_grad.restype = C.c_int
+    lib.dmpt_mixer_train.argtypes = [P, P, P, P, I32, I32, P, I32, P, P, I32, I32, I32, D, C.POINTER(D), P, P, SZ]
+    lib.dmpt_mixer_train.restype = C.c_int
     lib.dmpt_sp2_decide.argtypes = [D, D, D, D, I32, I32, D, I32, D]
     lib.dmpt_sp2_decide.restype = I32
     lib.dmpt_status_string.argtypes = [C.c_int]

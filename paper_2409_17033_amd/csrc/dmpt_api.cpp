@@ -425,8 +425,12 @@ __global__ void k_trivial(float* d, float* chi, int n, int nobs, int full, const
 }
 
 // The shared driver of dmpt_sp2_density and dmpt_susceptibility.
+// One solve.  reuse_x: the workspace already holds the bounds, the control
+// block and every stored X_n of an earlier adjoint solve with the same H and
+// options (the self-consistent loop sweeps new observables over one SP2
+// recursion); only the backward sweep, projection and outputs run.
 dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, double* a0,
-                const dmpt_opts* opts, dmpt_info* info) {
+                const dmpt_opts* opts, dmpt_info* info, bool reuse_x = false) {
   Opts o;
   dmpt_status st = normalise(opts, &o);
   if (st != DMPT_OK) return st;
@@ -495,10 +499,13 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   Profiler prof;
   prof.on = o.profile != 0;
   prof.s = s;
+  if (reuse_x && !adjoint) return fail(DMPT_ERR_ARG, "reusing the recursion needs the adjoint sweep");
   const int mb0 = prof.mark();
-  DMPT_HIP(launch_ctl_reset(ctl, s));
-  st = compute_bounds(o, p, H, ctl, (double*)(ws + p.off_lz), (double2*)(ws + p.off_gersh), s);
-  if (st != DMPT_OK) return st;
+  if (!reuse_x) {
+    DMPT_HIP(launch_ctl_reset(ctl, s));
+    st = compute_bounds(o, p, H, ctl, (double*)(ws + p.off_lz), (double2*)(ws + p.off_gersh), s);
+    if (st != DMPT_OK) return st;
+  }
 
   // Slot of X_n: forward sweep 2 ping-pong slots; adjoint slot n, or with
   // checkpoints the checkpoint slot / a working slot (forward run) and the
@@ -516,8 +523,9 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   };
   Part* part[2] = {(Part*)(ws + p.off_part[0]), (Part*)(ws + p.off_part[1])};
   // X_1 (and Y_1 = beta A for the forward sweep) into slot of step 1
-  DMPT_HIP(launch_init(p.prec, p.tile, H, A, o.n, p.n_pad, adjoint ? 0 : nobs, nullptr, 0,
-                       x_ref(p, ws, xslot(1)), y_ref(p, ws, 1), 0.0, part[1], ctl, s));
+  if (!reuse_x)
+    DMPT_HIP(launch_init(p.prec, p.tile, H, A, o.n, p.n_pad, adjoint ? 0 : nobs, nullptr, 0,
+                         x_ref(p, ws, xslot(1)), y_ref(p, ws, 1), 0.0, part[1], ctl, s));
   const int mb1 = prof.mark();
   std::vector<std::pair<int, int>> step_marks;
 
@@ -543,7 +551,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   const int njobs_step = adjoint ? p.nparts_step : njobs_main;
   const uint32_t* step_jobs = adjoint ? d_jobs + 0 : d_jobs;
   // adjoint X-only run uses the P-jobs only (the table holds no Z-jobs then)
-  int done = 0;
+  int done = reuse_x ? 1 : 0;
   int launched = 0;
   for (int n = 1; n <= o.max_iter + 2 && !done;) {
     const int end = std::min(o.max_iter + 2, n + kChunk - 1);
@@ -795,16 +803,425 @@ dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32
   return DMPT_OK;
 }
 
-dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
-                              const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info) {
-  (void)info;
-  Opts o;
-  dmpt_status st = normalise(opts, &o);
+// ---------------------------------------------------------------- learned mixer
+
+namespace dmpt {
+namespace {
+
+constexpr int kMixerMaxSteps = 65536;
+constexpr int kMixerMseBlocks = 256;
+
+struct MixWS {
+  size_t scratch, part, grad, loss, total;
+};
+
+bool mixer_sizes_ok(int n, int w, int h, int batch) {
+  return n >= 1 && n <= 65536 && w >= 0 && w <= 512 && h >= 1 && h <= 4096 && batch >= 1 &&
+         (size_t)batch * n <= ((size_t)1 << 20) && (size_t)batch * n * (2 * w + 2 + 2 * h) <= ((size_t)1 << 31);
+}
+
+MixWS mixer_ws(int n, int w, int h, int batch) {
+  MixWS m;
+  size_t off = 0;
+  m.scratch = off; off = align_up(off + mixer_scratch_floats(n, w, h, batch) * 4);
+  m.part = off; off = align_up(off + (size_t)kMixerMseBlocks * 8);
+  m.grad = off; off = align_up(off + mixer_param_count(w, h) * 4);
+  m.loss = off; off = align_up(off + (size_t)kMixerMaxSteps * 8);
+  m.total = off;
+  return m;
+}
+
+dmpt_status mixer_check(int n, int w, int h, int batch, void* ws, size_t wsb, MixWS* m) {
+  if (!mixer_sizes_ok(n, w, h, batch))
+    return fail(DMPT_ERR_ARG, "mixer sizes out of range (n %d, window %d, hidden %d, batch %d)", n, w, h, batch);
+  *m = mixer_ws(n, w, h, batch);
+  if (!ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", m->total);
+  if (wsb < m->total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", wsb, m->total);
+  return DMPT_OK;
+}
+
+// ---------------------------------------------------------------- self-consistent loop
+
+struct ScfWS {
+  size_t run_bytes;
+  size_t ca, cw[2], wmat, da, v, f, r, vt, ft, rt, x, y, mlp, dv, dr, tab, coef, dot, total;
+};
+
+ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
+  ScfWS w;
+  size_t off = align_up(run_bytes);
+  const size_t mat = align_up((size_t)n * n * 4), vec = align_up((size_t)n * 8);
+  w.run_bytes = run_bytes;
+  w.ca = off; off += mat;
+  w.cw[0] = off; off += mat;
+  w.cw[1] = off; off += mat;
+  w.wmat = off; off += mat;
+  w.da = off; off += vec;
+  w.v = off; off += vec;
+  w.f = off; off += vec;
+  w.r = off; off += vec;
+  w.vt = off; off += vec;
+  w.ft = off; off += vec;
+  w.rt = off; off += vec;
+  w.x = off; off += align_up((size_t)n * 4);
+  w.y = off; off += align_up((size_t)n * 4);
+  w.mlp = off; off += hidden > 0 ? align_up(mixer_scratch_floats(n, window, hidden, 1) * 4) : 0;
+  w.dv = off; off += (size_t)depth * vec;
+  w.dr = off; off += (size_t)depth * vec;
+  w.tab = off; off += align_up((size_t)2 * (2 + 2 * 16) * sizeof(void*));
+  w.coef = off; off += align_up((size_t)(2 + 2 * 16) * 8);
+  w.dot = off; off += align_up((size_t)(16 * 16 + 32) * 8);
+  w.total = off;
+  return w;
+}
+
+dmpt_status scf_check(const dmpt_opts* opts, const dmpt_scf_opts* scf, Opts* o, dmpt_opts* o2, size_t* run_bytes) {
+  dmpt_status st = normalise(opts, o);
   if (st != DMPT_OK) return st;
-  if (!H0 || !U || !A || !chi || !scf) return fail(DMPT_ERR_ARG, "H0, U, A, chi and scf must not be NULL");
-  if (scf->max_iter < 1 || !(scf->mix > 0 && scf->mix <= 1) || !(scf->tol > 0))
-    return fail(DMPT_ERR_ARG, "scf options out of range");
-  return fail(DMPT_ERR_UNSUPPORTED, "dmpt_scf_response is not implemented in this build");
+  if (!scf) return fail(DMPT_ERR_ARG, "scf options are NULL");
+  if (scf->max_iter < 1 || scf->max_iter > DMPT_MAX_SCF)
+    return fail(DMPT_ERR_ARG, "scf max_iter out of range [1, %d]", DMPT_MAX_SCF);
+  if (!(scf->mix > 0 && scf->mix <= 1)) return fail(DMPT_ERR_ARG, "scf mix must be in (0, 1]");
+  if (!(scf->tol > 0)) return fail(DMPT_ERR_ARG, "scf tol must be > 0");
+  if (scf->mixer < DMPT_MIX_LINEAR || scf->mixer > DMPT_MIX_LEARNED)
+    return fail(DMPT_ERR_ARG, "unknown mixer %d", scf->mixer);
+  if (scf->mixer == DMPT_MIX_ANDERSON && (scf->anderson_depth < 1 || scf->anderson_depth > 16))
+    return fail(DMPT_ERR_ARG, "anderson_depth out of range [1, 16]");
+  if (scf->mixer == DMPT_MIX_LEARNED &&
+      (!scf->mlp_params || !mixer_sizes_ok(o->n, scf->mlp_window, scf->mlp_hidden, 1)))
+    return fail(DMPT_ERR_ARG, "the learned mixer needs mlp_params and a valid mlp_window / mlp_hidden");
+  if (scf->reserved != 0) return fail(DMPT_ERR_ARG, "scf reserved must be 0");
+  *o2 = *opts;
+  o2->sweep = DMPT_SWEEP_ADJOINT;
+  o2->spin = 1.0;
+  Opts oo;
+  normalise(o2, &oo);
+  Plan p;
+  make_plan(oo, 1, &p);
+  *run_bytes = p.total;
+  return DMPT_OK;
+}
+
+// Solve the k x k system (g + lambda I) x = b by Gaussian elimination with
+// partial pivoting (k <= 16).
+void small_solve(std::vector<double> g, std::vector<double> b, int k, std::vector<double>* x) {
+  double tr = 0.0;
+  for (int i = 0; i < k; ++i) tr += g[i * k + i];
+  const double lambda = 1e-12 * (tr > 0 ? tr / k : 1.0);
+  for (int i = 0; i < k; ++i) g[i * k + i] += lambda;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (std::fabs(g[r * k + c]) > std::fabs(g[piv * k + c])) piv = r;
+    if (piv != c) {
+      for (int j = 0; j < k; ++j) std::swap(g[c * k + j], g[piv * k + j]);
+      std::swap(b[c], b[piv]);
+    }
+    const double d = g[c * k + c];
+    if (d == 0.0) continue;
+    for (int r = c + 1; r < k; ++r) {
+      const double f = g[r * k + c] / d;
+      for (int j = c; j < k; ++j) g[r * k + j] -= f * g[c * k + j];
+      b[r] -= f * b[c];
+    }
+  }
+  x->assign(k, 0.0);
+  for (int c = k - 1; c >= 0; --c) {
+    double t = b[c];
+    for (int j = c + 1; j < k; ++j) t -= g[c * k + j] * (*x)[j];
+    (*x)[c] = g[c * k + c] != 0.0 ? t / g[c * k + c] : 0.0;
+  }
+}
+
+}  // namespace
+}  // namespace dmpt
+
+size_t dmpt_mixer_param_count(int32_t window, int32_t hidden) {
+  if (!mixer_sizes_ok(1, window, hidden, 1)) return 0;
+  return mixer_param_count(window, hidden);
+}
+
+size_t dmpt_mixer_workspace_bytes(int32_t n, int32_t window, int32_t hidden, int32_t batch) {
+  if (!mixer_sizes_ok(n, window, hidden, batch)) {
+    fail(DMPT_ERR_ARG, "mixer sizes out of range (n %d, window %d, hidden %d, batch %d)", n, window, hidden, batch);
+    return 0;
+  }
+  return mixer_ws(n, window, hidden, batch).total;
+}
+
+dmpt_status dmpt_mixer_init(float* master, uint16_t* params, int32_t window, int32_t hidden, uint64_t seed,
+                            void* stream) {
+  if (!master || !params) return fail(DMPT_ERR_ARG, "master and params must not be NULL");
+  if (!mixer_sizes_ok(1, window, hidden, 1)) return fail(DMPT_ERR_ARG, "mixer sizes out of range");
+  hipStream_t s = (hipStream_t)stream;
+  DMPT_HIP(mixer_init(master, params, window, hidden, seed, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_mixer_forward(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+                               const float* x, int32_t batch, float* y, void* stream, void* workspace,
+                               size_t workspace_bytes) {
+  if (!params || !U || !x || !y) return fail(DMPT_ERR_ARG, "params, U, x and y must not be NULL");
+  MixWS m;
+  dmpt_status st = mixer_check(n, window, hidden, batch, workspace, workspace_bytes, &m);
+  if (st != DMPT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  DMPT_HIP(mixer_forward(params, window, hidden, U, n, x, batch, y, (float*)(ws + m.scratch), s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+                                 const float* x, const float* t, int32_t batch, float* grad, double* loss,
+                                 void* stream, void* workspace, size_t workspace_bytes) {
+  if (!params || !U || !x || !t || !grad || !loss) return fail(DMPT_ERR_ARG, "NULL argument");
+  MixWS m;
+  dmpt_status st = mixer_check(n, window, hidden, batch, workspace, workspace_bytes, &m);
+  if (st != DMPT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  double* ld = (double*)(ws + m.loss);
+  DMPT_HIP(mixer_loss_grad(params, window, hidden, U, n, x, t, batch, (float*)(ws + m.scratch),
+                           (double*)(ws + m.part), grad, ld, 0, s));
+  DMPT_HIP(hipMemcpyAsync(loss, ld, sizeof(double), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, float* adam_v, int32_t window,
+                             int32_t hidden, const float* U, int32_t n, const float* x, const float* t,
+                             int32_t npairs, int32_t batch, int32_t steps, double lr, double* loss_history,
+                             void* stream, void* workspace, size_t workspace_bytes) {
+  if (!master || !params || !adam_m || !adam_v || !U || !x || !t) return fail(DMPT_ERR_ARG, "NULL argument");
+  if (npairs < batch || steps < 1 || steps > kMixerMaxSteps || !(lr > 0))
+    return fail(DMPT_ERR_ARG, "need npairs >= batch, 1 <= steps <= %d, lr > 0", kMixerMaxSteps);
+  MixWS m;
+  dmpt_status st = mixer_check(n, window, hidden, batch, workspace, workspace_bytes, &m);
+  if (st != DMPT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  double* ld = (double*)(ws + m.loss);
+  const size_t np = mixer_param_count(window, hidden);
+  for (int k = 1; k <= steps; ++k) {
+    size_t start = ((size_t)(k - 1) * batch) % (size_t)npairs;
+    if (start + batch > (size_t)npairs) start = (size_t)npairs - batch;
+    DMPT_HIP(mixer_loss_grad(params, window, hidden, U, n, x + start * n, t + start * n, batch,
+                             (float*)(ws + m.scratch), (double*)(ws + m.part), (float*)(ws + m.grad), ld, k - 1, s));
+    DMPT_HIP(mixer_adam(master, params, adam_m, adam_v, (const float*)(ws + m.grad), np, (float)lr, k, s));
+  }
+  if (loss_history) DMPT_HIP(hipMemcpyAsync(loss_history, ld, sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+size_t dmpt_scf_workspace_bytes(const dmpt_opts* opts, const dmpt_scf_opts* scf) {
+  Opts o;
+  dmpt_opts o2;
+  size_t run_bytes = 0;
+  if (scf_check(opts, scf, &o, &o2, &run_bytes) != DMPT_OK) return 0;
+  return scf_ws(run_bytes, o.n, scf->mixer == DMPT_MIX_ANDERSON ? scf->anderson_depth : 0, scf->mlp_window,
+                scf->mixer == DMPT_MIX_LEARNED ? scf->mlp_hidden : 0).total;
+}
+
+dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
+                              const dmpt_scf_opts* scf, const dmpt_opts* opts, dmpt_info* info,
+                              dmpt_scf_info* sinfo) {
+  Opts o;
+  dmpt_opts o2;
+  size_t run_bytes = 0;
+  dmpt_status st = scf_check(opts, scf, &o, &o2, &run_bytes);
+  if (st != DMPT_OK) return st;
+  if (!H0 || !U || !A || !chi) return fail(DMPT_ERR_ARG, "H0, U, A and chi must not be NULL");
+  const int n = o.n;
+  const int depth = scf->mixer == DMPT_MIX_ANDERSON ? scf->anderson_depth : 0;
+  const ScfWS w = scf_ws(run_bytes, n, depth, scf->mlp_window, scf->mixer == DMPT_MIX_LEARNED ? scf->mlp_hidden : 0);
+  if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
+  if (o.ws_bytes < w.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, w.total);
+  if (sinfo) std::memset(sinfo, 0, sizeof(*sinfo));
+  hipStream_t s = o.stream;
+  char* ws = o.ws;
+  o2.workspace = ws;
+  o2.workspace_bytes = w.run_bytes;
+  float* ca = (float*)(ws + w.ca);
+  float* cw[2] = {(float*)(ws + w.cw[0]), (float*)(ws + w.cw[1])};
+  float* wmat = (float*)(ws + w.wmat);
+  double* da = (double*)(ws + w.da);
+  double *v = (double*)(ws + w.v), *f = (double*)(ws + w.f), *r = (double*)(ws + w.r);
+  double *vt = (double*)(ws + w.vt), *ft = (double*)(ws + w.ft), *rt = (double*)(ws + w.rt);
+  float* xf = (float*)(ws + w.x);
+  float* yf = (float*)(ws + w.y);
+  const void** tab = (const void**)(ws + w.tab);
+  double* coef = (double*)(ws + w.coef);
+  double* dot = (double*)(ws + w.dot);
+  const double spin = o.spin;
+
+  // chi'_A = L[A]: the SP2 recursion of H0 (X_n kept) and one backward sweep
+  st = run(H0, A, 1, ca, nullptr, nullptr, &o2, info, false);
+  if (st != DMPT_OK) return st;
+  DMPT_HIP(scf_get_diag(ca, n, da, s));
+  DMPT_HIP(hipMemsetAsync(v, 0, (size_t)n * 8, s));
+  DMPT_HIP(hipMemcpyAsync(f, da, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+
+  // host-side helpers: norms of r and f; F at a trial state
+  std::vector<const void*> htab(2 * (2 + 2 * 16));
+  auto norms = [&](const double* rr, const double* ff, double* rn, double* fn) -> dmpt_status {
+    htab[0] = rr; htab[1] = ff; htab[2] = rr; htab[3] = ff;
+    DMPT_HIP(hipMemcpyAsync(tab, htab.data(), 4 * sizeof(void*), hipMemcpyHostToDevice, s));
+    DMPT_HIP(scf_dots((const double* const*)tab, (const double* const*)(tab + 2), 2, n, dot, s));
+    double h2[2];
+    DMPT_HIP(hipMemcpyAsync(h2, dot, sizeof(h2), hipMemcpyDeviceToHost, s));
+    DMPT_HIP(hipStreamSynchronize(s));
+    *rn = std::sqrt(h2[0]);
+    *fn = std::sqrt(h2[1]);
+    return DMPT_OK;
+  };
+  int cur = 0;   // cw[cur] belongs to the accepted state (unused while v = 0)
+  bool have_cw = false;
+  auto evaluate = [&](const double* vv, double* ff, float* cwout) -> dmpt_status {
+    DMPT_HIP(scf_set_diag(wmat, n, U, vv, spin, s));
+    dmpt_status e = run(H0, wmat, 1, cwout, nullptr, nullptr, &o2, nullptr, true);
+    if (e != DMPT_OK) return e;
+    DMPT_HIP(scf_fvec(ff, da, cwout, n, s));
+    return DMPT_OK;
+  };
+
+  int evals = 1, rejected = 0, converged = 0, hist = 0, hhead = 0, accepted = 0;
+  double rn = 0, fn = 0;
+  DMPT_HIP(scf_residual(r, f, v, n, scf->record_v, scf->record_r, s));
+  st = norms(r, f, &rn, &fn);
+  if (st != DMPT_OK) return st;
+  double res = fn > 0 ? rn / fn : 0.0;
+  if (sinfo) sinfo->residual[0] = res;
+  converged = res <= scf->tol;
+  while (!converged && evals < scf->max_iter) {
+    // proposal
+    bool special = false;
+    if (scf->mixer == DMPT_MIX_LEARNED && rn > 0) {
+      const double sq = std::sqrt((double)n);
+      DMPT_HIP(scf_to_float(xf, r, sq / rn, n, s));
+      DMPT_HIP(mixer_forward(scf->mlp_params, scf->mlp_window, scf->mlp_hidden, U, n, xf, 1, yf,
+                             (float*)(ws + w.mlp), s));
+      DMPT_HIP(scf_step(vt, v, r, scf->mix, yf, rn / sq, n, s));
+      special = true;
+    } else if (scf->mixer == DMPT_MIX_ANDERSON && hist > 0) {
+      // gamma = argmin || r - sum_j gamma_j dR_j ||; v' = v + mix r - sum_j gamma_j (dV_j + mix dR_j)
+      const int k = hist;
+      std::vector<std::pair<int, int>> pairs;
+      for (int i = 0; i < k; ++i)
+        for (int j = i; j < k; ++j) pairs.emplace_back(i, j);
+      // the Gram matrix dR^T dR and dR^T r, 16 dot products per pass
+      std::vector<double> g(k * k), b(k);
+      auto dr = [&](int i) { return (const double*)(ws + w.dr) + (size_t)i * n; };
+      for (size_t base = 0; base < pairs.size() + k; base += 16) {
+        std::vector<const void*> xs, ys;
+        for (size_t e = base; e < std::min(pairs.size() + k, base + 16); ++e) {
+          if (e < pairs.size()) {
+            xs.push_back(dr(pairs[e].first));
+            ys.push_back(dr(pairs[e].second));
+          } else {
+            xs.push_back(dr((int)(e - pairs.size())));
+            ys.push_back(r);
+          }
+        }
+        const int cnt = (int)xs.size();
+        std::vector<const void*> both(xs);
+        both.insert(both.end(), ys.begin(), ys.end());
+        DMPT_HIP(hipMemcpyAsync(tab, both.data(), both.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+        DMPT_HIP(scf_dots((const double* const*)tab, (const double* const*)(tab + cnt), cnt, n, dot, s));
+        std::vector<double> out(cnt);
+        DMPT_HIP(hipMemcpyAsync(out.data(), dot, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+        DMPT_HIP(hipStreamSynchronize(s));
+        for (int e = 0; e < cnt; ++e) {
+          const size_t idx = base + e;
+          if (idx < pairs.size()) {
+            g[pairs[idx].first * k + pairs[idx].second] = out[e];
+            g[pairs[idx].second * k + pairs[idx].first] = out[e];
+          } else {
+            b[idx - pairs.size()] = out[e];
+          }
+        }
+      }
+      std::vector<double> gamma;
+      small_solve(g, b, k, &gamma);
+      std::vector<const void*> vecs = {v, r};
+      std::vector<double> cs = {1.0, scf->mix};
+      for (int j = 0; j < k; ++j) {
+        vecs.push_back((const double*)(ws + w.dv) + (size_t)j * n);
+        cs.push_back(-gamma[j]);
+        vecs.push_back(dr(j));
+        cs.push_back(-scf->mix * gamma[j]);
+      }
+      DMPT_HIP(hipMemcpyAsync(tab, vecs.data(), vecs.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+      DMPT_HIP(hipMemcpyAsync(coef, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      DMPT_HIP(scf_lincomb(vt, (const double* const*)tab, coef, (int)vecs.size(), n, s));
+      DMPT_HIP(hipStreamSynchronize(s));
+      special = true;
+    } else {
+      DMPT_HIP(scf_step(vt, v, r, scf->mix, nullptr, 0.0, n, s));
+    }
+    // evaluate the proposal
+    st = evaluate(vt, ft, cw[cur ^ 1]);
+    if (st != DMPT_OK) return st;
+    ++evals;
+    DMPT_HIP(scf_residual(rt, ft, vt, n, nullptr, nullptr, s));
+    double rn2 = 0, fn2 = 0;
+    st = norms(rt, ft, &rn2, &fn2);
+    if (st != DMPT_OK) return st;
+    if (special && rn2 > rn && evals < scf->max_iter) {
+      // the judge: fall back to the linear step from the current state
+      ++rejected;
+      DMPT_HIP(scf_step(vt, v, r, scf->mix, nullptr, 0.0, n, s));
+      st = evaluate(vt, ft, cw[cur ^ 1]);
+      if (st != DMPT_OK) return st;
+      ++evals;
+      DMPT_HIP(scf_residual(rt, ft, vt, n, nullptr, nullptr, s));
+      st = norms(rt, ft, &rn2, &fn2);
+      if (st != DMPT_OK) return st;
+    }
+    // accept: history (Anderson), swap state
+    if (depth > 0) {
+      double* dvj = (double*)(ws + w.dv) + (size_t)hhead * n;
+      double* drj = (double*)(ws + w.dr) + (size_t)hhead * n;
+      std::vector<const void*> vecs = {vt, v, rt, r};
+      DMPT_HIP(hipMemcpyAsync(tab, vecs.data(), 4 * sizeof(void*), hipMemcpyHostToDevice, s));
+      const double cs[4] = {1.0, -1.0, 1.0, -1.0};
+      DMPT_HIP(hipMemcpyAsync(coef, cs, sizeof(cs), hipMemcpyHostToDevice, s));
+      DMPT_HIP(scf_lincomb(dvj, (const double* const*)tab, coef, 2, n, s));
+      DMPT_HIP(scf_lincomb(drj, (const double* const*)(tab + 2), coef + 2, 2, n, s));
+      DMPT_HIP(hipStreamSynchronize(s));
+      hhead = (hhead + 1) % depth;
+      hist = std::min(hist + 1, depth);
+    }
+    std::swap(v, vt);
+    std::swap(f, ft);
+    std::swap(r, rt);
+    cur ^= 1;
+    have_cw = true;
+    rn = rn2;
+    fn = fn2;
+    res = fn > 0 ? rn / fn : 0.0;
+    ++accepted;   // accepted states are numbered 0 (v = 0), 1, 2, ... (<= evals - 1 < max_iter)
+    if (scf->record_v || scf->record_r) {
+      const size_t slot = (size_t)accepted * n;
+      DMPT_HIP(scf_residual(rt, f, v, n, scf->record_v ? scf->record_v + slot : nullptr,
+                            scf->record_r ? scf->record_r + slot : nullptr, s));
+    }
+    if (sinfo) sinfo->residual[accepted] = res;
+    converged = res <= scf->tol;
+  }
+  // chi = s (L[A] + L[diag(U s v)]) at the last accepted state
+  DMPT_HIP(scf_combine(chi, ca, have_cw ? cw[cur] : nullptr, spin, (size_t)n * n, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  if (sinfo) {
+    sinfo->iters = evals;
+    sinfo->converged = converged;
+    sinfo->rejected = rejected;
+    sinfo->states = accepted + 1;
+  }
+  if (!converged) return fail(DMPT_ERR_NOT_CONVERGED, "self-consistent loop did not converge in %d evaluations", evals);
+  return DMPT_OK;
 }
 
 int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev2, int32_t steps, int32_t n,

@@ -1,0 +1,115 @@
+"""The learned mixer of the self-consistent response loop (Eq. CP_SCF).
+
+A two-layer network of hidden width h with BF16 weights, applied site by site
+(site i sees the residual in a window of 2w + 1 sites and its U_i), stands
+in as the preconditioner of the loop: from the state v and residual r it
+proposes v + mix r + (||r|| / sqrt(n)) net(sqrt(n) r / ||r||).  It is trained
+on pairs the method itself produces: linear-mixing runs record (v_k, r_k);
+with their converged state v* the target of x = sqrt(n) r_k / ||r_k|| is
+t = sqrt(n) (v* - v_k - mix r_k) / ||r_k||, the exact correction to the
+linear step.  Forward, loss gradient and Adam run in the library's kernels
+(dmpt_mixer_*); this module owns the buffers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from ._lib import check, load
+
+
+class Mixer:
+    def __init__(self, U, window: int = 32, hidden: int = 256, seed: int = 0):
+        """U: (n,) float32 device tensor of on-site interactions (a per-site input)."""
+        lib = load()
+        self.U = U.contiguous().float()
+        self.n, self.window, self.hidden = U.shape[0], window, hidden
+        device = U.device
+        count = int(lib.dmpt_mixer_param_count(window, hidden))
+        if count == 0:
+            check(1)
+        self.count = count
+        self.master = torch.empty(count, dtype=torch.float32, device=device)
+        self.params = torch.empty(count, dtype=torch.int16, device=device)   # BF16 bit patterns
+        self.adam_m = torch.zeros(count, dtype=torch.float32, device=device)
+        self.adam_v = torch.zeros(count, dtype=torch.float32, device=device)
+        self.steps = 0
+        check(lib.dmpt_mixer_init(C.c_void_p(self.master.data_ptr()), C.c_void_p(self.params.data_ptr()),
+                                  window, hidden, seed, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def _ws(self, batch):
+        nbytes = int(load().dmpt_mixer_workspace_bytes(self.n, self.window, self.hidden, batch))
+        if nbytes == 0:
+            check(1)
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.master.device)
+
+    def params_float(self) -> torch.Tensor:
+        """The BF16 parameters widened to FP32 (exact)."""
+        return (self.params.to(torch.int32) << 16).view(torch.float32)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.contiguous().float()
+        b = x.shape[0]
+        y = torch.empty_like(x)
+        ws = self._ws(b)
+        check(load().dmpt_mixer_forward(C.c_void_p(self.params.data_ptr()), self.window, self.hidden,
+                                        C.c_void_p(self.U.data_ptr()), self.n,
+                                        C.c_void_p(x.data_ptr()), b, C.c_void_p(y.data_ptr()),
+                                        C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                        C.c_void_p(ws.data_ptr()), ws.numel()))
+        return y
+
+    def loss_grad(self, x: torch.Tensor, t: torch.Tensor):
+        x, t = x.contiguous().float(), t.contiguous().float()
+        b = x.shape[0]
+        grad = torch.empty(self.count, dtype=torch.float32, device=x.device)
+        loss = C.c_double()
+        ws = self._ws(b)
+        check(load().dmpt_mixer_loss_grad(C.c_void_p(self.params.data_ptr()), self.window, self.hidden,
+                                          C.c_void_p(self.U.data_ptr()), self.n,
+                                          C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), b,
+                                          C.c_void_p(grad.data_ptr()), C.byref(loss),
+                                          C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                          C.c_void_p(ws.data_ptr()), ws.numel()))
+        return loss.value, grad
+
+    def train(self, x: torch.Tensor, t: torch.Tensor, steps: int, batch: int = 64, lr: float = 1e-3):
+        """Adam steps over minibatches of consecutive pairs; returns the loss per step.
+        The step counter continues across calls only through the moment buffers
+        (each call restarts the bias correction at 1)."""
+        x, t = x.contiguous().float(), t.contiguous().float()
+        npairs = x.shape[0]
+        hist = (C.c_double * steps)()
+        ws = self._ws(batch)
+        check(load().dmpt_mixer_train(C.c_void_p(self.master.data_ptr()), C.c_void_p(self.params.data_ptr()),
+                                      C.c_void_p(self.adam_m.data_ptr()), C.c_void_p(self.adam_v.data_ptr()),
+                                      self.window, self.hidden, C.c_void_p(self.U.data_ptr()), self.n,
+                                      C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                      npairs, batch, steps, lr, hist,
+                                      C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                      C.c_void_p(ws.data_ptr()), ws.numel()))
+        self.steps += steps
+        return list(hist)
+
+
+def training_pairs(H0, U, observables, nocc: int, *, mix: float = 0.3, tol: float = 1e-6, max_iter: int = 400,
+                   min_residual: float = 1e-5, **kw):
+    """Pairs (x, t) from linear-mixing runs of dmpt_scf_response, one run per
+    observable: x_k = sqrt(n) r_k / ||r_k||, t_k = sqrt(n) (v* - v_k - mix r_k) / ||r_k||,
+    v* the run's last state.  States whose relative residual is below
+    min_residual are left out: their targets are dominated by the rounding
+    noise of v* (the FP32 loop's residual floor is ~1e-7)."""
+    from . import scf_response
+    xs, ts = [], []
+    for a in observables:
+        _, sinfo, _, v, r = scf_response(H0, U, a, nocc, mixer="linear", mix=mix, tol=tol, max_iter=max_iter,
+                                         record=True, **kw)
+        vstar = v[-1:]
+        res = torch.tensor(sinfo["residual"][:-1], device=v.device)
+        keep = res >= min_residual
+        rk, vk = r[:-1][keep], v[:-1][keep]
+        rn = torch.linalg.norm(rk, dim=1, keepdim=True) / float(rk.shape[1]) ** 0.5
+        xs.append(rk / rn)
+        ts.append((vstar - vk - mix * rk) / rn)
+    return torch.cat(xs), torch.cat(ts)

@@ -165,13 +165,50 @@ def test_response_validation(lib):
     assert lib.dmpt_response_workspace_bytes(16, 32, 8192) > lib.dmpt_response_workspace_bytes(8, 32, 8192)
 
 
-def test_scf_response_unsupported(lib):
-    from paper_2409_17033_amd._lib import SCFOpts
+def test_scf_response_validation(lib):
+    """Argument checks of dmpt_scf_response (none reaches the device)."""
+    from paper_2409_17033_amd._lib import SCFInfo, SCFOpts
     o = _opts(lib)
     s = SCFOpts(max_iter=10, mix=0.3, tol=1e-6)
-    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(s), C.byref(o), None) == 7
-    s.mix = 0.0
-    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(s), C.byref(o), None) == 1
+    si = SCFInfo()
+    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(s), C.byref(o), None, C.byref(si)) == 6
+    assert lib.dmpt_scf_response(FAKE, None, FAKE, FAKE, C.byref(s), C.byref(o), None, None) == 1
+    for field, value in (("mix", 0.0), ("mix", 1.5), ("tol", 0.0), ("max_iter", 0), ("max_iter", 5000),
+                         ("mixer", 3)):
+        bad = SCFOpts(max_iter=10, mix=0.3, tol=1e-6)
+        setattr(bad, field, value)
+        assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(bad), C.byref(o), None, None) == 1, field
+        assert lib.dmpt_scf_workspace_bytes(C.byref(o), C.byref(bad)) == 0
+    andersen = SCFOpts(max_iter=10, mixer=1, mix=0.3, tol=1e-6, anderson_depth=0)
+    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(andersen), C.byref(o), None, None) == 1
+    learned = SCFOpts(max_iter=10, mixer=2, mix=0.3, tol=1e-6, mlp_hidden=16, mlp_window=4)   # no parameters
+    assert lib.dmpt_scf_response(FAKE, FAKE, FAKE, FAKE, C.byref(learned), C.byref(o), None, None) == 1
+
+
+def test_scf_workspace_covers_the_adjoint_solve(lib):
+    from paper_2409_17033_amd._lib import SCFOpts
+    o = _opts(lib, 1000, 500)
+    s = SCFOpts(max_iter=10, mix=0.3, tol=1e-6)
+    o.sweep = 1
+    adj = lib.dmpt_workspace_bytes(C.byref(o), 1)
+    o.sweep = 0
+    ws = lib.dmpt_scf_workspace_bytes(C.byref(o), C.byref(s))
+    assert ws >= adj + 4 * 1000 * 1000 * 4       # adjoint solve + chi_A, two chi_W, diag(U s v)
+    s.mixer, s.anderson_depth = 1, 8
+    assert lib.dmpt_scf_workspace_bytes(C.byref(o), C.byref(s)) >= ws + 2 * 8 * 1000 * 8
+
+
+def test_mixer_sizes(lib):
+    k = 2 * 32 + 2
+    assert lib.dmpt_mixer_param_count(32, 256) == 256 * k + 2 * 256 + 1
+    assert lib.dmpt_mixer_param_count(-1, 256) == 0
+    assert lib.dmpt_mixer_workspace_bytes(1024, 32, 256, 64) > 64 * 1024 * (k + 2 * 256) * 4
+    assert lib.dmpt_mixer_workspace_bytes(1024, 32, 0, 64) == 0
+    out = (C.c_double * 1)()
+    assert lib.dmpt_mixer_forward(FAKE, 2, 4, FAKE, 8, FAKE, 2, FAKE, None, None, 0) == 6
+    assert lib.dmpt_mixer_forward(None, 2, 4, FAKE, 8, FAKE, 2, FAKE, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_mixer_train(FAKE, FAKE, FAKE, FAKE, 2, 4, FAKE, 8, FAKE, FAKE, 1, 2, 10, 1e-3, out, None, FAKE,
+                                1 << 20) == 1     # npairs < batch
 
 
 def test_status_strings(lib):

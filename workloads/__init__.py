@@ -162,6 +162,24 @@ def banded_gapped(n: int = 4096, nocc: int | None = None, gap: float = 0.1,
     return wl
 
 
+def scf_system(n: int = 1024, cfg: int = 4, ntrain: int = 40):
+    """Self-consistent response case (config 4): banded gapped H0 (the config-2
+    recipe at size n), on-site interactions U_i ~ U(0.5, 1.5), the test
+    observable A = site position, an external field H1 = diag(N(0, 0.01^2)),
+    and `ntrain` random symmetric Frobenius-normalised observables whose
+    linear-mixing runs provide the mixer's training pairs.
+    Returns (workload, U (float32), training observables (float32))."""
+    wl = banded_gapped(n, cfg=cfg, npert=1, cache=False)
+    rng = rng_for(cfg, n, 1)
+    u = rng.uniform(0.5, 1.5, size=n).astype(np.float32)
+    h1 = np.diag(rng.normal(0.0, 0.01, size=n))[None]
+    train = np.stack([_as32(frobenius_normalised(random_symmetric(rng, n))) for _ in range(ntrain)]) \
+        if ntrain else np.zeros((0, n, n), np.float32)
+    wl = Workload("scf_system", n, wl.nocc, wl.H, wl.A, np.stack([_as32(x) for x in h1]),
+                  {"cfg": cfg, "half_bandwidth": 64})
+    return wl, u, train
+
+
 def known_spectrum(n: int, nocc: int, gap: float = 0.3, seed: int = 0,
                    width: float = 2.0) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     """H = Q diag(w) Q^T with a chosen ascending spectrum and a random orthogonal Q.
