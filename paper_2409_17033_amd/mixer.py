@@ -93,23 +93,79 @@ class Mixer:
         return list(hist)
 
 
+def _pairs(v, r, residual, vstar, mix: float, min_residual: float, drop_last: bool):
+    """(x, t) of the recorded states whose relative residual is at least
+    min_residual: x = sqrt(n) r / ||r||, t = sqrt(n) (v* - v - mix r) / ||r||."""
+    k = v.shape[0]
+    keep = torch.tensor([residual[i] >= min_residual and not (drop_last and i == k - 1) for i in range(k)],
+                        device=v.device)
+    rk, vk = r[keep], v[keep]
+    rn = torch.linalg.norm(rk, dim=1, keepdim=True) / float(r.shape[1]) ** 0.5
+    return rk / rn, (vstar - vk - mix * rk) / rn
+
+
 def training_pairs(H0, U, observables, nocc: int, *, mix: float = 0.3, tol: float = 1e-6, max_iter: int = 400,
-                   min_residual: float = 1e-5, **kw):
+                   min_residual: float = 1e-5, return_fixed_points: bool = False, **kw):
     """Pairs (x, t) from linear-mixing runs of dmpt_scf_response, one run per
     observable: x_k = sqrt(n) r_k / ||r_k||, t_k = sqrt(n) (v* - v_k - mix r_k) / ||r_k||,
     v* the run's last state.  States whose relative residual is below
     min_residual are left out: their targets are dominated by the rounding
     noise of v* (the FP32 loop's residual floor is ~1e-7)."""
     from . import scf_response
-    xs, ts = [], []
+    xs, ts, vstars = [], [], []
     for a in observables:
         _, sinfo, _, v, r = scf_response(H0, U, a, nocc, mixer="linear", mix=mix, tol=tol, max_iter=max_iter,
                                          record=True, **kw)
-        vstar = v[-1:]
-        res = torch.tensor(sinfo["residual"][:-1], device=v.device)
-        keep = res >= min_residual
-        rk, vk = r[:-1][keep], v[:-1][keep]
-        rn = torch.linalg.norm(rk, dim=1, keepdim=True) / float(rk.shape[1]) ** 0.5
-        xs.append(rk / rn)
-        ts.append((vstar - vk - mix * rk) / rn)
-    return torch.cat(xs), torch.cat(ts)
+        vstar = v[-1:].clone()
+        x, t = _pairs(v, r, sinfo["residual"], vstar, mix, min_residual, drop_last=True)
+        xs.append(x)
+        ts.append(t)
+        vstars.append(vstar)
+    out = (torch.cat(xs), torch.cat(ts))
+    return out + (vstars,) if return_fixed_points else out
+
+
+def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int = 256, rounds: int = 2,
+                steps: int = 6000, batch: int = 64, lr: float = 1e-3, mix: float = 0.3, tol: float = 1e-6,
+                max_iter: int = 400, min_residual: float = 1e-5, seed: int = 11, **kw):
+    """Train a mixer for the loop of (H0, U) on the method's own pairs.
+
+    Round 0 trains on the states of linear-mixing runs (training_pairs).  A
+    network trained only there meets, once it is used, residuals that its own
+    earlier steps left behind, which linear mixing never produces; so each
+    further round runs the learned loop on the training observables, labels
+    every state it visits with the exact correction toward that observable's
+    fixed point v* (from the linear run), adds those pairs to the set and
+    trains a fresh network on the union (data aggregation; Ross, Gordon &
+    Bagnell, 2011).  Every network is scored by its mean number of loop
+    evaluations over the training observables and the best one is returned,
+    with a report {rounds: [(pairs, loss, mean evaluations)], chosen: index}.
+    """
+    from . import scf_response
+    x, t, vstars = training_pairs(H0, U, observables, nocc, mix=mix, tol=tol, max_iter=max_iter,
+                                  min_residual=min_residual, return_fixed_points=True, **kw)
+    gen = torch.Generator().manual_seed(seed)
+    report, best = {"rounds": []}, None
+    for rnd in range(rounds + 1):
+        net = Mixer(U, window=window, hidden=hidden, seed=seed + rnd)
+        hist = net.train(x, t, steps=steps, batch=batch, lr=lr)
+        loss = sum(hist[-100:]) / len(hist[-100:])
+        xs, ts, evals = [x], [t], []
+        for a, vstar in zip(observables, vstars):
+            _, sinfo, _, v, r = scf_response(H0, U, a, nocc, mixer="learned", net=net, mix=mix, tol=tol,
+                                             max_iter=max_iter, record=True, raise_on_error=False, **kw)
+            evals.append(sinfo["iters"])
+            if rnd < rounds:
+                xn, tn = _pairs(v, r, sinfo["residual"], vstar, mix, min_residual, drop_last=False)
+                xs.append(xn)
+                ts.append(tn)
+        score = sum(evals) / len(evals)
+        report["rounds"].append((int(x.shape[0]), loss, score))
+        if best is None or score < best[1]:
+            best = (net, score, rnd)
+        if rnd < rounds:
+            x, t = torch.cat(xs), torch.cat(ts)
+            perm = torch.randperm(x.shape[0], generator=gen).to(x.device)
+            x, t = x[perm].contiguous(), t[perm].contiguous()
+    report["chosen"] = best[2]
+    return best[0], report
