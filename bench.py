@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-χ (ms) + MFMA TFLOP/s at N=8192, split-BF16 vs FP32, at stated error"
 PEAK = {"bf16": 2516.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X)
-PRODUCTS = {"split3_bf16": 6, "split3x_bf16": 4, "split_bf16": 3, "fp32": 1, "bf16": 1}   # MFMA products per FP32-equivalent product (split3x: 6 for X^2, 3 for YX + XY)
+PRODUCTS = {"split3_bf16": 6, "split3x_bf16": 4, "split_bf16": 3, "split_fp16": 3, "fp32": 1, "bf16": 1}   # MFMA products per FP32-equivalent product (split3x: 6 for X^2, 3 for YX + XY)
 
 
 def log(msg):

@@ -67,11 +67,19 @@ typedef enum dmpt_precision {
   DMPT_SPLIT3_BF16 = 2, /* three BF16 terms hi+mid+lo (FP32-equivalent operands); the six
                            products of order >= 2^-16 (hh, hm, mh, hl, lh, mm) are kept */
   DMPT_BF16 = 3,        /* one BF16 term (plain BF16 operands), FP32 accumulate */
-  DMPT_SPLIT3X_BF16 = 4 /* three BF16 terms stored; the SP2 products X_n^2 keep the six split-3
+  DMPT_SPLIT3X_BF16 = 4,/* three BF16 terms stored; the SP2 products X_n^2 keep the six split-3
                            products, the sweep products Y_n X_n + X_n Y_n the two-term ones
                            (hh + hm + mh; mid is the two-term lo).  The SP2 products set the
                            accuracy of D and, through it, of chi; the sweep products tolerate
                            the two-term split. */
+  DMPT_SPLIT_FP16 = 5   /* Eq. doubleHalf with FP16 terms (the paper's own double-half split) on
+                           power-of-two scaled operands: x 2^s = hi + lo, hi = RNE_fp16(x 2^s),
+                           lo = RNE_fp16(x 2^s - hi); products hi*hi + hi*lo + lo*hi, FP32
+                           accumulate, result times 2^-(s_a + s_b).  X_n is scaled by 2^14
+                           (its entries lie in [-1, 1]); Y_n by the power of two that keeps
+                           4.5 ||Y_{n-1}||_F below 2^15, a bound on every entry of Y_n.
+                           Eleven-bit terms make the two-term split as accurate as FP32 at
+                           the cost of DMPT_SPLIT_BF16. */
 } dmpt_precision;
 
 typedef enum dmpt_bounds_mode {

@@ -24,7 +24,7 @@ STATUS = {
 }
 
 ABI_VERSION = 2   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
-PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4}
+PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4, "split_fp16": 5}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
 

@@ -54,7 +54,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (!o) return fail(DMPT_ERR_ARG, "opts is NULL");
   if (o->n < 1 || o->n > 65536) return fail(DMPT_ERR_ARG, "n = %d out of range [1, 65536]", o->n);
   if (o->nocc < 0 || o->nocc > o->n) return fail(DMPT_ERR_ARG, "nocc = %d out of range [0, n]", o->nocc);
-  if (o->precision < 0 || o->precision > DMPT_SPLIT3X_BF16) return fail(DMPT_ERR_ARG, "unknown precision %d", o->precision);
+  if (o->precision < 0 || o->precision > DMPT_SPLIT_FP16) return fail(DMPT_ERR_ARG, "unknown precision %d", o->precision);
   if (o->bounds < 0 || o->bounds > DMPT_BOUNDS_GIVEN) return fail(DMPT_ERR_ARG, "unknown bounds mode %d", o->bounds);
   if (o->bounds == DMPT_BOUNDS_GIVEN && !(std::isfinite(o->emin) && std::isfinite(o->emax) && o->emax > o->emin))
     return fail(DMPT_ERR_ARG, "given bounds need finite emin < emax");
@@ -73,7 +73,8 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   r->prec = o->precision == DMPT_FP32 ? kFP32
           : o->precision == DMPT_SPLIT_BF16 ? kSplit2
           : o->precision == DMPT_SPLIT3_BF16 ? kSplit3
-          : o->precision == DMPT_SPLIT3X_BF16 ? kSplit32 : kBF16;
+          : o->precision == DMPT_SPLIT3X_BF16 ? kSplit32
+          : o->precision == DMPT_SPLIT_FP16 ? kSplitH : kBF16;
   r->bounds = o->bounds;
   r->lanczos_steps = o->lanczos_steps ? o->lanczos_steps : 48;
   r->max_iter = o->max_iter ? o->max_iter : 100;
@@ -97,7 +98,7 @@ struct Plan {
   int n, n_pad, nobs, prec, tile, ntile, nb64, nparts_step;
   int xslots;
   int ckpt, nckpt;                 // adjoint checkpoint interval (0: every X_n kept) and slot count
-  size_t mat_f32, mat_op;          // bytes per matrix
+  size_t mat_f32, mat_op, mat_meta; // bytes per matrix: master, operand copy, metadata
   size_t off_ctl, off_part[2], off_jobs, off_jobs_proj, off_gersh, off_lz, off_a0, off_x, off_y;
   size_t x_slot_bytes, y_obs_bytes, y_slot_bytes;
   size_t total;
@@ -109,7 +110,7 @@ struct Plan {
 // (F stages x MFMAs per stage per block) against the outer one (stages / F)
 // gives F ~ sqrt(stages / chain).
 int flush_interval(int prec, int n_pad) {
-  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : (prec == kSplit2 || prec == kSplit32) ? 3 : 2;
+  const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : (prec == kSplit2 || prec == kSplit32 || prec == kSplitH) ? 3 : 2;
   const int stages = n_pad / stage_k(prec);
   const double f = std::sqrt((double)stages / chain) / 4.0;
   return std::max(1, (int)std::lround(f));
@@ -135,6 +136,7 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   const size_t np2 = (size_t)p->n_pad * p->n_pad;
   p->mat_f32 = np2 * 4;
   p->mat_op = o.prec == kFP32 ? 0 : np2 * operand_bytes(o.prec);
+  p->mat_meta = meta_bytes(std::max(p->nb64 * p->nb64, p->nparts_step));
   p->lz_steps = o.lanczos_steps;
   const int ut = p->nparts_step;                       // step tiles covering the upper triangle
   p->njobs_max = ut * (1 + std::max(nobs, 0));
@@ -149,7 +151,7 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   p->off_gersh = off; off = align_up(off + (size_t)gershgorin_blocks(o.n) * sizeof(double2));
   p->off_lz = off; off = align_up(off + (size_t)(3 * o.n + 2 * (p->lz_steps + 2)) * sizeof(double));
   p->off_a0 = off; off = align_up(off + (size_t)kOutBlocks * std::max(nobs, 1) * sizeof(double));
-  p->x_slot_bytes = align_up(p->mat_f32) + align_up(p->mat_op);
+  p->x_slot_bytes = align_up(p->mat_f32) + align_up(p->mat_op) + align_up(p->mat_meta);
   p->off_x = off; off = align_up(off + p->x_slot_bytes * p->xslots);
   p->y_obs_bytes = p->x_slot_bytes;
   p->y_slot_bytes = p->y_obs_bytes * std::max(nobs, 0);
@@ -164,6 +166,7 @@ MatRef x_ref(const Plan& p, char* ws, int slot) {
   m.op = p.prec == kFP32 ? (void*)base : (void*)(base + align_up(p.mat_f32));
   m.stride_f32 = 0;
   m.stride_op = 0;
+  m.meta = base + align_up(p.mat_f32) + align_up(p.mat_op);
   return m;
 }
 
@@ -174,6 +177,7 @@ MatRef y_ref(const Plan& p, char* ws, int slot) {
   m.op = p.prec == kFP32 ? (void*)base : (void*)(base + align_up(p.mat_f32));
   m.stride_f32 = p.y_obs_bytes / 4;
   m.stride_op = p.y_obs_bytes;
+  m.meta = base + align_up(p.mat_f32) + align_up(p.mat_op);
   return m;
 }
 
@@ -523,9 +527,12 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   };
   Part* part[2] = {(Part*)(ws + p.off_part[0]), (Part*)(ws + p.off_part[1])};
   // X_1 (and Y_1 = beta A for the forward sweep) into slot of step 1
-  if (!reuse_x)
+  if (!reuse_x) {
     DMPT_HIP(launch_init(p.prec, p.tile, H, A, o.n, p.n_pad, adjoint ? 0 : nobs, nullptr, 0,
                          x_ref(p, ws, xslot(1)), y_ref(p, ws, 1), 0.0, part[1], ctl, s));
+    // FP16 split: the Y copies are written once their norms are known
+    if (p.prec == kSplitH && !adjoint && nobs > 0) DMPT_HIP(launch_resplit(p.prec, y_ref(p, ws, 1), p.n_pad, nobs, s));
+  }
   const int mb1 = prof.mark();
   std::vector<std::pair<int, int>> step_marks;
 
@@ -596,6 +603,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // Eq. DM2: Y_M = A; for n = M..1, Y_{n-1} from Y_n with X_n, sigma_n; chi = beta Y_0.
     DMPT_HIP(launch_init(p.prec, p.tile, nullptr, A, o.n, p.n_pad, -nobs, nullptr, 0,
                          x_ref(p, ws, 0), y_ref(p, ws, 0), 1.0, nullptr, ctl, s));
+    if (p.prec == kSplitH) DMPT_HIP(launch_resplit(p.prec, y_ref(p, ws, 0), p.n_pad, nobs, s));
     const std::vector<uint32_t> zjobs = build_jobs(p.n_pad, nobs, false);
     uint32_t* d_zjobs = d_jobs + p.nparts_step;
     DMPT_HIP(hipMemcpyAsync(d_zjobs, zjobs.data(), zjobs.size() * 4, hipMemcpyHostToDevice, s));

@@ -18,11 +18,23 @@ enum Prec : int {
   kBF16 = 3,    // plain BF16 row-major
   kSplit32 = 4, // (hi, mid, lo) triples stored as for kSplit3; products use (hi, mid) only,
                 // i.e. the two-term split hh + hm + mh (mid = RNE(x - hi) is the two-term lo)
+  kSplitH = 5,  // packed (hi, lo) FP16 pairs of the operand scaled by 2^s, FP16 MFMA,
+                // FP32 accumulate; s = kXScaleExp for X, per matrix (MatMeta) for Y
 };
+
+// FP16 split (kSplitH): X_n's entries lie in [-1, 1] (spectrum in [0, 1]), so a
+// fixed 2^14 keeps them below the FP16 maximum with 4x headroom.  A Y matrix
+// carries its own exponent in its MatMeta: the producer of Y_{n+1} picks s
+// with 4.5 ||Y_n||_F 2^s <= 2^15, a bound on every entry of Y_{n+1}
+// (|Y_{n+1}|_ij <= ||Y_{n+1}||_2 <= (2 + 2 ||X_n||_2) ||Y_n||_2, ||X_n||_2 <= 1).
+constexpr int kXScaleExp = 14;
+constexpr double kYBound = 4.5;
+constexpr double kYTarget = 32768.0;
 
 // Bytes per matrix element in the operand copy of each format.
 __host__ __device__ constexpr int operand_bytes(int prec) {
-  return prec == kFP32 ? 4 : prec == kSplit2 ? 4 : (prec == kSplit3 || prec == kSplit32) ? 6 : prec == kBF16 ? 2 : 0;
+  return prec == kFP32 ? 4 : (prec == kSplit2 || prec == kSplitH) ? 4 : (prec == kSplit3 || prec == kSplit32) ? 6
+       : prec == kBF16 ? 2 : 0;
 }
 
 constexpr int kPadTo = 256;     // n is padded (with zeros in X-space) to a multiple of this
@@ -63,13 +75,25 @@ inline uint32_t job_pack(uint32_t kind, uint32_t obs, uint32_t ti, uint32_t tj) 
   return kind | (obs << 1) | (ti << 8) | (tj << 20);
 }
 
+// Per-matrix metadata next to each operand copy: the scale exponent of the
+// FP16 copy (kSplitH) and FP64 partials of ||M||_F^2 written by the producer
+// (`count` of them, fixed order), from which the next producer bounds its output.
+struct MatMeta {
+  int32_t scale;
+  int32_t count;
+  double nrm[1];       // count entries
+};
+inline size_t meta_bytes(int nparts) { return sizeof(int32_t) * 2 + sizeof(double) * (size_t)nparts; }
+
 // One operand matrix set: FP32 master plus (optionally) the operand copy in
-// the product format.  `stride_*` separates observables in a batch.
+// the product format.  `stride_*` separates observables in a batch; the
+// metadata of observable k sits at meta + k * stride_op.
 struct MatRef {
   float* f32;
   void* op;
   size_t stride_f32;   // elements
   size_t stride_op;    // bytes
+  char* meta;
 };
 
 struct StepArgs {

@@ -32,6 +32,8 @@
 //   workgroup 0 records it in the control block.  No host round trip per step.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dmpt_internal.h"
 #include "sp2_rule.h"
 
@@ -40,6 +42,7 @@ namespace dmpt {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -47,8 +50,9 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 #define GLB_AS __attribute__((address_space(1)))
 
 // Bytes per LDS row per pipeline stage: 16 k values of FP32 / packed split-2
-// (64 B = 4 slots of 16 B), 32 k values of plain BF16 (64 B), 16 k values of
-// packed split-3 (96 B = 6 slots); kSplit32 stages split-2-shaped rows.
+// (BF16 or FP16; 64 B = 4 slots of 16 B), 32 k values of plain BF16 (64 B),
+// 16 k values of packed split-3 (96 B = 6 slots); kSplit32 stages
+// split-2-shaped rows.
 template <int PREC> struct Fmt {
   static constexpr int RB = PREC == kSplit3 ? 96 : 64;
   static constexpr int S = RB / 16;
@@ -98,6 +102,10 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
 __device__ __forceinline__ float bf16_val(unsigned short b) {
   return __builtin_bit_cast(float, ((unsigned int)b) << 16);
 }
+__device__ __forceinline__ unsigned short f16_bits(float x) {
+  return __builtin_bit_cast(unsigned short, (_Float16)x);   // round to nearest even, subnormals kept
+}
+__device__ __forceinline__ float f16_val(unsigned short b) { return (float)__builtin_bit_cast(_Float16, b); }
 // Eq. doubleHalf with BF16 terms: part_0 = RNE(x), part_t = RNE(x - sum_{s<t} part_s).
 template <int T>
 __device__ __forceinline__ void split_terms(float x, unsigned short (&p)[T]) {
@@ -108,14 +116,53 @@ __device__ __forceinline__ void split_terms(float x, unsigned short (&p)[T]) {
     r = r - bf16_val(p[t]);
   }
 }
+// Eq. doubleHalf with FP16 terms on the scaled value: hi = RNE(x sc),
+// lo = RNE(x sc - hi); sc is a power of two, x sc - hi is exact in FP32.
+__device__ __forceinline__ void split_terms_h(float x, float sc, unsigned short (&p)[2]) {
+  const float xs = x * sc;
+  p[0] = f16_bits(xs);
+  p[1] = f16_bits(xs - f16_val(p[0]));
+}
 template <int PREC> struct Terms {
-  static constexpr int T = PREC == kSplit3 ? 3 : (PREC == kSplit2 || PREC == kSplit32) ? 2 : 1;
+  static constexpr int T = PREC == kSplit3 ? 3 : (PREC == kSplit2 || PREC == kSplit32 || PREC == kSplitH) ? 2 : 1;
 };
+// The split terms of one element in the operand format F (sc: kSplitH scale).
+template <int F>
+__device__ __forceinline__ void split_for(float v, float sc, unsigned short (&p)[Terms<F>::T]) {
+  if constexpr (F == kSplitH) split_terms_h(v, sc, p);
+  else split_terms<Terms<F>::T>(v, p);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// kSplitH: exponent s of the scale 2^s of a Y copy whose entries are bounded
+// by bound * nrm (nrm a Frobenius norm): the largest s with bound * nrm * 2^s
+// <= kYTarget, clamped to [-100, 100]; 0 for a zero or non-finite norm.
+__device__ __forceinline__ int yscale_exp(double nrm, double bound) {
+  const double b = bound * nrm;
+  if (!(b > 0.0) || !(b < 1e300)) return 0;
+  const int e = (int)floor(log2(kYTarget / b));
+  return e < -100 ? -100 : e > 100 ? 100 : e;
+}
+
+// Frobenius norm of a matrix from its producer's partials (count of them in
+// meta->nrm, at most cap = the allocated number), summed in a fixed order by
+// wave 0 of the block (every block gets the same value); the result is
+// broadcast through *s_out.
+__device__ __forceinline__ double meta_norm(const MatMeta* m, int cap, double* s_out) {
+  if (threadIdx.x < 64) {
+    const int cnt = m->count < cap ? m->count : cap;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += 64) t += m->nrm[i];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) *s_out = sqrt(t);
+  }
+  __syncthreads();
+  return *s_out;
 }
 
 // Physical 16-byte slot of logical slot ls in LDS row r.  4 slots/row:
@@ -232,6 +279,7 @@ template <int PREC> struct Ops;
 template <> struct Ops<kSplit3> { bf16x8 a[BR][3], b[BC][3]; };
 template <> struct Ops<kSplit2> { bf16x8 a[BR][2], b[BC][2]; };
 template <> struct Ops<kSplit32> { bf16x8 a[BR][2], b[BC][2]; };
+template <> struct Ops<kSplitH> { f16x8 a[BR][2], b[BC][2]; };
 template <> struct Ops<kBF16> { bf16x8 a[BR][2], b[BC][2]; };     // [t]: k16 step
 template <> struct Ops<kFP32> { f32x4 a[BR][2], b[BC][2]; };       // [q]: slot h + 2q
 
@@ -245,16 +293,17 @@ __device__ __forceinline__ void read_ops(const LDS_AS char* slot, Ops<PREC>& o, 
   constexpr int S = Pipe<PREC>::S;
   const LDS_AS char* pA = slot;
   const LDS_AS char* pB = slot + Pipe<PREC>::A_BYTES;
-  if constexpr (PREC == kSplit3 || PREC == kSplit2 || PREC == kSplit32) {
+  if constexpr (PREC == kSplit3 || PREC == kSplit2 || PREC == kSplit32 || PREC == kSplitH) {
     constexpr int T = Terms<PREC>::T;
+    using E = typename std::remove_reference<decltype(o.a[0][0])>::type;
 #pragma unroll
     for (int i = 0; i < BR; ++i)
 #pragma unroll
-      for (int p = 0; p < T; ++p) o.a[i][p] = __builtin_bit_cast(bf16x8, lds16(pA + swz<S>(rowA + 32 * i, T * h + p)));
+      for (int p = 0; p < T; ++p) o.a[i][p] = __builtin_bit_cast(E, lds16(pA + swz<S>(rowA + 32 * i, T * h + p)));
 #pragma unroll
     for (int j = 0; j < BC; ++j)
 #pragma unroll
-      for (int p = 0; p < T; ++p) o.b[j][p] = __builtin_bit_cast(bf16x8, lds16(pB + swz<S>(rowB + 32 * j, T * h + p)));
+      for (int p = 0; p < T; ++p) o.b[j][p] = __builtin_bit_cast(E, lds16(pB + swz<S>(rowB + 32 * j, T * h + p)));
   } else if constexpr (PREC == kBF16) {
 #pragma unroll
     for (int i = 0; i < BR; ++i)
@@ -278,7 +327,7 @@ __device__ __forceinline__ void read_ops(const LDS_AS char* slot, Ops<PREC>& o, 
 
 // acc[i][j] += A_i B_j^T for one stage.
 //   split-3: products of order >= 2^-16 (hh, hm, mh, hl, lh, mm), smallest first
-//   split-2: hh + hl + lh (lo*lo dropped, Eq. MixPrecMult)
+//   split-2: hh + hl + lh (lo*lo dropped, Eq. MixPrecMult), BF16 or FP16 terms
 template <int PREC>
 __device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC]) {
 #pragma unroll
@@ -297,6 +346,10 @@ __device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
+      } else if constexpr (PREC == kSplitH) {
+        c = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
       } else if constexpr (PREC == kBF16) {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][1], c, 0, 0, 0);
@@ -380,10 +433,10 @@ __device__ int step_controller(const StepArgs& a, int* s_code) {
 }
 
 template <int PREC>
-__device__ __forceinline__ void store_split1(char* oop, int nst, int r, int c, float v) {
+__device__ __forceinline__ void store_split1(char* oop, int nst, int r, int c, float v, float sc) {
   constexpr int T = Terms<PREC>::T;
   unsigned short part[T];
-  split_terms<T>(v, part);
+  split_for<PREC>(v, sc, part);
 #pragma unroll
   for (int t = 0; t < T; ++t) *(unsigned short*)(oop + op_off<PREC>(r, c, t, nst)) = part[t];
 }
@@ -391,11 +444,11 @@ __device__ __forceinline__ void store_split1(char* oop, int nst, int r, int c, f
 // Operand copy of 8 consecutive columns c0..c0+7 (c0 % 8 == 0) of row r, in
 // the tiled layout: each split term of the group is one 16-byte slot.
 template <int PREC>
-__device__ __forceinline__ void store_group8_t(char* op, int nst, int r, int c0, const float (&v)[8]) {
+__device__ __forceinline__ void store_group8_t(char* op, int nst, int r, int c0, const float (&v)[8], float sc) {
   constexpr int T = Terms<PREC>::T;
   unsigned short part[8][T];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) split_terms<T>(v[e], part[e]);
+  for (int e = 0; e < 8; ++e) split_for<PREC>(v[e], sc, part[e]);
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     u32x4 w;
@@ -423,6 +476,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   __shared__ __attribute__((aligned(1024))) char ring3[RSZ];
   __shared__ int s_code;
   __shared__ double s_red[3 * NW];
+  __shared__ double s_nrm;
 
   if (a.decide && a.ctl->done) return;
   int sigma;
@@ -453,6 +507,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const char* b0 = xop + rowJ;
   const char* a1 = xop + rowI;
   const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
+
+  // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
+  // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
+  // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
+  // exponent bounded from ||Y_n||_F.
+  float usc = 1.0f, sc_out = 1.0f;
+  int s_out = 0;
+  if constexpr (PREC == kSplitH) {
+    if (kind == kJobZ) {
+      const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
+      usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
+      const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
+      s_out = yscale_exp(meta_norm(mi, nb * nb, &s_nrm), kYBound);
+    } else {
+      usc = ldexpf(1.0f, -2 * kXScaleExp);
+      s_out = kXScaleExp;
+    }
+    sc_out = ldexpf(1.0f, s_out);
+  }
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -545,6 +618,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   for (int i = 0; i < BR; ++i)
 #pragma unroll
     for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
+  if constexpr (PREC == kSplitH) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
+  }
 
   // ------------------------------------------------------------ epilogue
   const size_t np = a.n_pad;
@@ -557,7 +636,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const bool wsplit = a.write_split && PREC != kFP32;
   const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
   double tr = 0.0, sq = 0.0, ep = 0.0;
-
+  double yq = 0.0;   // kSplitH Z-jobs: ||Y_{n+1}||_F^2 over this tile (and its mirror)
   const bool need_cur = kind == kJobP || sigma < 0;
   if (!onDiag) {
     // Off-diagonal tile: every element is stored twice (direct and mirror).
@@ -602,6 +681,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           for (int k = 0; k < 4; ++k) T[r * kLS + c + k] = v[k];
         }
       }
+      if constexpr (PREC == kSplitH) {
+        if (kind == kJobZ)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) yq += 2.0 * (double)v[k] * (double)v[k];
+      }
       *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
     }
     wait_vm<63, true>();
@@ -621,7 +705,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           float v[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
-          store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v);
+          store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v, sc_out);
         }
 #pragma unroll 2
         for (int rd = 0; rd < 8; ++rd) {
@@ -629,7 +713,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
           float v[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
-          store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v);
+          store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v, sc_out);
         }
       }
     }
@@ -658,8 +742,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             o32[(size_t)r * np + col] = v;
             o32[(size_t)col * np + r] = v;
             if (wsplit) {
-              store_split1<Store<PREC>::F>(oop, nstp, r, col, v);
-              if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v);
+              store_split1<Store<PREC>::F>(oop, nstp, r, col, v, sc_out);
+              if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v, sc_out);
+            }
+            if constexpr (PREC == kSplitH) {
+              if (kind == kJobZ) yq += (r == col ? 1.0 : 2.0) * (double)v * (double)v;
             }
             if (kind == kJobP) {
               const double w = r == col ? 1.0 : 2.0;
@@ -692,6 +779,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       a.part_out[tile_index(ti, tj, a.ntile)] = p;
     }
   }
+  if constexpr (PREC == kSplitH) {
+    if (kind == kJobZ) {
+      yq = wave_sum(yq);
+      if (lane == 0) s_red[wave] = yq;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += s_red[w];
+        MatMeta* mo = (MatMeta*)(a.y_out.meta + obs * a.y_out.stride_op);
+        const int idx = tile_index(ti, tj, a.ntile);
+        mo->nrm[idx] = t;
+        if (idx == 0) {
+          const int tr_ = a.n_pad / TM;
+          mo->scale = s_out;
+          mo->count = tr_ * (tr_ + 1);
+        }
+      }
+    }
+  }
 }
 
 hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s) {
@@ -702,6 +808,7 @@ hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s)
     case kSplit3: hipLaunchKernelGGL(k_step<kSplit3>, dim3(njobs), dim3(NT), 0, s, args); break;
     case kSplit32: hipLaunchKernelGGL(k_step<kSplit32>, dim3(njobs), dim3(NT), 0, s, args); break;
     case kBF16: hipLaunchKernelGGL(k_step<kBF16>, dim3(njobs), dim3(NT), 0, s, args); break;
+    case kSplitH: hipLaunchKernelGGL(k_step<kSplitH>, dim3(njobs), dim3(NT), 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -913,17 +1020,30 @@ hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, 
 
 // ---------------------------------------------------------------- operand copies
 
-__device__ __forceinline__ void store_group8(int prec, char* op, int n_pad, int r, int c0, const float (&v)[8]) {
-  if (prec == kSplit2) store_group8_t<kSplit2>(op, n_pad / Fmt<kSplit2>::K, r, c0, v);
-  else if (prec == kSplit3 || prec == kSplit32) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v);
-  else if (prec == kBF16) store_group8_t<kBF16>(op, n_pad / Fmt<kBF16>::K, r, c0, v);
+__device__ __forceinline__ void store_group8(int prec, char* op, int n_pad, int r, int c0, const float (&v)[8],
+                                             float sc) {
+  if (prec == kSplit2) store_group8_t<kSplit2>(op, n_pad / Fmt<kSplit2>::K, r, c0, v, sc);
+  else if (prec == kSplit3 || prec == kSplit32) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v, sc);
+  else if (prec == kBF16) store_group8_t<kBF16>(op, n_pad / Fmt<kBF16>::K, r, c0, v, sc);
+  else if (prec == kSplitH) store_group8_t<kSplitH>(op, n_pad / Fmt<kSplitH>::K, r, c0, v, sc);
 }
 
-// Rebuild the operand copy of nmat matrices from their FP32 masters.
+// Rebuild the operand copy of nmat matrices from their FP32 masters.  For
+// kSplitH (used for the Y matrices written by k_init) the scale comes from
+// the matrix's own norm partials: |M_ij| <= ||M||_F, and block (0, z) records
+// the exponent in the matrix's metadata.
 __global__ __launch_bounds__(256) void k_resplit(int prec, MatRef m, int n_pad) {
+  __shared__ double s_nrm;
   const int z = blockIdx.y;
   const float* src = m.f32 + (size_t)z * m.stride_f32;
   char* dst = (char*)m.op + (size_t)z * m.stride_op;
+  float sc = 1.0f;
+  if (prec == kSplitH) {
+    MatMeta* mm = (MatMeta*)(m.meta + (size_t)z * m.stride_op);
+    const int e = yscale_exp(meta_norm(mm, (n_pad / 64) * (n_pad / 64), &s_nrm), 1.0);
+    sc = ldexpf(1.0f, e);
+    if (blockIdx.x == 0 && threadIdx.x == 0) mm->scale = e;
+  }
   const size_t ngroups = (size_t)n_pad * n_pad / 8;
   for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < ngroups; g += (size_t)gridDim.x * 256) {
     const size_t r = g / (n_pad / 8);
@@ -931,7 +1051,7 @@ __global__ __launch_bounds__(256) void k_resplit(int prec, MatRef m, int n_pad) 
     const f32x4 a = *(const f32x4*)(src + r * n_pad + c0);
     const f32x4 b = *(const f32x4*)(src + r * n_pad + c0 + 4);
     const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-    store_group8(prec, dst, n_pad, (int)r, c0, v);
+    store_group8(prec, dst, n_pad, (int)r, c0, v, sc);
   }
 }
 
@@ -985,8 +1105,11 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
   const MatRef& m = z == 0 ? x : y;
   float* o32 = m.f32 + (z == 0 ? 0 : (size_t)(z - 1) * m.stride_f32);
   char* oop = (char*)m.op + (z == 0 ? 0 : (size_t)(z - 1) * m.stride_op);
-  const int opb = operand_bytes(prec);
-  const size_t ldb = (size_t)n_pad * opb;
+  // kSplitH: X_1's copy at the fixed 2^14; a Y copy needs the matrix's norm
+  // first, so here Y gets only its master and norm partials (k_resplit
+  // writes the copy)
+  const bool ycopy_later = prec == kSplitH && z != 0;
+  const float sc = prec == kSplitH ? ldexpf(1.0f, kXScaleExp) : 1.0f;
   double tr = 0.0, sq = 0.0;
   // each thread: 2 groups of 8 consecutive columns
   for (int gidx = t; gidx < 64 * 8; gidx += 256) {
@@ -1004,16 +1127,24 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
         val = ys * (double)s;
       }
       v[e] = (float)val;
-      if (z == 0) {
-        const double d = v[e];
-        sq += d * d;
-        if (gi == gj) tr += d;
-      }
+      const double d = v[e];
+      sq += d * d;
+      if (z == 0 && gi == gj) tr += d;
     }
     float* dst = o32 + (size_t)gi * n_pad + bj * 64 + cg;
     *(f32x4*)dst = f32x4{v[0], v[1], v[2], v[3]};
     *(f32x4*)(dst + 4) = f32x4{v[4], v[5], v[6], v[7]};
-    store_group8(prec, oop, n_pad, gi, bj * 64 + cg, v);
+    if (!ycopy_later) store_group8(prec, oop, n_pad, gi, bj * 64 + cg, v, sc);
+  }
+  if (ycopy_later) {
+    sq = wave_sum(sq);
+    if ((t & 63) == 0) s_red[t >> 6] = sq;
+    __syncthreads();
+    if (t == 0) {
+      MatMeta* mm = (MatMeta*)(m.meta + (size_t)(z - 1) * m.stride_op);
+      mm->nrm[bi * gridDim.x + bj] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+      if (bi == 0 && bj == 0) mm->count = gridDim.x * gridDim.y;
+    }
   }
   if (z == 0) {
     tr = wave_sum(tr);

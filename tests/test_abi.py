@@ -73,7 +73,7 @@ def test_checkpoint_workspace(lib):
     instead of max_iter + 3 slots."""
     full = _opts(lib, 1000, 500, sweep=1)
     w_full = lib.dmpt_workspace_bytes(C.byref(full), 1)
-    slot = 1024 * 1024 * 4
+    slot = 1024 * 1024 * 4 + 2304   # FP32 master + metadata (8 B + 256 FP64 partials, 256-aligned)
     for k in (1, 4, 8, 16):
         ck = _opts(lib, 1000, 500, sweep=1, ckpt_interval=k)
         w = lib.dmpt_workspace_bytes(C.byref(ck), 1)

@@ -3,7 +3,8 @@ banded gapped tight-binding H (half-bandwidth 64, gap 0.1 at N_occ = 2048),
 A = site-position operator, 8 perturbations.  The FP64 oracle is the
 Daleckii-Krein closed form (eigendecomposition on the host).
 
-Tolerances (relative Frobenius): FP32 products 1e-5; split BF16 (hi+mid+lo)
+Tolerances (relative Frobenius): FP32 products and the scaled FP16 split 1e-5;
+split BF16 (hi+mid+lo)
 1e-4, also with the sweep products on (hi, mid) only; the two-term split
 (hi+lo) is reported with a 2e-3 bound.
 """
@@ -15,7 +16,7 @@ from oracle import closed_form as cf
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "split3_bf16": 1e-4, "split3x_bf16": 1e-4, "split_bf16": 2e-3}
+TOL = {"fp32": 1e-5, "split_fp16": 1e-5, "split3_bf16": 1e-4, "split3x_bf16": 1e-4, "split_bf16": 2e-3}
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +29,7 @@ def c2():
     return wl, d, chi
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split3_bf16", "split3x_bf16", "split_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16", "split3_bf16", "split3x_bf16", "split_bf16"])
 def test_config2_parity(gpu, c2, prec):
     import torch
 

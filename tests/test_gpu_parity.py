@@ -2,6 +2,8 @@
 
 Tolerances (relative Frobenius error against the closed form):
   FP32 products                    D <= 1e-5, chi <= 1e-5
+  split-FP16 products (hi+lo, 11-bit terms on scaled operands: 22 bits
+  per operand, the dropped lo*lo is 2^-22 relative)  D, chi <= 1e-5
   split-BF16 products (hi+mid+lo)  D <= 1e-4, chi <= 1e-4
   two-term split (hi+lo, the paper's Eq. MixPrecMult scheme) is tracked with
   1e-4 on dense observables and 1e-3 on the site-position observable, whose
@@ -19,8 +21,8 @@ from oracle import sp2
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "split3_bf16": 1e-4, "split_bf16": 1e-4, "split3x_bf16": 1e-4}
-PRECS = ["fp32", "split3_bf16", "split3x_bf16", "split_bf16"]
+TOL = {"fp32": 1e-5, "split_fp16": 1e-5, "split3_bf16": 1e-4, "split_bf16": 1e-4, "split3x_bf16": 1e-4}
+PRECS = ["fp32", "split_fp16", "split3_bf16", "split3x_bf16", "split_bf16"]
 
 
 def _tol(prec, case):
