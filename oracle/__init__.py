@@ -22,6 +22,9 @@ scf           Self-consistent susceptibility (Eq. CP_SCF) and density response
               (Eq. DM_CP_SCF) for an on-site interaction, iterated with linear
               mixing as the paper writes them; the SCF ground state for FD.
 mlp           The learned mixer network (forward, MSE loss gradient, Adam) in FP64.
+nonorth       Non-orthonormal basis (Sec. V.A): congruences with an inverse
+              factor Z, D = Z D_perp Z^T, chi_perp and the atomic-orbital
+              chi_ao = Z chi_perp Z^T; the generalised-eigenproblem density.
 
 Pins (tests/test_oracle_*.py): hand-derived 2x2 closed forms, textbook
 Rayleigh-Schroedinger first-order theory for diagonal H, brute-force finite
@@ -29,4 +32,4 @@ differences, exact-spectrum constructions, projector identities, the
 commutator identity [H, chi] = [D, A], the duality identity for unconverged
 recursions and the forward/backward equivalence.
 """
-from . import closed_form, sp2, finite_diff, scf, mlp  # noqa: F401
+from . import closed_form, sp2, finite_diff, scf, mlp, nonorth  # noqa: F401
