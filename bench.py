@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "time-to-χ (ms) + MFMA TFLOP/s at N=8192, split-BF16 vs FP32, at stated error"
-PEAK = {"bf16": 2516.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X)
+PEAK = {"bf16": 2516.6, "f16": 2516.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X)
 PRODUCTS = {"split3_bf16": 6, "split3x_bf16": 4, "split_bf16": 3, "split_fp16": 3, "fp32": 1, "bf16": 1}   # MFMA products per FP32-equivalent product (split3x: 6 for X^2, 3 for YX + XY)
 
 
@@ -39,8 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="split3_bf16")
-    ap.add_argument("--compare", default="fp32,split3x_bf16,split_bf16", help="other precisions timed for context")
+    ap.add_argument("--precision", default="split_fp16")
+    ap.add_argument("--compare", default="fp32,split3_bf16,split_bf16", help="other precisions timed for context")
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5, help="FP64 oracle SP2+chi steps in the CPU sample")
@@ -181,7 +181,7 @@ def main():
 
     main_prec = args.precision
     r = results[main_prec]
-    dtype = "fp32" if main_prec == "fp32" else "bf16"
+    dtype = "fp32" if main_prec == "fp32" else "f16" if main_prec == "split_fp16" else "bf16"
     roof = {
         "bound": "mfma",
         "kernel": f"k_step<{main_prec}> (one SP2 + chi step)",
