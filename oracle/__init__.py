@@ -25,6 +25,10 @@ mlp           The learned mixer network (forward, MSE loss gradient, Adam) in FP
 nonorth       Non-orthonormal basis (Sec. V.A): congruences with an inverse
               factor Z, D = Z D_perp Z^T, chi_perp and the atomic-orbital
               chi_ao = Z chi_perp Z^T; the generalised-eigenproblem density.
+fermi         Finite electronic temperature (Sec. V.B): the Fermi function with
+              the canonical chemical potential, the temperature-dependent
+              susceptibility with its mu_1 shift, and the recursive doubling
+              expansion with its first-order response.
 
 Pins (tests/test_oracle_*.py): hand-derived 2x2 closed forms, textbook
 Rayleigh-Schroedinger first-order theory for diagonal H, brute-force finite
@@ -32,4 +36,4 @@ differences, exact-spectrum constructions, projector identities, the
 commutator identity [H, chi] = [D, A], the duality identity for unconverged
 recursions and the forward/backward equivalence.
 """
-from . import closed_form, sp2, finite_diff, scf, mlp, nonorth  # noqa: F401
+from . import closed_form, sp2, finite_diff, scf, mlp, nonorth, fermi  # noqa: F401
