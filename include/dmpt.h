@@ -186,6 +186,30 @@ dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32
                           size_t workspace_bytes);
 
 /* ---------------------------------------------------------------------------
+ * Non-orthonormal basis (Sec. V.A).  With overlap S and an inverse factor Z
+ * (Z^T S Z = I: Z = S^{-1/2} for Loewdin orthonormalisation, or the inverse
+ * of the Cholesky factor's transpose) the orthonormal problem is
+ *   H_perp = Z^T H Z,  A_perp = Z^T A Z,  D_perp = theta(mu I - H_perp),
+ * solved as dmpt_susceptibility does (same opts: precision, sweep, bounds,
+ * projection), and mapped back: D = Z D_perp Z^T.  Outputs:
+ *   chi_perp  s dTr[A_perp D_perp]/dH_perp, the dual of H_perp-perturbations
+ *             (Tr[A_perp D_perp_tau] = Tr[chi_perp H_perp_tau]);
+ *   chi_ao    Z chi_perp Z^T, the dual of perturbations of H at fixed S
+ *             (Tr[chi_perp Z^T dH Z] = Tr[chi_ao dH]);
+ *   D         the density matrix in the atomic-orbital basis;
+ *   a0        s Tr[A D] = s Tr[A_perp D_perp] (host, nobs values).
+ * H (n x n, symmetric), Z (n x n, any inverse factor) and A (nobs x n x n,
+ * symmetric) are device FP32 row-major; chi_perp, chi_ao (nobs x n x n), D
+ * and a0 may each be NULL.  The congruences run as FP32 MFMA products on
+ * zero-padded copies in the workspace (>= dmpt_nonorth_workspace_bytes).
+ * Returns the status of the orthonormal solve (NOT_CONVERGED still maps the
+ * last iterate back). */
+size_t dmpt_nonorth_workspace_bytes(const dmpt_opts* opts, int32_t nobs);
+dmpt_status dmpt_susceptibility_nonorth(const float* H, const float* Z, const float* A, int32_t nobs,
+                                        float* chi_perp, float* chi_ao, float* D, double* a0,
+                                        const dmpt_opts* opts, dmpt_info* info);
+
+/* ---------------------------------------------------------------------------
  * Self-consistent susceptibility (Eq. CP_SCF; Sec. V.C and the Appendix) at
  * zero temperature in an orthonormal basis (Z = I, mu_1 = 0), for an on-site
  * self-consistent field: H = H0 + diag(U_i (n_i - n0_i)), n = s diag(D),

@@ -133,6 +133,41 @@ def susceptibility(H, A, nocc: int, *, want_density: bool = True, workspace=None
     return (chi[0] if single else chi), D, list(a0), info.as_dict()
 
 
+def susceptibility_nonorth(H, Z, A, nocc: int, *, raise_on_error: bool = True, **kw):
+    """Sec. V.A: the susceptibility in a non-orthonormal basis with inverse
+    factor Z (Z^T S Z = I).  A: (n, n) or (nobs, n, n).  Returns
+    (chi_perp, chi_ao, D, a0 [nobs], info dict): chi_perp is the dual of
+    H_perp = Z^T H Z, chi_ao = Z chi_perp Z^T the dual of H at fixed S, D the
+    atomic-orbital density matrix Z D_perp Z^T."""
+    torch = _torch()
+    n = H.shape[-1]
+    _check_matrix(H, n, "H")
+    _check_matrix(Z, n, "Z")
+    _check_matrix(A, n, "A")
+    single = A.dim() == 2
+    nobs = 1 if single else A.shape[0]
+    o = make_opts(n, nocc, **kw)
+    lib = load()
+    nbytes = int(lib.dmpt_nonorth_workspace_bytes(C.byref(o), nobs))
+    if nbytes == 0:
+        check(1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=H.device)
+    o.workspace, o.workspace_bytes = ws.data_ptr(), nbytes
+    chi_p = torch.empty((nobs, n, n), dtype=torch.float32, device=H.device)
+    chi_ao = torch.empty((nobs, n, n), dtype=torch.float32, device=H.device)
+    D = torch.empty((n, n), dtype=torch.float32, device=H.device)
+    a0 = (C.c_double * nobs)()
+    info = Info()
+    st = lib.dmpt_susceptibility_nonorth(C.c_void_p(H.data_ptr()), C.c_void_p(Z.data_ptr()),
+                                         C.c_void_p(A.data_ptr()), nobs, C.c_void_p(chi_p.data_ptr()),
+                                         C.c_void_p(chi_ao.data_ptr()), C.c_void_p(D.data_ptr()), a0,
+                                         C.byref(o), C.byref(info))
+    _finish(st, info, raise_on_error)
+    if single:
+        chi_p, chi_ao = chi_p[0], chi_ao[0]
+    return chi_p, chi_ao, D, list(a0), info.as_dict()
+
+
 def response(chi, H1, *, stream=None):
     """Eq. dual: out[k, p] = Tr[chi_k H1_p] (FP64).  chi: (n,n)/(K,n,n); H1: (n,n)/(P,n,n)."""
     torch = _torch()

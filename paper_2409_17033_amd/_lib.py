@@ -33,6 +33,7 @@ EXPORTS = [
     "dmpt_susceptibility", "dmpt_response_workspace_bytes", "dmpt_response",
     "dmpt_scf_response", "dmpt_scf_workspace_bytes", "dmpt_mixer_param_count", "dmpt_mixer_workspace_bytes",
     "dmpt_mixer_init", "dmpt_mixer_forward", "dmpt_mixer_loss_grad", "dmpt_mixer_train",
+    "dmpt_nonorth_workspace_bytes", "dmpt_susceptibility_nonorth",
     "dmpt_sp2_decide", "dmpt_status_string", "dmpt_last_error",
 ]
 
@@ -130,6 +131,11 @@ def load() -> C.CDLL:
     lib.dmpt_sp2_density.restype = C.c_int
     lib.dmpt_susceptibility.argtypes = [P, P, I32, P, P, C.POINTER(D), C.POINTER(Opts), C.POINTER(Info)]
     lib.dmpt_susceptibility.restype = C.c_int
+    lib.dmpt_nonorth_workspace_bytes.argtypes = [C.POINTER(Opts), I32]
+    lib.dmpt_nonorth_workspace_bytes.restype = C.c_size_t
+    lib.dmpt_susceptibility_nonorth.argtypes = [P, P, P, I32, P, P, P, C.POINTER(D), C.POINTER(Opts),
+                                                C.POINTER(Info)]
+    lib.dmpt_susceptibility_nonorth.restype = C.c_int
     lib.dmpt_response_workspace_bytes.argtypes = [I32, I32, I32]
     lib.dmpt_response_workspace_bytes.restype = SZ
     lib.dmpt_response.argtypes = [P, I32, P, I32, I32, C.POINTER(D), P, P, SZ]

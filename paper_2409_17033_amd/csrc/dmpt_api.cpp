@@ -771,6 +771,107 @@ dmpt_status dmpt_susceptibility(const float* H, const float* A, int32_t nobs, fl
   return run(H, A, nobs, chi, D, a0, opts, info);
 }
 
+// ---------------------------------------------------------------- non-orthonormal basis
+
+// Workspace of dmpt_susceptibility_nonorth: the orthonormal problem's
+// workspace, then four n_pad x n_pad FP32 matrices (Z, Z^T, a product and a
+// padded operand/result) and n x n FP32 matrices for H_perp, D_perp and
+// nobs each of A_perp and chi_perp.
+struct NonorthWS {
+  size_t run, zp, ztp, tp, up, hperp, dperp, aperp, cperp, total;
+};
+
+NonorthWS nonorth_ws(size_t run_bytes, int n, int n_pad, int nobs) {
+  NonorthWS w;
+  const size_t pad2 = (size_t)n_pad * n_pad * 4, n2 = (size_t)n * n * 4;
+  size_t off = align_up(run_bytes);
+  w.run = run_bytes;
+  w.zp = off; off = align_up(off + pad2);
+  w.ztp = off; off = align_up(off + pad2);
+  w.tp = off; off = align_up(off + pad2);
+  w.up = off; off = align_up(off + pad2);
+  w.hperp = off; off = align_up(off + n2);
+  w.dperp = off; off = align_up(off + n2);
+  w.aperp = off; off = align_up(off + n2 * nobs);
+  w.cperp = off; off = align_up(off + n2 * nobs);
+  w.total = off;
+  return w;
+}
+
+dmpt_status nonorth_check(const dmpt_opts* opts, int nobs, Opts* o, Plan* p) {
+  dmpt_status st = normalise(opts, o);
+  if (st != DMPT_OK) return st;
+  if (nobs < 1 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [1, %d]", nobs, kMaxObs);
+  make_plan(*o, nobs, p);
+  return DMPT_OK;
+}
+
+size_t dmpt_nonorth_workspace_bytes(const dmpt_opts* opts, int32_t nobs) {
+  Opts o;
+  Plan p;
+  if (nonorth_check(opts, nobs, &o, &p) != DMPT_OK) return 0;
+  return nonorth_ws(p.total, o.n, p.n_pad, nobs).total;
+}
+
+dmpt_status dmpt_susceptibility_nonorth(const float* H, const float* Z, const float* A, int32_t nobs,
+                                        float* chi_perp, float* chi_ao, float* D, double* a0,
+                                        const dmpt_opts* opts, dmpt_info* info) {
+  Opts o;
+  Plan p;
+  dmpt_status st = nonorth_check(opts, nobs, &o, &p);
+  if (st != DMPT_OK) return st;
+  if (!H || !Z || !A) return fail(DMPT_ERR_ARG, "H, Z and A must not be NULL");
+  const int n = o.n, np = p.n_pad;
+  const NonorthWS w = nonorth_ws(p.total, n, np, nobs);
+  if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
+  if (o.ws_bytes < w.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, w.total);
+  hipStream_t s = o.stream;
+  char* ws = o.ws;
+  float* zp = (float*)(ws + w.zp);
+  float* ztp = (float*)(ws + w.ztp);
+  float* tp = (float*)(ws + w.tp);
+  float* up = (float*)(ws + w.up);
+  float* hperp = (float*)(ws + w.hperp);
+  float* dperp = (float*)(ws + w.dperp);
+  float* aperp = (float*)(ws + w.aperp);
+  float* cperp = chi_perp ? chi_perp : (float*)(ws + w.cperp);
+  const size_t n2 = (size_t)n * n;
+  const int fl = flush_interval(kFP32, np);
+  // M_perp = Z^T M Z for symmetric M: T = Z^T M^T = Z^T M, then Z^T T^T = Z^T M Z
+  auto to_perp = [&](const float* m, float* out) -> dmpt_status {
+    DMPT_HIP(launch_pad(m, n, np, up, 0, s));
+    DMPT_HIP(launch_gemm_nt(ztp, up, tp, np, 1.0f, fl, s));
+    DMPT_HIP(launch_gemm_nt(ztp, tp, up, np, 1.0f, fl, s));
+    DMPT_HIP(launch_copy_out(up, n, np, out, s));
+    return DMPT_OK;
+  };
+  // M = Z M_perp Z^T for symmetric M_perp: T = Z M_perp^T = Z M_perp, then T Z^T
+  auto from_perp = [&](const float* m, float* out) -> dmpt_status {
+    DMPT_HIP(launch_pad(m, n, np, up, 0, s));
+    DMPT_HIP(launch_gemm_nt(zp, up, tp, np, 1.0f, fl, s));
+    DMPT_HIP(launch_gemm_nt(tp, zp, up, np, 1.0f, fl, s));
+    DMPT_HIP(launch_copy_out(up, n, np, out, s));
+    return DMPT_OK;
+  };
+  DMPT_HIP(launch_pad(Z, n, np, zp, 0, s));
+  DMPT_HIP(launch_pad(Z, n, np, ztp, 1, s));
+  if ((st = to_perp(H, hperp)) != DMPT_OK) return st;
+  for (int k = 0; k < nobs; ++k)
+    if ((st = to_perp(A + k * n2, aperp + k * n2)) != DMPT_OK) return st;
+  dmpt_opts o2 = *opts;
+  o2.workspace = ws;
+  o2.workspace_bytes = w.run;
+  // the orthonormal problem: D_perp, chi_perp and a0 = s Tr[A_perp D_perp] = s Tr[A D]
+  const dmpt_status rs = run(hperp, aperp, nobs, cperp, dperp, a0, &o2, info);
+  if (rs != DMPT_OK && rs != DMPT_ERR_NOT_CONVERGED) return rs;
+  if (D && (st = from_perp(dperp, D)) != DMPT_OK) return st;
+  if (chi_ao)
+    for (int k = 0; k < nobs; ++k)
+      if ((st = from_perp(cperp + k * n2, chi_ao + k * n2)) != DMPT_OK) return st;
+  DMPT_HIP(hipStreamSynchronize(s));
+  return rs;
+}
+
 // Responses are formed in groups of up to kRespObs observables x kRespPert
 // perturbations (one pass over the group's chi and H1 per group).
 constexpr int kRespObs = 8, kRespPert = 64, kRespMax = 1 << 20;

@@ -140,6 +140,11 @@ hipError_t launch_response(const float* chi, int nobs, const float* h1, int nper
                            double* part, int nblk, double* out_dev, int ld, hipStream_t s);
 int response_blocks(size_t n2);
 hipError_t launch_copy_out(const float* src, int n, int n_pad, float* dst, hipStream_t s);
+// Non-orthonormal basis: C = alpha A B^T (n_pad x n_pad, n_pad % 256 == 0,
+// FP32 MFMA) and zero-padded (optionally transposed) copies.
+hipError_t launch_gemm_nt(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
+                          hipStream_t s);
+hipError_t launch_pad(const float* src, int n, int n_pad, float* dst, int transpose, hipStream_t s);
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);
 int stage_k(int prec);   // k values per pipeline stage of the step kernel
 

@@ -814,6 +814,138 @@ hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s)
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- general products
+
+// C = alpha A B^T over all 256 x 128 tiles of an n_pad x n_pad result; A, B
+// and C are n_pad x n_pad row-major FP32 (zero padded).  These are the
+// congruences of the non-orthonormal basis (Sec. V.A: Z^T H Z, Z^T A Z,
+// Z D Z^T), formed as two NT products each.  Same operand pipeline as the
+// FP32 step kernel (row-major DMA into the four-slot LDS ring, FP32 MFMA
+// 32x32x2, two-level accumulation every `flush` groups of 4 stages); the
+// epilogue stores the tile as is.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nt(
+    const float* A, const float* B, float* C, int n_pad, float alpha, int flush) {
+  using P = Pipe<kFP32>;
+  __shared__ __attribute__((aligned(1024))) char ring0[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char ring1[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char ring2[P::SLOT];
+  __shared__ __attribute__((aligned(1024))) char ring3[P::SLOT];
+  const int tcols = n_pad / TN;
+  const int ti = blockIdx.x / tcols, tj = blockIdx.x % tcols;
+  const size_t ldb = (size_t)n_pad * 4;
+  const uint32_t ldb32 = (uint32_t)ldb;
+  const int nst = n_pad / Fmt<kFP32>::K;
+  const char* a0 = (const char*)A + (size_t)ti * TM * ldb;
+  const char* b0 = (const char*)B + (size_t)tj * TN * ldb;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
+  f32x16 acc[BR][BC], tot[BR][BC];
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) {
+      acc[i][j] = f32x16{0};
+      tot[i][j] = f32x16{0};
+    }
+  // stages past the end re-fetch stage 0 into a slot that is never read again
+  auto dma = [&](LDS_AS char* slot, int s) {
+    const size_t kb = (size_t)(s < nst ? s : 0) * P::RB;
+    dma_stage_rows<kFP32>(slot, a0 + kb, b0 + kb, ldb32, wave, lane);
+  };
+  LDS_AS char* R0 = (LDS_AS char*)ring0;
+  LDS_AS char* R1 = (LDS_AS char*)ring1;
+  LDS_AS char* R2 = (LDS_AS char*)ring2;
+  LDS_AS char* R3 = (LDS_AS char*)ring3;
+  Ops<kFP32> o0, o1;
+  dma(R0, 0);
+  dma(R1, 1);
+  dma(R2, 2);
+  wait_vm<2 * P::L, false>();
+  barrier_nofence();
+  dma(R3, 3);
+  __builtin_amdgcn_sched_barrier(0);
+  read_ops<kFP32>(R0, o0, rowA, rowB, h);
+#define DMPT_GITER(S_, NEXT, REFILL, OC, ON)              \
+  {                                                       \
+    wait_vm<2 * P::L, true>();                            \
+    barrier_nofence();                                    \
+    dma(REFILL, (S_) + 4);                                \
+    __builtin_amdgcn_sched_barrier(0);                    \
+    read_ops<kFP32>(NEXT, ON, rowA, rowB, h);             \
+    mma_ops<kFP32>(OC, acc);                              \
+  }
+  const int fl4 = flush > 0 ? flush : 1 << 30;
+  int since = 0;
+  for (int s = 0; s < nst; s += 4) {
+    DMPT_GITER(s + 0, R1, R0, o0, o1)
+    DMPT_GITER(s + 1, R2, R1, o1, o0)
+    DMPT_GITER(s + 2, R3, R2, o0, o1)
+    DMPT_GITER(s + 3, R0, R3, o1, o0)
+    if (++since == fl4) {
+      since = 0;
+#pragma unroll
+      for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int j = 0; j < BC; ++j) {
+          tot[i][j] += acc[i][j];
+          acc[i][j] = f32x16{0};
+        }
+    }
+  }
+#undef DMPT_GITER
+  wait_vm<0, true>();
+  // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+#pragma unroll
+  for (int bi = 0; bi < BR; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BC; ++bj) {
+      const f32x16 v = tot[bi][bj] + acc[bi][bj];
+      const int col = tj * TN + wc * 64 + bj * 32 + l32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h + e;
+          C[(size_t)r * n_pad + col] = alpha * v[4 * g + e];
+        }
+    }
+}
+
+hipError_t launch_gemm_nt(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
+                          hipStream_t s) {
+  if (n_pad <= 0 || n_pad % TM != 0) return hipErrorInvalidValue;
+  const int tiles = (n_pad / TM) * (n_pad / TN);
+  hipLaunchKernelGGL(k_gemm_nt, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush);
+  return hipGetLastError();
+}
+
+// dst (n_pad x n_pad, zero padded) = src (n x n, row-major, ld n), or its
+// transpose; one 64 x 64 block per workgroup, transposed through LDS.
+__global__ __launch_bounds__(256) void k_pad(const float* src, int n, int n_pad, float* dst, int transpose) {
+  __shared__ float tile[64][65];
+  const int bi = blockIdx.y, bj = blockIdx.x;          // output block
+  const int si = transpose ? bj : bi, sj = transpose ? bi : bj;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int gi = si * 64 + r, gj = sj * 64 + c;
+    tile[r][c] = (gi < n && gj < n) ? src[(size_t)gi * n + gj] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    dst[(size_t)(bi * 64 + r) * n_pad + bj * 64 + c] = transpose ? tile[c][r] : tile[r][c];
+  }
+}
+
+hipError_t launch_pad(const float* src, int n, int n_pad, float* dst, int transpose, hipStream_t s) {
+  const int nb = n_pad / 64;
+  hipLaunchKernelGGL(k_pad, dim3(nb, nb), dim3(256), 0, s, src, n, n_pad, dst, transpose);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- control
 
 __global__ void k_ctl_reset(Ctl* c) {

@@ -270,3 +270,16 @@ def test_controller_error_codes():
     # exactly idempotent / idem_tol
     assert dm.sp2_decide(5.0, 5.0, 0.0, 0.0, 10, 10, 5) == 0
     assert dm.sp2_decide(5.0, 5.0, 5e-7, 1e-9, 20, 10, 5, 10, 1e-6) == 0
+
+
+def test_nonorth_sizes_and_validation(lib):
+    o = _opts(lib, 1000, 500)
+    base = lib.dmpt_workspace_bytes(C.byref(o), 2)
+    w = lib.dmpt_nonorth_workspace_bytes(C.byref(o), 2)
+    # four padded n_pad^2 FP32 matrices and (2 + 2 nobs) n^2 FP32 matrices on top
+    assert w >= base + 4 * 1024 * 1024 * 4 + 6 * 1000 * 1000 * 4
+    assert lib.dmpt_nonorth_workspace_bytes(C.byref(o), 0) == 0
+    out = (C.c_double * 1)()
+    # NULL inputs are rejected before any device call
+    assert lib.dmpt_susceptibility_nonorth(None, None, None, 1, None, None, None, out, C.byref(o), None) == 1
+    assert lib.dmpt_susceptibility_nonorth(None, None, None, 0, None, None, None, out, C.byref(o), None) == 1
