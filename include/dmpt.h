@@ -210,6 +210,58 @@ dmpt_status dmpt_susceptibility_nonorth(const float* H, const float* Z, const fl
                                         const dmpt_opts* opts, dmpt_info* info);
 
 /* ---------------------------------------------------------------------------
+ * Fractional occupation at finite electronic temperature (Sec. V.B).
+ *   D = f(H) = (exp(beta (H - mu I)) + I)^{-1},  beta = 1 / kT,
+ *   chi = s d/dlambda f(H + lambda (A + mu_1 I)) at lambda = 0,
+ * canonical: mu with Tr D = N_occ and mu_1 with Tr chi = 0 (the electron
+ * count does not move); grand canonical: mu given, mu_1 = 0.
+ * Recursive Fermi-operator expansion (the doubling scheme of Niklasson,
+ * Phys. Rev. B 66, 155115 (2002)), run on E = D - I/2 so that FP32 keeps
+ * the relative precision of the high-temperature start:
+ *   E_0 = -(beta / 2^{m+2}) (H - mu I),  E_{k+1} = 2 E_k (I + 4 E_k^2)^{-1},
+ * D = I/2 + E_m; each inverse by Newton-Schulz iterations (the spectrum of
+ * I + 4 E_k^2 lies in [1, 1 + tanh^2(2^{k-1-m} beta w)], w = max |e - mu|
+ * over the bounds, which fixes the start and the iteration count).  The
+ * response Y = dE/dlambda of each observable runs alongside:
+ *   Y_0 = -(beta / 2^{m+2}) A,  Y_{k+1} = (2 Y_k - 4 E_{k+1} (Y_k E_k + E_k Y_k)) R_k,
+ * R_k = (I + 4 E_k^2)^{-1}, symmetrised every step.  mu (canonical) by
+ * Newton steps on Tr D(mu) = N_occ with dTr D/dmu = beta Tr[D - D^2]
+ * = beta (n/4 - ||E_m||_F^2), safeguarded by bisection; then
+ * mu_1 = Tr Y_m / (beta Tr[D - D^2]) and chi = s (Y_m - mu_1 beta (D - D^2)).
+ * All products are FP32 MFMA (DMPT_FP32 is the only precision accepted).
+ * H (n x n), A (nobs x n x n) device FP32 symmetric; chi (nobs x n x n) and
+ * D (n x n, nullable) device; a0 host (nobs, nullable) = s Tr[A D].  opts:
+ * n, nocc, bounds (Lanczos / Gershgorin / given, as for dmpt_sp2_density),
+ * spin, stream, workspace (>= dmpt_fermi_workspace_bytes). */
+typedef struct dmpt_fermi_opts {
+  double kt;             /* k_B T_e > 0, in the energy units of H */
+  double mu;             /* grand canonical: the chemical potential; canonical: the first
+                            Newton guess (NaN: from the bounds and N_occ / n) */
+  double count_tol;      /* canonical: |Tr D - N_occ| target (0: 1e-6 n) */
+  int32_t canonical;     /* 1 canonical, 0 grand canonical */
+  int32_t doublings;     /* m; 0: smallest m with beta w / 2^m <= 2^-8 */
+  int32_t newton_max;    /* canonical: Newton / bisection steps (0: 40) */
+  int32_t reserved;      /* must be 0 */
+} dmpt_fermi_opts;
+
+typedef struct dmpt_fermi_info {
+  double mu;             /* chemical potential used */
+  double trace_d;        /* Tr D */
+  double emin, emax;     /* spectral bounds */
+  int32_t doublings;     /* m of the final run */
+  int32_t newton;        /* recursions run to find mu (canonical) */
+  int32_t products;      /* matrix products of the final run */
+  int32_t reserved;
+  double mu1[64];        /* mu_1 per observable (first nobs valid) */
+  double elapsed_ms;
+} dmpt_fermi_info;
+
+size_t dmpt_fermi_workspace_bytes(const dmpt_opts* opts, const dmpt_fermi_opts* fopts, int32_t nobs);
+dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t nobs, float* chi, float* D,
+                                      double* a0, const dmpt_fermi_opts* fopts, const dmpt_opts* opts,
+                                      dmpt_fermi_info* finfo);
+
+/* ---------------------------------------------------------------------------
  * Self-consistent susceptibility (Eq. CP_SCF; Sec. V.C and the Appendix) at
  * zero temperature in an orthonormal basis (Z = I, mu_1 = 0), for an on-site
  * self-consistent field: H = H0 + diag(U_i (n_i - n0_i)), n = s diag(D),

@@ -168,6 +168,46 @@ def susceptibility_nonorth(H, Z, A, nocc: int, *, raise_on_error: bool = True, *
     return chi_p, chi_ao, D, list(a0), info.as_dict()
 
 
+def susceptibility_fermi(H, A, nocc: int, kt: float, *, canonical: bool = True, mu: float = float("nan"),
+                         doublings: int = 0, newton_max: int = 0, count_tol: float = 0.0,
+                         raise_on_error: bool = True, **kw):
+    """Sec. V.B: D = f(H) (Fermi function at k_B T_e = kt) and the
+    temperature-dependent susceptibility chi = s d/dlambda f(H + lambda (A + mu_1 I))
+    by the recursive doubling expansion (dmpt_susceptibility_fermi).  A:
+    (n, n), (nobs, n, n) or None.  Returns (chi or None, D, a0 [nobs], info dict)."""
+    torch = _torch()
+    from ._lib import FermiInfo, FermiOpts
+    n = H.shape[-1]
+    _check_matrix(H, n, "H")
+    nobs = 0
+    single = False
+    if A is not None:
+        _check_matrix(A, n, "A")
+        single = A.dim() == 2
+        nobs = 1 if single else A.shape[0]
+    o = make_opts(n, nocc, **kw)
+    f = FermiOpts(kt=kt, mu=mu, count_tol=count_tol, canonical=1 if canonical else 0, doublings=doublings,
+                  newton_max=newton_max)
+    lib = load()
+    nbytes = int(lib.dmpt_fermi_workspace_bytes(C.byref(o), C.byref(f), nobs))
+    if nbytes == 0:
+        check(1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=H.device)
+    o.workspace, o.workspace_bytes = ws.data_ptr(), nbytes
+    chi = torch.empty((max(nobs, 1), n, n), dtype=torch.float32, device=H.device) if nobs else None
+    D = torch.empty((n, n), dtype=torch.float32, device=H.device)
+    a0 = (C.c_double * max(nobs, 1))()
+    info = FermiInfo()
+    st = lib.dmpt_susceptibility_fermi(C.c_void_p(H.data_ptr()), C.c_void_p(A.data_ptr()) if nobs else None, nobs,
+                                       C.c_void_p(chi.data_ptr()) if nobs else None, C.c_void_p(D.data_ptr()), a0,
+                                       C.byref(f), C.byref(o), C.byref(info))
+    if st != 0 and (raise_on_error or st != 3):
+        check(st)
+    if chi is not None and single:
+        chi = chi[0]
+    return chi, D, list(a0[:nobs]), info.as_dict(nobs)
+
+
 def response(chi, H1, *, stream=None):
     """Eq. dual: out[k, p] = Tr[chi_k H1_p] (FP64).  chi: (n,n)/(K,n,n); H1: (n,n)/(P,n,n)."""
     torch = _torch()

@@ -34,6 +34,7 @@ EXPORTS = [
     "dmpt_scf_response", "dmpt_scf_workspace_bytes", "dmpt_mixer_param_count", "dmpt_mixer_workspace_bytes",
     "dmpt_mixer_init", "dmpt_mixer_forward", "dmpt_mixer_loss_grad", "dmpt_mixer_train",
     "dmpt_nonorth_workspace_bytes", "dmpt_susceptibility_nonorth",
+    "dmpt_fermi_workspace_bytes", "dmpt_susceptibility_fermi",
     "dmpt_sp2_decide", "dmpt_status_string", "dmpt_last_error",
 ]
 
@@ -99,6 +100,22 @@ class SCFInfo(C.Structure):
                 "states": self.states, "residual": list(self.residual[:self.states])}
 
 
+class FermiOpts(C.Structure):
+    _fields_ = [("kt", C.c_double), ("mu", C.c_double), ("count_tol", C.c_double), ("canonical", C.c_int32),
+                ("doublings", C.c_int32), ("newton_max", C.c_int32), ("reserved", C.c_int32)]
+
+
+class FermiInfo(C.Structure):
+    _fields_ = [("mu", C.c_double), ("trace_d", C.c_double), ("emin", C.c_double), ("emax", C.c_double),
+                ("doublings", C.c_int32), ("newton", C.c_int32), ("products", C.c_int32), ("reserved", C.c_int32),
+                ("mu1", C.c_double * 64), ("elapsed_ms", C.c_double)]
+
+    def as_dict(self, nobs: int = 0) -> dict:
+        return {"mu": self.mu, "trace_d": self.trace_d, "emin": self.emin, "emax": self.emax,
+                "doublings": self.doublings, "newton": self.newton, "products": self.products,
+                "mu1": list(self.mu1[:nobs]), "elapsed_ms": self.elapsed_ms}
+
+
 class DMPTError(RuntimeError):
     def __init__(self, status: int, message: str, info: dict | None = None):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
@@ -136,6 +153,11 @@ def load() -> C.CDLL:
     lib.dmpt_susceptibility_nonorth.argtypes = [P, P, P, I32, P, P, P, C.POINTER(D), C.POINTER(Opts),
                                                 C.POINTER(Info)]
     lib.dmpt_susceptibility_nonorth.restype = C.c_int
+    lib.dmpt_fermi_workspace_bytes.argtypes = [C.POINTER(Opts), C.POINTER(FermiOpts), I32]
+    lib.dmpt_fermi_workspace_bytes.restype = C.c_size_t
+    lib.dmpt_susceptibility_fermi.argtypes = [P, P, I32, P, P, C.POINTER(D), C.POINTER(FermiOpts), C.POINTER(Opts),
+                                              C.POINTER(FermiInfo)]
+    lib.dmpt_susceptibility_fermi.restype = C.c_int
     lib.dmpt_response_workspace_bytes.argtypes = [I32, I32, I32]
     lib.dmpt_response_workspace_bytes.restype = SZ
     lib.dmpt_response.argtypes = [P, I32, P, I32, I32, C.POINTER(D), P, P, SZ]

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "dmpt_fermi.h"
 #include "dmpt_internal.h"
 #include "sp2_rule.h"
 
@@ -870,6 +871,256 @@ dmpt_status dmpt_susceptibility_nonorth(const float* H, const float* Z, const fl
       if ((st = from_perp(cperp + k * n2, chi_ao + k * n2)) != DMPT_OK) return st;
   DMPT_HIP(hipStreamSynchronize(s));
   return rs;
+}
+
+// ---------------------------------------------------------------- finite temperature
+
+// Workspace of dmpt_susceptibility_fermi: the bounds part of the plan of an
+// SP2 solve (control block, Lanczos and Gershgorin scratch), then n_pad x
+// n_pad FP32 matrices E, E^2, R, T, V, E_next and, per observable, Y, plus
+// four product temporaries for the response updates, trace partials and
+// a0 partials.
+struct FermiWS {
+  size_t e, e2, r, t, v, en, y, g, sm, u, w, part, a0p, total;
+};
+
+FermiWS fermi_ws(size_t base, int n_pad, int nobs) {
+  FermiWS w;
+  const size_t m = (size_t)n_pad * n_pad * 4;
+  size_t off = align_up(base);
+  w.e = off; off = align_up(off + m);
+  w.e2 = off; off = align_up(off + m);
+  w.r = off; off = align_up(off + m);
+  w.t = off; off = align_up(off + m);
+  w.v = off; off = align_up(off + m);
+  w.en = off; off = align_up(off + m);
+  w.y = off; off = align_up(off + m * nobs);
+  w.g = off; off = align_up(off + m);
+  w.sm = off; off = align_up(off + m);
+  w.u = off; off = align_up(off + m);
+  w.w = off; off = align_up(off + m);
+  w.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)trace_sq_blocks(n_pad));
+  w.a0p = off; off = align_up(off + sizeof(double) * kOutBlocks * (size_t)std::max(nobs, 1));
+  w.total = off;
+  return w;
+}
+
+dmpt_status fermi_check(const dmpt_opts* opts, const dmpt_fermi_opts* f, int nobs, Opts* o, Plan* p) {
+  dmpt_status st = normalise(opts, o);
+  if (st != DMPT_OK) return st;
+  if (!f) return fail(DMPT_ERR_ARG, "fermi options are NULL");
+  if (o->prec != kFP32) return fail(DMPT_ERR_UNSUPPORTED, "the finite-temperature path runs in DMPT_FP32 only");
+  if (nobs < 0 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [0, %d]", nobs, kMaxObs);
+  if (!(std::isfinite(f->kt) && f->kt > 0)) return fail(DMPT_ERR_ARG, "kt must be finite and > 0");
+  if (f->canonical != 0 && f->canonical != 1) return fail(DMPT_ERR_ARG, "canonical must be 0 or 1");
+  if (f->canonical && (o->nocc <= 0 || o->nocc >= o->n))
+    return fail(DMPT_ERR_ARG, "the canonical ensemble needs 0 < nocc < n");
+  if (!f->canonical && !std::isfinite(f->mu)) return fail(DMPT_ERR_ARG, "the grand canonical ensemble needs a finite mu");
+  if (f->doublings < 0 || f->doublings > 40) return fail(DMPT_ERR_ARG, "doublings out of range [0, 40]");
+  if (f->newton_max < 0 || f->newton_max > 200) return fail(DMPT_ERR_ARG, "newton_max out of range [0, 200]");
+  if (!(f->count_tol >= 0) || !std::isfinite(f->count_tol)) return fail(DMPT_ERR_ARG, "count_tol must be finite and >= 0");
+  if (f->reserved != 0) return fail(DMPT_ERR_ARG, "reserved must be 0");
+  make_plan(*o, 0, p);
+  return DMPT_OK;
+}
+
+size_t dmpt_fermi_workspace_bytes(const dmpt_opts* opts, const dmpt_fermi_opts* fopts, int32_t nobs) {
+  Opts o;
+  Plan p;
+  if (fermi_check(opts, fopts, nobs, &o, &p) != DMPT_OK) return 0;
+  return fermi_ws(p.off_x, p.n_pad, nobs).total;
+}
+
+dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t nobs, float* chi, float* D,
+                                      double* a0, const dmpt_fermi_opts* fopts, const dmpt_opts* opts,
+                                      dmpt_fermi_info* finfo) {
+  Opts o;
+  Plan p;
+  dmpt_status st = fermi_check(opts, fopts, nobs, &o, &p);
+  if (st != DMPT_OK) return st;
+  if (!H) return fail(DMPT_ERR_ARG, "H is NULL");
+  if (nobs > 0 && (!A || !chi)) return fail(DMPT_ERR_ARG, "A and chi must not be NULL");
+  const int n = o.n, np = p.n_pad;
+  const FermiWS w = fermi_ws(p.off_x, np, nobs);
+  if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
+  if (o.ws_bytes < w.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, w.total);
+  if (finfo) std::memset(finfo, 0, sizeof(*finfo));
+  hipStream_t s = o.stream;
+  char* ws = o.ws;
+  Ctl* ctl = (Ctl*)(ws + p.off_ctl);
+  float* E = (float*)(ws + w.e);
+  float* E2 = (float*)(ws + w.e2);
+  float* R = (float*)(ws + w.r);
+  float* T = (float*)(ws + w.t);
+  float* V = (float*)(ws + w.v);
+  float* En = (float*)(ws + w.en);
+  float* Y = (float*)(ws + w.y);
+  float* G = (float*)(ws + w.g);
+  float* Sm = (float*)(ws + w.sm);
+  float* U = (float*)(ws + w.u);
+  float* Wm = (float*)(ws + w.w);
+  double* part = (double*)(ws + w.part);
+  const size_t np2 = (size_t)np * np;
+  const int fl = flush_interval(kFP32, np);
+  const double beta = 1.0 / fopts->kt;
+  ScopedEvents ev;
+  DMPT_HIP(hipEventCreate(&ev.e0));
+  DMPT_HIP(hipEventCreate(&ev.e1));
+  DMPT_HIP(hipEventRecord(ev.e0, s));
+
+  // spectral bounds (also the NaN / Inf scan)
+  DMPT_HIP(launch_ctl_reset(ctl, s));
+  st = compute_bounds(o, p, H, ctl, (double*)(ws + p.off_lz), (double2*)(ws + p.off_gersh), s);
+  if (st != DMPT_OK) return st;
+  Ctl hctl;
+  DMPT_HIP(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  if (hctl.nonfinite) return fail(DMPT_ERR_NONFINITE, "H holds NaN or Inf");
+  const double emin = hctl.emin, emax = hctl.emax;
+
+  // traces over the leading n x n block: (Tr M, ||M||_F^2), fixed order
+  auto trace_sq = [&](const float* m, double* tr, double* sq) -> dmpt_status {
+    const int nb = trace_sq_blocks(np);
+    std::vector<double> h(2 * nb);
+    DMPT_HIP(launch_trace_sq(m, n, np, part, s));
+    DMPT_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
+    DMPT_HIP(hipStreamSynchronize(s));
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nb; ++i) { a += h[2 * i]; b += h[2 * i + 1]; }
+    *tr = a;
+    *sq = b;
+    return DMPT_OK;
+  };
+  int products = 0;
+  auto gemm = [&](const float* a, const float* b, float* c, float alpha) -> dmpt_status {
+    ++products;
+    DMPT_HIP(launch_gemm_nt(a, b, c, np, alpha, fl, s));
+    return DMPT_OK;
+  };
+  auto doublings_for = [&](double mu) {
+    if (fopts->doublings > 0) return fopts->doublings;
+    const double wmax = std::max(std::fabs(emax - mu), std::fabs(emin - mu));
+    int m = 1;
+    while (m < 40 && beta * wmax / std::ldexp(1.0, m) > std::ldexp(1.0, -8)) ++m;
+    return m;
+  };
+  // The recursion at mu; with ny > 0 also the responses Y_k (k < ny) of the
+  // observables.  Leaves E_m in E and E_m^2 in E2.
+  auto recursion = [&](double mu, int ny, int* m_out) -> dmpt_status {
+    const int m = doublings_for(mu);
+    *m_out = m;
+    const double c = beta / std::ldexp(1.0, m + 2);
+    const double wmax = std::max(std::fabs(emax - mu), std::fabs(emin - mu));
+    dmpt_status e;
+    DMPT_HIP(launch_fermi_start(H, n, np, -c, mu, E, s));
+    for (int k = 0; k < ny; ++k) DMPT_HIP(launch_fermi_start(A + (size_t)k * n * n, n, np, -c, 0.0, Y + k * np2, s));
+    for (int step = 0; step < m; ++step) {
+      if ((e = gemm(E, E, E2, 1.0f)) != DMPT_OK) return e;
+      // R = (I + 4 E^2)^{-1}: spectrum in [1, b], b from |E_k| <= tanh(2^{k-1-m} beta w) / 2
+      // (with a margin for the linearised start and rounding)
+      const double th = std::tanh(std::ldexp(beta * wmax, step - 1 - m));
+      const double b = 1.0 + std::min(1.0, 1.02 * th * th + 1e-6);
+      const double alpha = 2.0 / (1.0 + b);
+      double err = (b - 1.0) / (b + 1.0);
+      int iters = 0;
+      while (err > 1e-8 && iters < 8) { err *= err; ++iters; }
+      DMPT_HIP(launch_axpby(R, E2, 0.0f, nullptr, 0.0f, (float)alpha, np, np, s));
+      for (int it = 0; it < iters; ++it) {
+        // T = (I + 4 E^2) R, V = R T, R = 2 R - V
+        if ((e = gemm(E2, R, T, 4.0f)) != DMPT_OK) return e;
+        DMPT_HIP(launch_axpby(T, T, 1.0f, R, 1.0f, 0.0f, 0, np, s));
+        if ((e = gemm(R, T, V, 1.0f)) != DMPT_OK) return e;
+        DMPT_HIP(launch_axpby(R, R, 2.0f, V, -1.0f, 0.0f, 0, np, s));
+      }
+      // E_next = 2 E R (symmetrised into En)
+      if ((e = gemm(E, R, V, 2.0f)) != DMPT_OK) return e;
+      DMPT_HIP(launch_symm(V, 0.5f, nullptr, 0.0f, En, np, s));
+      for (int k = 0; k < ny; ++k) {
+        float* y = Y + k * np2;
+        // S = Y E + E Y; U = E_next S; W = 2 Y - 4 U; Y = sym(W R)
+        if ((e = gemm(y, E, G, 1.0f)) != DMPT_OK) return e;
+        DMPT_HIP(launch_symm(G, 1.0f, nullptr, 0.0f, Sm, np, s));
+        if ((e = gemm(En, Sm, U, 1.0f)) != DMPT_OK) return e;
+        DMPT_HIP(launch_axpby(Wm, y, 2.0f, U, -4.0f, 0.0f, 0, np, s));
+        if ((e = gemm(Wm, R, G, 1.0f)) != DMPT_OK) return e;
+        DMPT_HIP(launch_symm(G, 0.5f, nullptr, 0.0f, y, np, s));
+      }
+      std::swap(E, En);
+    }
+    if ((e = gemm(E, E, E2, 1.0f)) != DMPT_OK) return e;
+    return DMPT_OK;
+  };
+
+  // chemical potential
+  double mu = fopts->mu;
+  int newton = 0, m = 0;
+  double tre = 0.0, sqe = 0.0;
+  if (fopts->canonical) {
+    const double nocc = o.nocc;
+    const double tol = fopts->count_tol > 0 ? fopts->count_tol : 1e-6 * n;
+    double lo = emin - 40.0 / beta, hi = emax + 40.0 / beta;
+    if (!std::isfinite(mu) || mu <= lo || mu >= hi) mu = emin + (emax - emin) * nocc / n;
+    const int maxn = fopts->newton_max > 0 ? fopts->newton_max : 40;
+    bool ok = false;
+    for (newton = 1; newton <= maxn; ++newton) {
+      if ((st = recursion(mu, 0, &m)) != DMPT_OK) return st;
+      if ((st = trace_sq(E, &tre, &sqe)) != DMPT_OK) return st;
+      const double count = 0.5 * n + tre;
+      const double slope = beta * (0.25 * n - sqe);   // dTr D / dmu = beta Tr[D - D^2]
+      if (std::fabs(count - nocc) <= tol) { ok = true; break; }
+      if (count < nocc) lo = mu; else hi = mu;
+      double next = slope > 0 ? mu - (count - nocc) / slope : 0.5 * (lo + hi);
+      if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+      mu = next;
+    }
+    if (!ok) return fail(DMPT_ERR_NOT_CONVERGED, "chemical potential: |Tr D - N_occ| above %g after %d steps", tol, maxn);
+  }
+  // final run with the responses
+  products = 0;
+  if ((st = recursion(mu, nobs, &m)) != DMPT_OK) return st;
+  if ((st = trace_sq(E, &tre, &sqe)) != DMPT_OK) return st;
+  const double trdd = 0.25 * n - sqe;   // Tr[D - D^2]
+  std::vector<double> mu1(std::max(nobs, 1), 0.0);
+  for (int k = 0; k < nobs; ++k) {
+    float* y = Y + k * np2;
+    if (fopts->canonical && trdd > 0) {
+      double try_ = 0.0, sqy = 0.0;
+      if ((st = trace_sq(y, &try_, &sqy)) != DMPT_OK) return st;
+      mu1[k] = try_ / (beta * trdd);
+      // chi' = Y + mu_1 chi_gc(I), chi_gc(I) = -beta (D - D^2) = -beta (I/4 - E^2)
+      const float gam = (float)(-mu1[k] * beta);
+      DMPT_HIP(launch_axpby(y, y, 1.0f, E2, -gam, 0.25f * gam, n, np, s));
+    }
+  }
+  // D = I/2 + E (into E2's buffer, no longer needed), outputs and a0 = s Tr[A D]
+  DMPT_HIP(launch_axpby(E2, E, 1.0f, nullptr, 0.0f, 0.5f, n, np, s));
+  double* a0p = (double*)(ws + w.a0p);
+  DMPT_HIP(launch_output(E2, nobs ? Y : nullptr, np2, A, n, np, nobs, D, nobs ? chi : nullptr, o.spin, 0, nullptr,
+                         0, 0, a0p, ctl, s));
+  std::vector<double> hpart((size_t)kOutBlocks * std::max(nobs, 1));
+  if (nobs) DMPT_HIP(hipMemcpyAsync(hpart.data(), a0p, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipEventRecord(ev.e1, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  if (a0)
+    for (int k = 0; k < nobs; ++k) {
+      double t = 0.0;
+      for (int b = 0; b < kOutBlocks; ++b) t += hpart[(size_t)k * kOutBlocks + b];
+      a0[k] = o.spin * t;
+    }
+  if (finfo) {
+    finfo->mu = mu;
+    finfo->trace_d = 0.5 * n + tre;
+    finfo->emin = emin;
+    finfo->emax = emax;
+    finfo->doublings = m;
+    finfo->newton = newton;
+    finfo->products = products;
+    for (int k = 0; k < nobs && k < 64; ++k) finfo->mu1[k] = mu1[k];
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev.e0, ev.e1);
+    finfo->elapsed_ms = ms;
+  }
+  return DMPT_OK;
 }
 
 // Responses are formed in groups of up to kRespObs observables x kRespPert

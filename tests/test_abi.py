@@ -283,3 +283,22 @@ def test_nonorth_sizes_and_validation(lib):
     # NULL inputs are rejected before any device call
     assert lib.dmpt_susceptibility_nonorth(None, None, None, 1, None, None, None, out, C.byref(o), None) == 1
     assert lib.dmpt_susceptibility_nonorth(None, None, None, 0, None, None, None, out, C.byref(o), None) == 1
+
+
+def test_fermi_validation(lib):
+    from paper_2409_17033_amd._lib import FermiOpts
+    o = _opts(lib, 1000, 500)
+    f = FermiOpts(kt=0.01, mu=float("nan"), canonical=1)
+    w = lib.dmpt_fermi_workspace_bytes(C.byref(o), C.byref(f), 2)
+    assert w >= (6 + 2 + 4) * 1024 * 1024 * 4          # E, E^2, R, T, V, E_next, 2 Y, 4 temporaries
+    for bad in (FermiOpts(kt=0.0, canonical=1), FermiOpts(kt=0.01, canonical=2),
+                FermiOpts(kt=0.01, canonical=0, mu=float("nan")), FermiOpts(kt=0.01, canonical=1, doublings=41),
+                FermiOpts(kt=0.01, canonical=1, reserved=1), FermiOpts(kt=0.01, canonical=1, count_tol=-1.0)):
+        assert lib.dmpt_fermi_workspace_bytes(C.byref(o), C.byref(bad), 1) == 0
+    split = _opts(lib, 1000, 500, precision=1)
+    assert lib.dmpt_fermi_workspace_bytes(C.byref(split), C.byref(f), 1) == 0
+    edge = _opts(lib, 1000, 0)                          # canonical needs 0 < nocc < n
+    assert lib.dmpt_fermi_workspace_bytes(C.byref(edge), C.byref(f), 1) == 0
+    out = (C.c_double * 1)()
+    assert lib.dmpt_susceptibility_fermi(None, None, 1, None, None, out, C.byref(f), C.byref(o), None) == 1
+    assert lib.dmpt_susceptibility_fermi(None, None, 1, None, None, out, C.byref(f), C.byref(split), None) == 7

@@ -162,6 +162,23 @@ def banded_gapped(n: int = 4096, nocc: int | None = None, gap: float = 0.1,
     return wl
 
 
+def banded_gapless(n: int = 16384, nocc: int | None = None, half_bandwidth: int = 256, hop_std: float = 0.05,
+                   nobs: int = 32, cfg: int = 5) -> Workload:
+    """Config 5 (finite temperature): random banded H (half-bandwidth 256,
+    hopping ~ N(0, hop_std^2), onsite ~ U(-1, 1)) with no gap opened, and
+    nobs random symmetric Frobenius-normalised observables."""
+    nocc = n // 2 if nocc is None else nocc
+    rng = rng_for(cfg, n)
+    hop = rng.normal(0.0, hop_std, size=(n, n))
+    hop = np.triu(hop, 1) * banded_mask(n, half_bandwidth)
+    h = hop + hop.T
+    h[np.diag_indices(n)] = rng.uniform(-1.0, 1.0, size=n)
+    a = np.stack([_as32(frobenius_normalised(random_symmetric(rng, n))) for _ in range(nobs)]) if nobs \
+        else np.zeros((0, n, n), np.float32)
+    return Workload("banded_gapless", n, nocc, _as32(h), a, np.zeros((0, n, n), np.float32),
+                    {"cfg": cfg, "half_bandwidth": half_bandwidth})
+
+
 def scf_system(n: int = 1024, cfg: int = 4, ntrain: int = 40):
     """Self-consistent response case (config 4): banded gapped H0 (the config-2
     recipe at size n), on-site interactions U_i ~ U(0.5, 1.5), the test
