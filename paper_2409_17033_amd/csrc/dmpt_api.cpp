@@ -997,6 +997,12 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
     DMPT_HIP(launch_gemm_nt(a, b, c, np, alpha, fl, s));
     return DMPT_OK;
   };
+  // products of commuting functions of H (symmetric): upper triangle + mirror
+  auto gemm_sym = [&](const float* a, const float* b, float* c, float alpha) -> dmpt_status {
+    ++products;
+    DMPT_HIP(launch_gemm_nt_sym(a, b, c, np, alpha, fl, s));
+    return DMPT_OK;
+  };
   auto doublings_for = [&](double mu) {
     if (fopts->doublings > 0) return fopts->doublings;
     const double wmax = std::max(std::fabs(emax - mu), std::fabs(emin - mu));
@@ -1015,7 +1021,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
     DMPT_HIP(launch_fermi_start(H, n, np, -c, mu, E, s));
     for (int k = 0; k < ny; ++k) DMPT_HIP(launch_fermi_start(A + (size_t)k * n * n, n, np, -c, 0.0, Y + k * np2, s));
     for (int step = 0; step < m; ++step) {
-      if ((e = gemm(E, E, E2, 1.0f)) != DMPT_OK) return e;
+      if ((e = gemm_sym(E, E, E2, 1.0f)) != DMPT_OK) return e;
       // R = (I + 4 E^2)^{-1}: spectrum in [1, b], b from |E_k| <= tanh(2^{k-1-m} beta w) / 2
       // (with a margin for the linearised start and rounding)
       const double th = std::tanh(std::ldexp(beta * wmax, step - 1 - m));
@@ -1027,14 +1033,13 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
       DMPT_HIP(launch_axpby(R, E2, 0.0f, nullptr, 0.0f, (float)alpha, np, np, s));
       for (int it = 0; it < iters; ++it) {
         // T = (I + 4 E^2) R, V = R T, R = 2 R - V
-        if ((e = gemm(E2, R, T, 4.0f)) != DMPT_OK) return e;
+        if ((e = gemm_sym(E2, R, T, 4.0f)) != DMPT_OK) return e;
         DMPT_HIP(launch_axpby(T, T, 1.0f, R, 1.0f, 0.0f, 0, np, s));
-        if ((e = gemm(R, T, V, 1.0f)) != DMPT_OK) return e;
+        if ((e = gemm_sym(R, T, V, 1.0f)) != DMPT_OK) return e;
         DMPT_HIP(launch_axpby(R, R, 2.0f, V, -1.0f, 0.0f, 0, np, s));
       }
-      // E_next = 2 E R (symmetrised into En)
-      if ((e = gemm(E, R, V, 2.0f)) != DMPT_OK) return e;
-      DMPT_HIP(launch_symm(V, 0.5f, nullptr, 0.0f, En, np, s));
+      // E_next = 2 E R
+      if ((e = gemm_sym(E, R, En, 2.0f)) != DMPT_OK) return e;
       for (int k = 0; k < ny; ++k) {
         float* y = Y + k * np2;
         // S = Y E + E Y; U = E_next S; W = 2 Y - 4 U; Y = sym(W R)
@@ -1047,7 +1052,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
       }
       std::swap(E, En);
     }
-    if ((e = gemm(E, E, E2, 1.0f)) != DMPT_OK) return e;
+    if ((e = gemm_sym(E, E, E2, 1.0f)) != DMPT_OK) return e;
     return DMPT_OK;
   };
 

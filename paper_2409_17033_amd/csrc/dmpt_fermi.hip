@@ -39,15 +39,17 @@ __global__ __launch_bounds__(256) void k_fermi_start(const float* src, int n, in
   }
 }
 
+// One row per block iteration (coalesced, no index division).
 __global__ __launch_bounds__(256) void k_axpby(float* z, const float* x, float a, const float* y, float b, float d,
                                                int nd, int n_pad) {
-  const size_t count = (size_t)n_pad * n_pad;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
-    float v = a * x[e];
-    if (y) v += b * y[e];
-    const size_t i = e / n_pad, j = e % n_pad;
-    if (i == j && (int)i < nd) v += d;
-    z[e] = v;
+  for (int i = blockIdx.x; i < n_pad; i += gridDim.x) {
+    const size_t row = (size_t)i * n_pad;
+    for (int j = threadIdx.x; j < n_pad; j += 256) {
+      float v = a * x[row + j];
+      if (y) v += b * y[row + j];
+      if (i == j && i < nd) v += d;
+      z[row + j] = v;
+    }
   }
 }
 

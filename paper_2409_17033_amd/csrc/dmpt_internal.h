@@ -144,6 +144,10 @@ hipError_t launch_copy_out(const float* src, int n, int n_pad, float* dst, hipSt
 // FP32 MFMA) and zero-padded (optionally transposed) copies.
 hipError_t launch_gemm_nt(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
                           hipStream_t s);
+// The same for a product known to be symmetric: upper-triangle tiles only,
+// then the lower triangle mirrored (exactly symmetric result).
+hipError_t launch_gemm_nt_sym(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
+                              hipStream_t s);
 hipError_t launch_pad(const float* src, int n, int n_pad, float* dst, int transpose, hipStream_t s);
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);
 int stage_k(int prec);   // k values per pipeline stage of the step kernel

@@ -816,22 +816,36 @@ hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s)
 
 // ---------------------------------------------------------------- general products
 
-// C = alpha A B^T over all 256 x 128 tiles of an n_pad x n_pad result; A, B
-// and C are n_pad x n_pad row-major FP32 (zero padded).  These are the
+// C = alpha A B^T over all 256 x 128 tiles of an n_pad x n_pad result (or,
+// with sym, only the tiles (I, J >= 2I) that cover the upper triangle, for a
+// product known to be symmetric); A, B and C are n_pad x n_pad row-major
+// FP32 (zero padded).  These are the
 // congruences of the non-orthonormal basis (Sec. V.A: Z^T H Z, Z^T A Z,
 // Z D Z^T), formed as two NT products each.  Same operand pipeline as the
 // FP32 step kernel (row-major DMA into the four-slot LDS ring, FP32 MFMA
 // 32x32x2, two-level accumulation every `flush` groups of 4 stages); the
 // epilogue stores the tile as is.
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nt(
-    const float* A, const float* B, float* C, int n_pad, float alpha, int flush) {
+    const float* A, const float* B, float* C, int n_pad, float alpha, int flush, int sym) {
   using P = Pipe<kFP32>;
   __shared__ __attribute__((aligned(1024))) char ring0[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring1[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring2[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring3[P::SLOT];
   const int tcols = n_pad / TN;
-  const int ti = blockIdx.x / tcols, tj = blockIdx.x % tcols;
+  int ti, tj;
+  if (sym) {   // row-major order over the triangle tiles
+    int b = blockIdx.x;
+    ti = 0;
+    while (b >= tcols - 2 * ti) {
+      b -= tcols - 2 * ti;
+      ++ti;
+    }
+    tj = 2 * ti + b;
+  } else {
+    ti = blockIdx.x / tcols;
+    tj = blockIdx.x % tcols;
+  }
   const size_t ldb = (size_t)n_pad * 4;
   const uint32_t ldb32 = (uint32_t)ldb;
   const int nst = n_pad / Fmt<kFP32>::K;
@@ -918,7 +932,35 @@ hipError_t launch_gemm_nt(const float* A, const float* B, float* C, int n_pad, f
                           hipStream_t s) {
   if (n_pad <= 0 || n_pad % TM != 0) return hipErrorInvalidValue;
   const int tiles = (n_pad / TM) * (n_pad / TN);
-  hipLaunchKernelGGL(k_gemm_nt, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush);
+  hipLaunchKernelGGL(k_gemm_nt, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, 0);
+  return hipGetLastError();
+}
+
+// Strictly lower triangle of C := transpose of the upper one (64 x 64 blocks
+// through LDS; blocks above the diagonal are read, never written).
+__global__ __launch_bounds__(256) void k_mirror_lower(float* C, int n_pad) {
+  __shared__ float t[64][65];
+  const int bi = blockIdx.y, bj = blockIdx.x;   // destination block (bi >= bj)
+  if (bi < bj) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    t[r][c] = C[(size_t)(bj * 64 + r) * n_pad + bi * 64 + c];   // source block (bj, bi)
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    if (bi == bj && r <= c) continue;
+    C[(size_t)(bi * 64 + r) * n_pad + bj * 64 + c] = t[c][r];
+  }
+}
+
+hipError_t launch_gemm_nt_sym(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
+                              hipStream_t s) {
+  if (n_pad <= 0 || n_pad % TM != 0) return hipErrorInvalidValue;
+  const int tr = n_pad / TM;
+  hipLaunchKernelGGL(k_gemm_nt, dim3(tr * (tr + 1)), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, 1);
+  const int nb = n_pad / 64;
+  hipLaunchKernelGGL(k_mirror_lower, dim3(nb, nb), dim3(256), 0, s, C, n_pad);
   return hipGetLastError();
 }
 
