@@ -228,7 +228,11 @@ dmpt_status dmpt_susceptibility_nonorth(const float* H, const float* Z, const fl
  * Newton steps on Tr D(mu) = N_occ with dTr D/dmu = beta Tr[D - D^2]
  * = beta (n/4 - ||E_m||_F^2), safeguarded by bisection; then
  * mu_1 = Tr Y_m / (beta Tr[D - D^2]) and chi = s (Y_m - mu_1 beta (D - D^2)).
- * All products are FP32 MFMA (DMPT_FP32 is the only precision accepted).
+ * Products: FP32 MFMA (DMPT_FP32) or the FP16 double-half split
+ * (DMPT_SPLIT_FP16: tiled FP16 copies of every operand, scaled by 2^15 for E,
+ * 2^16 for E^2, 2^14 for R and T (entry bounds 1/2, 1/4, 1, 1), and by
+ * 2^15 / ||M||_F for the responses and their intermediates); other
+ * precisions return DMPT_ERR_UNSUPPORTED.
  * H (n x n), A (nobs x n x n) device FP32 symmetric; chi (nobs x n x n) and
  * D (n x n, nullable) device; a0 host (nobs, nullable) = s Tr[A D].  opts:
  * n, nocc, bounds (Lanczos / Gershgorin / given, as for dmpt_sp2_density),

@@ -877,16 +877,17 @@ dmpt_status dmpt_susceptibility_nonorth(const float* H, const float* Z, const fl
 
 // Workspace of dmpt_susceptibility_fermi: the bounds part of the plan of an
 // SP2 solve (control block, Lanczos and Gershgorin scratch), then n_pad x
-// n_pad FP32 matrices E, E^2, R, T, V, E_next and, per observable, Y, plus
-// four product temporaries for the response updates, trace partials and
-// a0 partials.
+// n_pad FP32 matrices E, E^2, R, T, V, E_next and, per observable, Y, four
+// product temporaries, and for the FP16 split the operand copies of E, E^2,
+// R, T, E_next, every Y, S and W; trace and a0 partials.
 struct FermiWS {
-  size_t e, e2, r, t, v, en, y, g, sm, u, w, part, a0p, total;
+  size_t e, e2, r, t, v, en, y, g, sm, u, w, ce, ce2, cr, ct, cen, cy, cs, cw, part, a0p, total;
 };
 
-FermiWS fermi_ws(size_t base, int n_pad, int nobs) {
+FermiWS fermi_ws(size_t base, int n_pad, int nobs, bool split) {
   FermiWS w;
   const size_t m = (size_t)n_pad * n_pad * 4;
+  const size_t mc = split ? m : 0;   // FP16 split copy: 4 bytes per element
   size_t off = align_up(base);
   w.e = off; off = align_up(off + m);
   w.e2 = off; off = align_up(off + m);
@@ -899,6 +900,14 @@ FermiWS fermi_ws(size_t base, int n_pad, int nobs) {
   w.sm = off; off = align_up(off + m);
   w.u = off; off = align_up(off + m);
   w.w = off; off = align_up(off + m);
+  w.ce = off; off = align_up(off + mc);
+  w.ce2 = off; off = align_up(off + mc);
+  w.cr = off; off = align_up(off + mc);
+  w.ct = off; off = align_up(off + mc);
+  w.cen = off; off = align_up(off + mc);
+  w.cy = off; off = align_up(off + mc * nobs);
+  w.cs = off; off = align_up(off + mc);
+  w.cw = off; off = align_up(off + mc);
   w.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)trace_sq_blocks(n_pad));
   w.a0p = off; off = align_up(off + sizeof(double) * kOutBlocks * (size_t)std::max(nobs, 1));
   w.total = off;
@@ -909,7 +918,8 @@ dmpt_status fermi_check(const dmpt_opts* opts, const dmpt_fermi_opts* f, int nob
   dmpt_status st = normalise(opts, o);
   if (st != DMPT_OK) return st;
   if (!f) return fail(DMPT_ERR_ARG, "fermi options are NULL");
-  if (o->prec != kFP32) return fail(DMPT_ERR_UNSUPPORTED, "the finite-temperature path runs in DMPT_FP32 only");
+  if (o->prec != kFP32 && o->prec != kSplitH)
+    return fail(DMPT_ERR_UNSUPPORTED, "the finite-temperature path runs in DMPT_FP32 or DMPT_SPLIT_FP16");
   if (nobs < 0 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [0, %d]", nobs, kMaxObs);
   if (!(std::isfinite(f->kt) && f->kt > 0)) return fail(DMPT_ERR_ARG, "kt must be finite and > 0");
   if (f->canonical != 0 && f->canonical != 1) return fail(DMPT_ERR_ARG, "canonical must be 0 or 1");
@@ -928,8 +938,21 @@ size_t dmpt_fermi_workspace_bytes(const dmpt_opts* opts, const dmpt_fermi_opts* 
   Opts o;
   Plan p;
   if (fermi_check(opts, fopts, nobs, &o, &p) != DMPT_OK) return 0;
-  return fermi_ws(p.off_x, p.n_pad, nobs).total;
+  return fermi_ws(p.off_x, p.n_pad, nobs, o.prec == kSplitH).total;
 }
+
+// An operand of the finite-temperature products: FP32 master, and for the
+// FP16 split its tiled copy at the scale 2^e.
+struct FMat {
+  float* m;
+  void* c;
+  int e;
+};
+
+// Fixed exponents of the FP16 copies (entry bounds x 2^e <= 2^14..2^15):
+// |E| <= 1/2 (E = D - I/2), |E^2| <= 1/4, |R| <= 1 and |T| <= 1 (spectra in
+// [1/2, 1] and [0, 1]); Y, S and W take 2^15 / ||M||_F (|M_ij| <= ||M||_F).
+constexpr int kExpE = 15, kExpE2 = 16, kExpR = 14, kExpT = 14;
 
 dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t nobs, float* chi, float* D,
                                       double* a0, const dmpt_fermi_opts* fopts, const dmpt_opts* opts,
@@ -941,27 +964,27 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   if (!H) return fail(DMPT_ERR_ARG, "H is NULL");
   if (nobs > 0 && (!A || !chi)) return fail(DMPT_ERR_ARG, "A and chi must not be NULL");
   const int n = o.n, np = p.n_pad;
-  const FermiWS w = fermi_ws(p.off_x, np, nobs);
+  const bool split = o.prec == kSplitH;
+  const FermiWS w = fermi_ws(p.off_x, np, nobs, split);
   if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
   if (o.ws_bytes < w.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, w.total);
   if (finfo) std::memset(finfo, 0, sizeof(*finfo));
   hipStream_t s = o.stream;
   char* ws = o.ws;
   Ctl* ctl = (Ctl*)(ws + p.off_ctl);
-  float* E = (float*)(ws + w.e);
-  float* E2 = (float*)(ws + w.e2);
-  float* R = (float*)(ws + w.r);
-  float* T = (float*)(ws + w.t);
-  float* V = (float*)(ws + w.v);
-  float* En = (float*)(ws + w.en);
-  float* Y = (float*)(ws + w.y);
-  float* G = (float*)(ws + w.g);
-  float* Sm = (float*)(ws + w.sm);
-  float* U = (float*)(ws + w.u);
-  float* Wm = (float*)(ws + w.w);
-  double* part = (double*)(ws + w.part);
   const size_t np2 = (size_t)np * np;
-  const int fl = flush_interval(kFP32, np);
+  auto fm = [&](size_t master, size_t copy, size_t k) {
+    return FMat{(float*)(ws + master) + k * np2, split ? (void*)(ws + copy + k * np2 * 4) : nullptr, 0};
+  };
+  FMat E = fm(w.e, w.ce, 0), E2 = fm(w.e2, w.ce2, 0), R = fm(w.r, w.cr, 0), T = fm(w.t, w.ct, 0);
+  FMat En = fm(w.en, w.cen, 0), Sm = fm(w.sm, w.cs, 0), Wm = fm(w.w, w.cw, 0);
+  std::vector<FMat> Y(std::max(nobs, 1));
+  for (int k = 0; k < nobs; ++k) Y[k] = fm(w.y, w.cy, k);
+  float* V = (float*)(ws + w.v);
+  float* G = (float*)(ws + w.g);
+  float* U = (float*)(ws + w.u);
+  double* part = (double*)(ws + w.part);
+  const int fl = flush_interval(split ? kSplitH : kFP32, np);
   const double beta = 1.0 / fopts->kt;
   ScopedEvents ev;
   DMPT_HIP(hipEventCreate(&ev.e0));
@@ -991,16 +1014,31 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
     *sq = b;
     return DMPT_OK;
   };
-  int products = 0;
-  auto gemm = [&](const float* a, const float* b, float* c, float alpha) -> dmpt_status {
-    ++products;
-    DMPT_HIP(launch_gemm_nt(a, b, c, np, alpha, fl, s));
+  // operand copy at a fixed exponent, or at 2^15 / ||M||_F
+  auto refresh = [&](FMat& a, int e) -> dmpt_status {
+    if (!split) return DMPT_OK;
+    a.e = e;
+    DMPT_HIP(launch_split_copy(a.m, a.c, np, e, s));
     return DMPT_OK;
   };
-  // products of commuting functions of H (symmetric): upper triangle + mirror
-  auto gemm_sym = [&](const float* a, const float* b, float* c, float alpha) -> dmpt_status {
+  auto refresh_dyn = [&](FMat& a) -> dmpt_status {
+    if (!split) return DMPT_OK;
+    double tr = 0.0, sq = 0.0;
+    dmpt_status e = trace_sq(a.m, &tr, &sq);
+    if (e != DMPT_OK) return e;
+    const double nrm = std::sqrt(sq);
+    int ex = 0;
+    if (nrm > 0 && std::isfinite(nrm)) ex = std::max(-100, std::min(100, (int)std::floor(std::log2(32768.0 / nrm))));
+    return refresh(a, ex);
+  };
+  int products = 0;
+  // out = alpha a b^T (all tiles, or the symmetric triangle + mirror)
+  auto prod = [&](const FMat& a, const FMat& b, float* out, double alpha, bool sym) -> dmpt_status {
     ++products;
-    DMPT_HIP(launch_gemm_nt_sym(a, b, c, np, alpha, fl, s));
+    if (split)
+      DMPT_HIP(launch_gemm_op(kSplitH, a.c, b.c, out, np, (float)std::ldexp(alpha, -(a.e + b.e)), fl, sym ? 1 : 0, s));
+    else
+      DMPT_HIP(launch_gemm_op(kFP32, a.m, b.m, out, np, (float)alpha, fl, sym ? 1 : 0, s));
     return DMPT_OK;
   };
   auto doublings_for = [&](double mu) {
@@ -1011,17 +1049,22 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
     return m;
   };
   // The recursion at mu; with ny > 0 also the responses Y_k (k < ny) of the
-  // observables.  Leaves E_m in E and E_m^2 in E2.
+  // observables.  Leaves E_m in E.m and E_m^2 in E2.m.
   auto recursion = [&](double mu, int ny, int* m_out) -> dmpt_status {
     const int m = doublings_for(mu);
     *m_out = m;
     const double c = beta / std::ldexp(1.0, m + 2);
     const double wmax = std::max(std::fabs(emax - mu), std::fabs(emin - mu));
     dmpt_status e;
-    DMPT_HIP(launch_fermi_start(H, n, np, -c, mu, E, s));
-    for (int k = 0; k < ny; ++k) DMPT_HIP(launch_fermi_start(A + (size_t)k * n * n, n, np, -c, 0.0, Y + k * np2, s));
+    DMPT_HIP(launch_fermi_start(H, n, np, -c, mu, E.m, s));
+    if ((e = refresh(E, kExpE)) != DMPT_OK) return e;
+    for (int k = 0; k < ny; ++k) {
+      DMPT_HIP(launch_fermi_start(A + (size_t)k * n * n, n, np, -c, 0.0, Y[k].m, s));
+      if ((e = refresh_dyn(Y[k])) != DMPT_OK) return e;
+    }
     for (int step = 0; step < m; ++step) {
-      if ((e = gemm_sym(E, E, E2, 1.0f)) != DMPT_OK) return e;
+      if ((e = prod(E, E, E2.m, 1.0, true)) != DMPT_OK) return e;
+      if ((e = refresh(E2, kExpE2)) != DMPT_OK) return e;
       // R = (I + 4 E^2)^{-1}: spectrum in [1, b], b from |E_k| <= tanh(2^{k-1-m} beta w) / 2
       // (with a margin for the linearised start and rounding)
       const double th = std::tanh(std::ldexp(beta * wmax, step - 1 - m));
@@ -1030,29 +1073,35 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
       double err = (b - 1.0) / (b + 1.0);
       int iters = 0;
       while (err > 1e-8 && iters < 8) { err *= err; ++iters; }
-      DMPT_HIP(launch_axpby(R, E2, 0.0f, nullptr, 0.0f, (float)alpha, np, np, s));
+      DMPT_HIP(launch_axpby(R.m, E2.m, 0.0f, nullptr, 0.0f, (float)alpha, np, np, s));
+      if ((e = refresh(R, kExpR)) != DMPT_OK) return e;
       for (int it = 0; it < iters; ++it) {
         // T = (I + 4 E^2) R, V = R T, R = 2 R - V
-        if ((e = gemm_sym(E2, R, T, 4.0f)) != DMPT_OK) return e;
-        DMPT_HIP(launch_axpby(T, T, 1.0f, R, 1.0f, 0.0f, 0, np, s));
-        if ((e = gemm_sym(R, T, V, 1.0f)) != DMPT_OK) return e;
-        DMPT_HIP(launch_axpby(R, R, 2.0f, V, -1.0f, 0.0f, 0, np, s));
+        if ((e = prod(E2, R, T.m, 4.0, true)) != DMPT_OK) return e;
+        DMPT_HIP(launch_axpby(T.m, T.m, 1.0f, R.m, 1.0f, 0.0f, 0, np, s));
+        if ((e = refresh(T, kExpT)) != DMPT_OK) return e;
+        if ((e = prod(R, T, V, 1.0, true)) != DMPT_OK) return e;
+        DMPT_HIP(launch_axpby(R.m, R.m, 2.0f, V, -1.0f, 0.0f, 0, np, s));
+        if ((e = refresh(R, kExpR)) != DMPT_OK) return e;
       }
       // E_next = 2 E R
-      if ((e = gemm_sym(E, R, En, 2.0f)) != DMPT_OK) return e;
+      if ((e = prod(E, R, En.m, 2.0, true)) != DMPT_OK) return e;
+      if ((e = refresh(En, kExpE)) != DMPT_OK) return e;
       for (int k = 0; k < ny; ++k) {
-        float* y = Y + k * np2;
         // S = Y E + E Y; U = E_next S; W = 2 Y - 4 U; Y = sym(W R)
-        if ((e = gemm(y, E, G, 1.0f)) != DMPT_OK) return e;
-        DMPT_HIP(launch_symm(G, 1.0f, nullptr, 0.0f, Sm, np, s));
-        if ((e = gemm(En, Sm, U, 1.0f)) != DMPT_OK) return e;
-        DMPT_HIP(launch_axpby(Wm, y, 2.0f, U, -4.0f, 0.0f, 0, np, s));
-        if ((e = gemm(Wm, R, G, 1.0f)) != DMPT_OK) return e;
-        DMPT_HIP(launch_symm(G, 0.5f, nullptr, 0.0f, y, np, s));
+        if ((e = prod(Y[k], E, G, 1.0, false)) != DMPT_OK) return e;
+        DMPT_HIP(launch_symm(G, 1.0f, nullptr, 0.0f, Sm.m, np, s));
+        if ((e = refresh_dyn(Sm)) != DMPT_OK) return e;
+        if ((e = prod(En, Sm, U, 1.0, false)) != DMPT_OK) return e;
+        DMPT_HIP(launch_axpby(Wm.m, Y[k].m, 2.0f, U, -4.0f, 0.0f, 0, np, s));
+        if ((e = refresh_dyn(Wm)) != DMPT_OK) return e;
+        if ((e = prod(Wm, R, G, 1.0, false)) != DMPT_OK) return e;
+        DMPT_HIP(launch_symm(G, 0.5f, nullptr, 0.0f, Y[k].m, np, s));
+        if (step + 1 < m && (e = refresh_dyn(Y[k])) != DMPT_OK) return e;
       }
       std::swap(E, En);
     }
-    if ((e = gemm_sym(E, E, E2, 1.0f)) != DMPT_OK) return e;
+    if ((e = prod(E, E, E2.m, 1.0, true)) != DMPT_OK) return e;
     return DMPT_OK;
   };
 
@@ -1069,7 +1118,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
     bool ok = false;
     for (newton = 1; newton <= maxn; ++newton) {
       if ((st = recursion(mu, 0, &m)) != DMPT_OK) return st;
-      if ((st = trace_sq(E, &tre, &sqe)) != DMPT_OK) return st;
+      if ((st = trace_sq(E.m, &tre, &sqe)) != DMPT_OK) return st;
       const double count = 0.5 * n + tre;
       const double slope = beta * (0.25 * n - sqe);   // dTr D / dmu = beta Tr[D - D^2]
       if (std::fabs(count - nocc) <= tol) { ok = true; break; }
@@ -1083,25 +1132,24 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   // final run with the responses
   products = 0;
   if ((st = recursion(mu, nobs, &m)) != DMPT_OK) return st;
-  if ((st = trace_sq(E, &tre, &sqe)) != DMPT_OK) return st;
+  if ((st = trace_sq(E.m, &tre, &sqe)) != DMPT_OK) return st;
   const double trdd = 0.25 * n - sqe;   // Tr[D - D^2]
   std::vector<double> mu1(std::max(nobs, 1), 0.0);
   for (int k = 0; k < nobs; ++k) {
-    float* y = Y + k * np2;
     if (fopts->canonical && trdd > 0) {
       double try_ = 0.0, sqy = 0.0;
-      if ((st = trace_sq(y, &try_, &sqy)) != DMPT_OK) return st;
+      if ((st = trace_sq(Y[k].m, &try_, &sqy)) != DMPT_OK) return st;
       mu1[k] = try_ / (beta * trdd);
       // chi' = Y + mu_1 chi_gc(I), chi_gc(I) = -beta (D - D^2) = -beta (I/4 - E^2)
       const float gam = (float)(-mu1[k] * beta);
-      DMPT_HIP(launch_axpby(y, y, 1.0f, E2, -gam, 0.25f * gam, n, np, s));
+      DMPT_HIP(launch_axpby(Y[k].m, Y[k].m, 1.0f, E2.m, -gam, 0.25f * gam, n, np, s));
     }
   }
-  // D = I/2 + E (into E2's buffer, no longer needed), outputs and a0 = s Tr[A D]
-  DMPT_HIP(launch_axpby(E2, E, 1.0f, nullptr, 0.0f, 0.5f, n, np, s));
+  // D = I/2 + E (into E^2's buffer, no longer needed), outputs and a0 = s Tr[A D]
+  DMPT_HIP(launch_axpby(E2.m, E.m, 1.0f, nullptr, 0.0f, 0.5f, n, np, s));
   double* a0p = (double*)(ws + w.a0p);
-  DMPT_HIP(launch_output(E2, nobs ? Y : nullptr, np2, A, n, np, nobs, D, nobs ? chi : nullptr, o.spin, 0, nullptr,
-                         0, 0, a0p, ctl, s));
+  DMPT_HIP(launch_output(E2.m, nobs ? Y[0].m : nullptr, np2, A, n, np, nobs, D, nobs ? chi : nullptr, o.spin, 0,
+                         nullptr, 0, 0, a0p, ctl, s));
   std::vector<double> hpart((size_t)kOutBlocks * std::max(nobs, 1));
   if (nobs) DMPT_HIP(hipMemcpyAsync(hpart.data(), a0p, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s));
   DMPT_HIP(hipEventRecord(ev.e1, s));

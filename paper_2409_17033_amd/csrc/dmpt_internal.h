@@ -148,6 +148,13 @@ hipError_t launch_gemm_nt(const float* A, const float* B, float* C, int n_pad, f
 // then the lower triangle mirrored (exactly symmetric result).
 hipError_t launch_gemm_nt_sym(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
                               hipStream_t s);
+// General form: operands FP32 row-major (prec = kFP32) or tiled FP16 split
+// copies (prec = kSplitH, written by launch_split_copy); sym as above.
+hipError_t launch_gemm_op(int prec, const void* A, const void* B, float* C, int n_pad, float alpha, int flush,
+                          int sym, hipStream_t s);
+// Tiled FP16 split copy (the kSplitH operand format) of an n_pad x n_pad FP32
+// matrix scaled by 2^e.
+hipError_t launch_split_copy(const float* src, void* dst, int n_pad, int e, hipStream_t s);
 hipError_t launch_pad(const float* src, int n, int n_pad, float* dst, int transpose, hipStream_t s);
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);
 int stage_k(int prec);   // k values per pipeline stage of the step kernel

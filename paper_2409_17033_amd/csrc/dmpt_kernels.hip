@@ -818,16 +818,19 @@ hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s)
 
 // C = alpha A B^T over all 256 x 128 tiles of an n_pad x n_pad result (or,
 // with sym, only the tiles (I, J >= 2I) that cover the upper triangle, for a
-// product known to be symmetric); A, B and C are n_pad x n_pad row-major
-// FP32 (zero padded).  These are the
-// congruences of the non-orthonormal basis (Sec. V.A: Z^T H Z, Z^T A Z,
-// Z D Z^T), formed as two NT products each.  Same operand pipeline as the
-// FP32 step kernel (row-major DMA into the four-slot LDS ring, FP32 MFMA
-// 32x32x2, two-level accumulation every `flush` groups of 4 stages); the
-// epilogue stores the tile as is.
+// product known to be symmetric); C is n_pad x n_pad row-major FP32 (zero
+// padded).  The operands are FP32 row-major (PREC = kFP32) or tiled FP16
+// split copies (PREC = kSplitH; alpha then carries the 2^-(s_a + s_b) that
+// undoes their scales).  Used for the congruences of the non-orthonormal
+// basis (Sec. V.A: Z^T H Z, Z^T A Z, Z D Z^T, two NT products each) and the
+// products of the finite-temperature recursion (Sec. V.B).  Same operand
+// pipeline as the step kernel (DMA into the four-slot LDS ring, MFMA,
+// two-level accumulation every `flush` groups of 4 stages); the epilogue
+// stores the tile as is.
+template <int PREC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_nt(
-    const float* A, const float* B, float* C, int n_pad, float alpha, int flush, int sym) {
-  using P = Pipe<kFP32>;
+    const void* A, const void* B, float* C, int n_pad, float alpha, int flush, int sym) {
+  using P = Pipe<PREC>;
   __shared__ __attribute__((aligned(1024))) char ring0[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring1[P::SLOT];
   __shared__ __attribute__((aligned(1024))) char ring2[P::SLOT];
@@ -846,9 +849,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     ti = blockIdx.x / tcols;
     tj = blockIdx.x % tcols;
   }
-  const size_t ldb = (size_t)n_pad * 4;
+  // row block I / J starts at the same byte offset in the row-major and the
+  // tiled layouts (rows * ldb, or row blocks * nst chunks of 128 rows)
+  const size_t ldb = (size_t)n_pad * operand_bytes(PREC);
   const uint32_t ldb32 = (uint32_t)ldb;
-  const int nst = n_pad / Fmt<kFP32>::K;
+  const int nst = n_pad / Fmt<PREC>::K;
   const char* a0 = (const char*)A + (size_t)ti * TM * ldb;
   const char* b0 = (const char*)B + (size_t)tj * TN * ldb;
   const int lane = threadIdx.x & 63;
@@ -866,14 +871,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     }
   // stages past the end re-fetch stage 0 into a slot that is never read again
   auto dma = [&](LDS_AS char* slot, int s) {
-    const size_t kb = (size_t)(s < nst ? s : 0) * P::RB;
-    dma_stage_rows<kFP32>(slot, a0 + kb, b0 + kb, ldb32, wave, lane);
+    const int st = s < nst ? s : 0;
+    if constexpr (P::TILED) {
+      const char* ca = a0 + (size_t)st * P::CHUNK;
+      dma_stage_tiled<PREC>(slot, ca, ca + (size_t)nst * P::CHUNK, b0 + (size_t)st * P::CHUNK, wave, lane);
+    } else {
+      const size_t kb = (size_t)st * P::RB;
+      dma_stage_rows<PREC>(slot, a0 + kb, b0 + kb, ldb32, wave, lane);
+    }
   };
   LDS_AS char* R0 = (LDS_AS char*)ring0;
   LDS_AS char* R1 = (LDS_AS char*)ring1;
   LDS_AS char* R2 = (LDS_AS char*)ring2;
   LDS_AS char* R3 = (LDS_AS char*)ring3;
-  Ops<kFP32> o0, o1;
+  Ops<PREC> o0, o1;
   dma(R0, 0);
   dma(R1, 1);
   dma(R2, 2);
@@ -881,15 +892,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   barrier_nofence();
   dma(R3, 3);
   __builtin_amdgcn_sched_barrier(0);
-  read_ops<kFP32>(R0, o0, rowA, rowB, h);
+  read_ops<PREC>(R0, o0, rowA, rowB, h);
 #define DMPT_GITER(S_, NEXT, REFILL, OC, ON)              \
   {                                                       \
     wait_vm<2 * P::L, true>();                            \
     barrier_nofence();                                    \
     dma(REFILL, (S_) + 4);                                \
     __builtin_amdgcn_sched_barrier(0);                    \
-    read_ops<kFP32>(NEXT, ON, rowA, rowB, h);             \
-    mma_ops<kFP32>(OC, acc);                              \
+    read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
+    mma_ops<PREC>(OC, acc);                               \
   }
   const int fl4 = flush > 0 ? flush : 1 << 30;
   int since = 0;
@@ -932,7 +943,7 @@ hipError_t launch_gemm_nt(const float* A, const float* B, float* C, int n_pad, f
                           hipStream_t s) {
   if (n_pad <= 0 || n_pad % TM != 0) return hipErrorInvalidValue;
   const int tiles = (n_pad / TM) * (n_pad / TN);
-  hipLaunchKernelGGL(k_gemm_nt, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, 0);
+  hipLaunchKernelGGL(k_gemm_nt<kFP32>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, 0);
   return hipGetLastError();
 }
 
@@ -956,11 +967,23 @@ __global__ __launch_bounds__(256) void k_mirror_lower(float* C, int n_pad) {
 
 hipError_t launch_gemm_nt_sym(const float* A, const float* B, float* C, int n_pad, float alpha, int flush,
                               hipStream_t s) {
+  return launch_gemm_op(kFP32, A, B, C, n_pad, alpha, flush, 1, s);
+}
+
+hipError_t launch_gemm_op(int prec, const void* A, const void* B, float* C, int n_pad, float alpha, int flush,
+                          int sym, hipStream_t s) {
   if (n_pad <= 0 || n_pad % TM != 0) return hipErrorInvalidValue;
   const int tr = n_pad / TM;
-  hipLaunchKernelGGL(k_gemm_nt, dim3(tr * (tr + 1)), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, 1);
-  const int nb = n_pad / 64;
-  hipLaunchKernelGGL(k_mirror_lower, dim3(nb, nb), dim3(256), 0, s, C, n_pad);
+  const int tiles = sym ? tr * (tr + 1) : (n_pad / TM) * (n_pad / TN);
+  switch (prec) {
+    case kFP32: hipLaunchKernelGGL(k_gemm_nt<kFP32>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
+    case kSplitH: hipLaunchKernelGGL(k_gemm_nt<kSplitH>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (sym) {
+    const int nb = n_pad / 64;
+    hipLaunchKernelGGL(k_mirror_lower, dim3(nb, nb), dim3(256), 0, s, C, n_pad);
+  }
   return hipGetLastError();
 }
 
@@ -1227,6 +1250,24 @@ __global__ __launch_bounds__(256) void k_resplit(int prec, MatRef m, int n_pad) 
     const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
     store_group8(prec, dst, n_pad, (int)r, c0, v, sc);
   }
+}
+
+// Tiled FP16 split copy of one n_pad x n_pad FP32 matrix at the scale 2^e.
+__global__ __launch_bounds__(256) void k_split_copy(const float* src, char* dst, int n_pad, float sc) {
+  const size_t ngroups = (size_t)n_pad * n_pad / 8;
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < ngroups; g += (size_t)gridDim.x * 256) {
+    const size_t r = g / (n_pad / 8);
+    const int c0 = (int)(g % (n_pad / 8)) * 8;
+    const f32x4 a = *(const f32x4*)(src + r * n_pad + c0);
+    const f32x4 b = *(const f32x4*)(src + r * n_pad + c0 + 4);
+    const float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    store_group8_t<kSplitH>(dst, n_pad / Fmt<kSplitH>::K, (int)r, c0, v, sc);
+  }
+}
+
+hipError_t launch_split_copy(const float* src, void* dst, int n_pad, int e, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_copy, dim3(2048), dim3(256), 0, s, src, (char*)dst, n_pad, ldexpf(1.0f, e));
+  return hipGetLastError();
 }
 
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s) {

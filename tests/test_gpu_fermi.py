@@ -6,7 +6,8 @@ Cases: config-5-like gapless banded H (half-bandwidth 256 scaled down to
 n = 1000, 4 observables batched) at kT = 0.01 and 0.05, canonical and grand
 canonical; the low-temperature limit on a gapped H equals the zero-temperature
 path; the duality Tr[chi_A B] = Tr[A chi_B]; batched observables equal single
-runs bit for bit.  Tolerance 2e-5 relative Frobenius: FP32 products through
+runs bit for bit; FP32 and FP16 double-half split products.  Tolerance
+2e-5 relative Frobenius: FP32 (or 22-bit split) products through
 m ~ 16 doubling steps, each with up to five Newton-Schulz products, plus the
 linearised start (relative (beta w / 2^m)^2 / 12 <= 2e-6 with the default m).
 """
@@ -32,12 +33,14 @@ def c5():
     return W.banded_gapless(1000, half_bandwidth=256, nobs=4)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16"])
 @pytest.mark.parametrize("kt", [0.01, 0.05])
-def test_canonical_matches_oracle(gpu, c5, kt):
+def test_canonical_matches_oracle(gpu, c5, kt, prec):
     import paper_2409_17033_amd as dm
     wl = c5
     h = wl.H.astype(np.float64)
-    chi, D, a0, info = dm.susceptibility_fermi(_dev(wl.H, gpu), _dev(wl.A, gpu), wl.nocc, kt, bounds="gershgorin")
+    chi, D, a0, info = dm.susceptibility_fermi(_dev(wl.H, gpu), _dev(wl.A, gpu), wl.nocc, kt, bounds="gershgorin",
+                                               precision=prec)
     d_ref, mu_ref = fo.fermi_density(h, wl.nocc, 1.0 / kt)
     assert abs(info["mu"] - mu_ref) <= 1e-4 * (info["emax"] - info["emin"])
     ed = cf.rel_frobenius(D.double().cpu().numpy(), d_ref)
@@ -48,7 +51,7 @@ def test_canonical_matches_oracle(gpu, c5, kt):
         assert abs(info["mu1"][k] - mu1) <= 1e-4 * max(1.0, abs(mu1))
         assert abs(a0[k] - 2.0 * np.sum(wl.A[k].astype(np.float64) * d_ref)) <= TOL * np.linalg.norm(d_ref) * 2
         assert abs(float(chi[k].double().trace())) <= 1e-4 * np.linalg.norm(ref)
-    print(f"\nkT={kt}: m={info['doublings']} newton={info['newton']} products={info['products']} mu={info['mu']:.6f} "
+    print(f"\n{prec} kT={kt}: m={info['doublings']} newton={info['newton']} products={info['products']} mu={info['mu']:.6f} "
           f"errD {ed:.2e} errchi {max(errs):.2e} {info['elapsed_ms']:.1f} ms")
     assert ed <= TOL and max(errs) <= TOL
     assert abs(info["trace_d"] - wl.nocc) <= 1e-6 * wl.n + 1e-9
