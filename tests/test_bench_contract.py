@@ -1,0 +1,34 @@
+"""Host-side checks of bench.py's contract (no GPU): more than one GPU is
+refused with a message, and the committed HBM-traffic figure is used only
+while the kernel sources hash to the value recorded with it."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_figure_follows_the_kernel_sources(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    committed = bench.measured_traffic("split_fp16", 8192)
+    assert committed is None or committed > 0
+    # a copy of the tree whose kernel source differs: the figure is not used
+    (tmp_path / "profiles").mkdir()
+    src = os.path.join(ROOT, "profiles", "k_step_split_fp16_n8192_traffic.md")
+    if os.path.exists(src):
+        (tmp_path / "profiles" / "k_step_split_fp16_n8192_traffic.md").write_text(open(src).read())
+    csrc = tmp_path / "paper_2409_17033_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "dmpt_kernels.hip").write_text("// changed\n")
+    (csrc / "dmpt_internal.h").write_text("// changed\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("split_fp16", 8192) is None
+    assert bench.measured_traffic("no_such_precision", 8192) is None
