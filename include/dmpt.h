@@ -292,7 +292,14 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
  * info (optional) describes the SP2 recursion of H0; sinfo (optional) the
  * self-consistent loop.  NOT_CONVERGED when max_iter is reached (chi then
  * holds the last iterate). */
-typedef enum dmpt_mixer { DMPT_MIX_LINEAR = 0, DMPT_MIX_ANDERSON = 1, DMPT_MIX_LEARNED = 2 } dmpt_mixer;
+typedef enum dmpt_mixer {
+  DMPT_MIX_LINEAR = 0,
+  DMPT_MIX_ANDERSON = 1,
+  DMPT_MIX_LEARNED = 2,
+  DMPT_MIX_LEARNED_ANDERSON = 3   /* Anderson extrapolation with the network as its preconditioner:
+                                     vb = v - sum_j gamma_j dV_j, rb = r - sum_j gamma_j dR_j, then the
+                                     LEARNED step from (vb, rb); judged like LEARNED */
+} dmpt_mixer;
 
 #define DMPT_MAX_SCF 1024
 

@@ -242,7 +242,8 @@ def scf_response(H0, U, A, nocc: int, *, mixer: str = "linear", max_iter: int = 
                  raise_on_error: bool = True, **kw):
     """Eq. CP_SCF: self-consistent chi = s chi', chi' = L[A + G(chi')], G(X) = diag(U s diag X).
 
-    mixer: "linear" (c_mix = mix), "anderson" or "learned" (net: a mixer.Mixer).
+    mixer: "linear" (c_mix = mix), "anderson", "learned" (net: a mixer.Mixer) or
+    "learned_anderson" (Anderson extrapolation with the network as preconditioner).
     Returns (chi, scf_info dict, info dict of the SP2 recursion); with
     record=True also (v, r) of every accepted state, each (states, n).
     """
@@ -253,7 +254,7 @@ def scf_response(H0, U, A, nocc: int, *, mixer: str = "linear", max_iter: int = 
     _check_matrix(A, n, "A")
     o = make_opts(n, nocc, sweep="adjoint", **kw)
     sopt = SCFOpts(max_iter=max_iter, mixer=MIXER[mixer], mix=mix, tol=tol, anderson_depth=anderson_depth)
-    if mixer == "learned":
+    if mixer in ("learned", "learned_anderson"):
         if net is None:
             raise ValueError("the learned mixer needs net=Mixer(...)")
         sopt.mlp_hidden, sopt.mlp_window = net.hidden, net.window

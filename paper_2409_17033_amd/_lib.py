@@ -80,7 +80,7 @@ class Info(C.Structure):
         }
 
 
-MIXER = {"linear": 0, "anderson": 1, "learned": 2}
+MIXER = {"linear": 0, "anderson": 1, "learned": 2, "learned_anderson": 3}
 DMPT_MAX_SCF = 1024
 
 

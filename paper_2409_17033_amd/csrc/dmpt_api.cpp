@@ -1257,8 +1257,16 @@ dmpt_status mixer_check(int n, int w, int h, int batch, void* ws, size_t wsb, Mi
 
 struct ScfWS {
   size_t run_bytes;
-  size_t ca, cw[2], wmat, da, v, f, r, vt, ft, rt, x, y, mlp, dv, dr, tab, coef, dot, total;
+  size_t ca, cw[2], wmat, da, v, f, r, vt, ft, rt, vb, rb, x, y, mlp, dv, dr, tab, coef, dot, total;
 };
+
+// History depth and hidden width the mixer uses (0 when it uses none).
+int scf_depth(const dmpt_scf_opts* scf) {
+  return scf->mixer == DMPT_MIX_ANDERSON || scf->mixer == DMPT_MIX_LEARNED_ANDERSON ? scf->anderson_depth : 0;
+}
+int scf_hidden(const dmpt_scf_opts* scf) {
+  return scf->mixer == DMPT_MIX_LEARNED || scf->mixer == DMPT_MIX_LEARNED_ANDERSON ? scf->mlp_hidden : 0;
+}
 
 ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
   ScfWS w;
@@ -1276,6 +1284,8 @@ ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
   w.vt = off; off += vec;
   w.ft = off; off += vec;
   w.rt = off; off += vec;
+  w.vb = off; off += vec;
+  w.rb = off; off += vec;
   w.x = off; off += align_up((size_t)n * 4);
   w.y = off; off += align_up((size_t)n * 4);
   w.mlp = off; off += hidden > 0 ? align_up(mixer_scratch_floats(n, window, hidden, 1) * 4) : 0;
@@ -1296,11 +1306,13 @@ dmpt_status scf_check(const dmpt_opts* opts, const dmpt_scf_opts* scf, Opts* o, 
     return fail(DMPT_ERR_ARG, "scf max_iter out of range [1, %d]", DMPT_MAX_SCF);
   if (!(scf->mix > 0 && scf->mix <= 1)) return fail(DMPT_ERR_ARG, "scf mix must be in (0, 1]");
   if (!(scf->tol > 0)) return fail(DMPT_ERR_ARG, "scf tol must be > 0");
-  if (scf->mixer < DMPT_MIX_LINEAR || scf->mixer > DMPT_MIX_LEARNED)
+  if (scf->mixer < DMPT_MIX_LINEAR || scf->mixer > DMPT_MIX_LEARNED_ANDERSON)
     return fail(DMPT_ERR_ARG, "unknown mixer %d", scf->mixer);
-  if (scf->mixer == DMPT_MIX_ANDERSON && (scf->anderson_depth < 1 || scf->anderson_depth > 16))
+  const bool anderson = scf->mixer == DMPT_MIX_ANDERSON || scf->mixer == DMPT_MIX_LEARNED_ANDERSON;
+  const bool learned = scf->mixer == DMPT_MIX_LEARNED || scf->mixer == DMPT_MIX_LEARNED_ANDERSON;
+  if (anderson && (scf->anderson_depth < 1 || scf->anderson_depth > 16))
     return fail(DMPT_ERR_ARG, "anderson_depth out of range [1, 16]");
-  if (scf->mixer == DMPT_MIX_LEARNED &&
+  if (learned &&
       (!scf->mlp_params || !mixer_sizes_ok(o->n, scf->mlp_window, scf->mlp_hidden, 1)))
     return fail(DMPT_ERR_ARG, "the learned mixer needs mlp_params and a valid mlp_window / mlp_hidden");
   if (scf->reserved != 0) return fail(DMPT_ERR_ARG, "scf reserved must be 0");
@@ -1434,8 +1446,7 @@ size_t dmpt_scf_workspace_bytes(const dmpt_opts* opts, const dmpt_scf_opts* scf)
   dmpt_opts o2;
   size_t run_bytes = 0;
   if (scf_check(opts, scf, &o, &o2, &run_bytes) != DMPT_OK) return 0;
-  return scf_ws(run_bytes, o.n, scf->mixer == DMPT_MIX_ANDERSON ? scf->anderson_depth : 0, scf->mlp_window,
-                scf->mixer == DMPT_MIX_LEARNED ? scf->mlp_hidden : 0).total;
+  return scf_ws(run_bytes, o.n, scf_depth(scf), scf->mlp_window, scf_hidden(scf)).total;
 }
 
 dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, float* chi,
@@ -1448,8 +1459,8 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
   if (st != DMPT_OK) return st;
   if (!H0 || !U || !A || !chi) return fail(DMPT_ERR_ARG, "H0, U, A and chi must not be NULL");
   const int n = o.n;
-  const int depth = scf->mixer == DMPT_MIX_ANDERSON ? scf->anderson_depth : 0;
-  const ScfWS w = scf_ws(run_bytes, n, depth, scf->mlp_window, scf->mixer == DMPT_MIX_LEARNED ? scf->mlp_hidden : 0);
+  const int depth = scf_depth(scf);
+  const ScfWS w = scf_ws(run_bytes, n, depth, scf->mlp_window, scf_hidden(scf));
   if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
   if (o.ws_bytes < w.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, w.total);
   if (sinfo) std::memset(sinfo, 0, sizeof(*sinfo));
@@ -1511,22 +1522,28 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
   while (!converged && evals < scf->max_iter) {
     // proposal
     bool special = false;
-    if (scf->mixer == DMPT_MIX_LEARNED && rn > 0) {
+    const bool learned = scf->mixer == DMPT_MIX_LEARNED || scf->mixer == DMPT_MIX_LEARNED_ANDERSON;
+    const bool anderson = scf->mixer == DMPT_MIX_ANDERSON || scf->mixer == DMPT_MIX_LEARNED_ANDERSON;
+    // the learned step from (vv, rr) with ||rr|| = rrn:
+    // vt = vv + mix rr + (rrn / sqrt(n)) net(sqrt(n) rr / rrn)
+    auto learned_step = [&](const double* vv, const double* rr, double rrn) -> dmpt_status {
       const double sq = std::sqrt((double)n);
-      DMPT_HIP(scf_to_float(xf, r, sq / rn, n, s));
+      DMPT_HIP(scf_to_float(xf, rr, sq / rrn, n, s));
       DMPT_HIP(mixer_forward(scf->mlp_params, scf->mlp_window, scf->mlp_hidden, U, n, xf, 1, yf,
                              (float*)(ws + w.mlp), s));
-      DMPT_HIP(scf_step(vt, v, r, scf->mix, yf, rn / sq, n, s));
-      special = true;
-    } else if (scf->mixer == DMPT_MIX_ANDERSON && hist > 0) {
-      // gamma = argmin || r - sum_j gamma_j dR_j ||; v' = v + mix r - sum_j gamma_j (dV_j + mix dR_j)
+      DMPT_HIP(scf_step(vt, vv, rr, scf->mix, yf, rrn / sq, n, s));
+      return DMPT_OK;
+    };
+    auto dr = [&](int i) { return (const double*)(ws + w.dr) + (size_t)i * n; };
+    auto dv = [&](int i) { return (const double*)(ws + w.dv) + (size_t)i * n; };
+    // gamma = argmin || r - sum_j gamma_j dR_j || over the history
+    auto anderson_gamma = [&](std::vector<double>* gamma) -> dmpt_status {
       const int k = hist;
       std::vector<std::pair<int, int>> pairs;
       for (int i = 0; i < k; ++i)
         for (int j = i; j < k; ++j) pairs.emplace_back(i, j);
       // the Gram matrix dR^T dR and dR^T r, 16 dot products per pass
       std::vector<double> g(k * k), b(k);
-      auto dr = [&](int i) { return (const double*)(ws + w.dr) + (size_t)i * n; };
       for (size_t base = 0; base < pairs.size() + k; base += 16) {
         std::vector<const void*> xs, ys;
         for (size_t e = base; e < std::min(pairs.size() + k, base + 16); ++e) {
@@ -1556,20 +1573,58 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
           }
         }
       }
-      std::vector<double> gamma;
-      small_solve(g, b, k, &gamma);
-      std::vector<const void*> vecs = {v, r};
-      std::vector<double> cs = {1.0, scf->mix};
-      for (int j = 0; j < k; ++j) {
-        vecs.push_back((const double*)(ws + w.dv) + (size_t)j * n);
-        cs.push_back(-gamma[j]);
-        vecs.push_back(dr(j));
-        cs.push_back(-scf->mix * gamma[j]);
-      }
+      small_solve(g, b, k, gamma);
+      return DMPT_OK;
+    };
+    // out = sum_q c_q x_q (device vectors), synchronised
+    auto lincomb = [&](double* out, const std::vector<const void*>& vecs, const std::vector<double>& cs) -> dmpt_status {
       DMPT_HIP(hipMemcpyAsync(tab, vecs.data(), vecs.size() * sizeof(void*), hipMemcpyHostToDevice, s));
       DMPT_HIP(hipMemcpyAsync(coef, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      DMPT_HIP(scf_lincomb(vt, (const double* const*)tab, coef, (int)vecs.size(), n, s));
+      DMPT_HIP(scf_lincomb(out, (const double* const*)tab, coef, (int)vecs.size(), n, s));
       DMPT_HIP(hipStreamSynchronize(s));
+      return DMPT_OK;
+    };
+    if (anderson && hist > 0) {
+      std::vector<double> gamma;
+      if ((st = anderson_gamma(&gamma)) != DMPT_OK) return st;
+      if (!learned) {
+        // v' = v + mix r - sum_j gamma_j (dV_j + mix dR_j)
+        std::vector<const void*> vecs = {v, r};
+        std::vector<double> cs = {1.0, scf->mix};
+        for (int j = 0; j < hist; ++j) {
+          vecs.push_back(dv(j));
+          cs.push_back(-gamma[j]);
+          vecs.push_back(dr(j));
+          cs.push_back(-scf->mix * gamma[j]);
+        }
+        if ((st = lincomb(vt, vecs, cs)) != DMPT_OK) return st;
+        special = true;
+      } else {
+        // the learned step from the extrapolated state and residual
+        // vb = v - sum_j gamma_j dV_j, rb = r - sum_j gamma_j dR_j
+        std::vector<const void*> vv = {v}, rr = {r};
+        std::vector<double> cv = {1.0}, cr = {1.0};
+        for (int j = 0; j < hist; ++j) {
+          vv.push_back(dv(j));
+          cv.push_back(-gamma[j]);
+          rr.push_back(dr(j));
+          cr.push_back(-gamma[j]);
+        }
+        double* vb = (double*)(ws + w.vb);
+        double* rb = (double*)(ws + w.rb);
+        if ((st = lincomb(vb, vv, cv)) != DMPT_OK) return st;
+        if ((st = lincomb(rb, rr, cr)) != DMPT_OK) return st;
+        double rbn = 0, unused = 0;
+        if ((st = norms(rb, rb, &rbn, &unused)) != DMPT_OK) return st;
+        if (rbn > 0) {
+          if ((st = learned_step(vb, rb, rbn)) != DMPT_OK) return st;
+          special = true;
+        } else {
+          DMPT_HIP(scf_step(vt, v, r, scf->mix, nullptr, 0.0, n, s));
+        }
+      }
+    } else if (learned && rn > 0) {
+      if ((st = learned_step(v, r, rn)) != DMPT_OK) return st;
       special = true;
     } else {
       DMPT_HIP(scf_step(vt, v, r, scf->mix, nullptr, 0.0, n, s));

@@ -160,7 +160,7 @@ def test_learned_mixer_gain_config4(gpu, c4):
     net, report = train_mixer(H, U, obs[:72], wl.nocc, window=32, hidden=256, rounds=2)
     print(f"\ntraining rounds (pairs, loss, mean evaluations): {report['rounds']}, chosen {report['chosen']}")
     held = [torch.from_numpy(wl.A[0]).to(gpu)] + obs[72:80]
-    ev = {"linear": [], "anderson": [], "learned": []}
+    ev = {"linear": [], "anderson": [], "learned": [], "learned_anderson": []}
     for j, a in enumerate(held):
         chis = {}
         for mixer in ev:
@@ -168,8 +168,9 @@ def test_learned_mixer_gain_config4(gpu, c4):
             assert sinfo["converged"], (j, mixer)
             ev[mixer].append(sinfo["iters"])
             chis[mixer] = chi.double().cpu().numpy()
-        for k in ("anderson", "learned"):
+        for k in ("anderson", "learned", "learned_anderson"):
             assert cf.rel_frobenius(chis[k], chis["linear"]) <= 1e-5
     print("evaluations to 1e-6 on held-out observables: " + "; ".join(f"{k} {v}" for k, v in ev.items()))
     assert report["rounds"][-1][0] >= 2000
     assert sum(ev["learned"]) < 0.75 * sum(ev["linear"])
+    assert sum(ev["learned_anderson"]) < 0.75 * sum(ev["linear"])
