@@ -1105,34 +1105,46 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
     return DMPT_OK;
   };
 
-  // chemical potential
+  // chemical potential (canonical): safeguarded Newton steps on Tr D(mu) = N_occ.
+  // A run carries the observables' responses when it is expected to verify mu
+  // (or at a mu the caller supplies), so the verifying run is usually also the
+  // final one; if such a run misses the tolerance, Newton continues.
   double mu = fopts->mu;
   int newton = 0, m = 0;
   double tre = 0.0, sqe = 0.0;
+  bool have_final = false;
   if (fopts->canonical) {
     const double nocc = o.nocc;
     const double tol = fopts->count_tol > 0 ? fopts->count_tol : 1e-6 * n;
     double lo = emin - 40.0 / beta, hi = emax + 40.0 / beta;
-    if (!std::isfinite(mu) || mu <= lo || mu >= hi) mu = emin + (emax - emin) * nocc / n;
+    const bool given = std::isfinite(mu) && mu > lo && mu < hi;
+    if (!given) mu = emin + (emax - emin) * nocc / n;
     const int maxn = fopts->newton_max > 0 ? fopts->newton_max : 40;
-    bool ok = false;
+    bool with_obs = given;
     for (newton = 1; newton <= maxn; ++newton) {
-      if ((st = recursion(mu, 0, &m)) != DMPT_OK) return st;
+      products = 0;
+      if ((st = recursion(mu, with_obs ? nobs : 0, &m)) != DMPT_OK) return st;
       if ((st = trace_sq(E.m, &tre, &sqe)) != DMPT_OK) return st;
       const double count = 0.5 * n + tre;
       const double slope = beta * (0.25 * n - sqe);   // dTr D / dmu = beta Tr[D - D^2]
-      if (std::fabs(count - nocc) <= tol) { ok = true; break; }
+      if (std::fabs(count - nocc) <= tol) { have_final = with_obs || nobs == 0; break; }
       if (count < nocc) lo = mu; else hi = mu;
       double next = slope > 0 ? mu - (count - nocc) / slope : 0.5 * (lo + hi);
       if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+      // |c''| <= beta c' for the Fermi count c(mu), so the error after this step
+      // is at most beta |dmu| |c - N_occ| / 2: carry the responses when that is below tol
+      with_obs = 0.5 * beta * std::fabs(next - mu) * std::fabs(count - nocc) <= 0.5 * tol;
       mu = next;
     }
-    if (!ok) return fail(DMPT_ERR_NOT_CONVERGED, "chemical potential: |Tr D - N_occ| above %g after %d steps", tol, maxn);
+    if (newton > maxn)
+      return fail(DMPT_ERR_NOT_CONVERGED, "chemical potential: |Tr D - N_occ| above %g after %d steps", tol, maxn);
   }
-  // final run with the responses
-  products = 0;
-  if ((st = recursion(mu, nobs, &m)) != DMPT_OK) return st;
-  if ((st = trace_sq(E.m, &tre, &sqe)) != DMPT_OK) return st;
+  // final run with the responses (unless the last canonical run was one)
+  if (!have_final) {
+    products = 0;
+    if ((st = recursion(mu, nobs, &m)) != DMPT_OK) return st;
+    if ((st = trace_sq(E.m, &tre, &sqe)) != DMPT_OK) return st;
+  }
   const double trdd = 0.25 * n - sqe;   // Tr[D - D^2]
   std::vector<double> mu1(std::max(nobs, 1), 0.0);
   for (int k = 0; k < nobs; ++k) {
