@@ -4,8 +4,10 @@ oracle/__init__.py).
 
 The network is applied site by site with shared weights: for a residual
 vector x in R^n (one self-consistent state) the input of site i is
-    z_i = [x_{i-w}, ..., x_{i+w}, U_i]          (k = 2w + 2 features;
-                                                 x_j = 0 outside 0..n-1)
+    z_i = [x_{i-w}, ..., x_{i+w}, e_{i-w}, ..., e_{i+w}, U_i]
+                          (k = 4w + 3 features; x_j = e_j = 0 outside 0..n-1),
+with e the on-site energies (diagonal of H0), which tell the network where
+the polarisable sites are.
 and the output is the scalar
     y_i = w2 . tanh(W1 z_i + b1) + b2,
 a two-layer network of hidden width h.  Parameters are one vector
@@ -20,7 +22,7 @@ import numpy as np
 
 
 def features(window: int) -> int:
-    return 2 * window + 2
+    return 4 * window + 3
 
 
 def param_count(window: int, h: int) -> int:
@@ -39,33 +41,36 @@ def unpack(p: np.ndarray, window: int, h: int):
     return w1, b1, w2, b2
 
 
-def site_inputs(x: np.ndarray, u: np.ndarray, window: int) -> np.ndarray:
+def site_inputs(x: np.ndarray, u: np.ndarray, e: np.ndarray, window: int) -> np.ndarray:
     """(B, n) states -> (B * n, k) site inputs, rows ordered (b, i)."""
     x = np.asarray(x, np.float64)
+    e = np.asarray(e, np.float64)
     bsz, n = x.shape
     k = features(window)
+    m = 2 * window + 1
     z = np.zeros((bsz, n, k))
     for d in range(-window, window + 1):
         lo, hi = max(0, -d), min(n, n - d)          # sites i with 0 <= i + d < n
         if lo < hi:                                 # none when |d| >= n
             z[:, lo:hi, d + window] = x[:, lo + d:hi + d]
+            z[:, lo:hi, m + d + window] = e[None, lo + d:hi + d]
     z[:, :, k - 1] = np.asarray(u, np.float64)[None, :]
     return z.reshape(bsz * n, k)
 
 
-def forward(p, x, u, window: int, h: int):
+def forward(p, x, u, e, window: int, h: int):
     """x: (B, n) -> (y (B, n), site inputs, hidden activations)."""
     w1, b1, w2, b2 = unpack(p, window, h)
     bsz, n = np.asarray(x).shape
-    z = site_inputs(x, u, window)
+    z = site_inputs(x, u, e, window)
     a = np.tanh(z @ w1.T + b1)
     return (a @ w2 + b2).reshape(bsz, n), z, a
 
 
-def loss_grad(p, x, t, u, window: int, h: int):
+def loss_grad(p, x, t, u, e, window: int, h: int):
     """(loss, gradient with respect to the packed parameters)."""
     w1, b1, w2, b2 = unpack(p, window, h)
-    y, z, a = forward(p, x, u, window, h)
+    y, z, a = forward(p, x, u, e, window, h)
     r = (y - np.asarray(t, np.float64)).ravel()
     m = r.size
     loss = float(r @ r / m)

@@ -69,32 +69,39 @@ def test_ground_state_without_field_is_d_of_h0():
 # ------------------------------------------------------------------ mixer network
 
 def test_mlp_site_inputs_by_hand():
-    """n = 3, window 1: site i sees (x_{i-1}, x_i, x_{i+1}, U_i), zeros off the ends."""
-    z = mlp.site_inputs(np.array([[1.0, 2.0, 3.0]]), np.array([0.5, 0.6, 0.7]), 1)
-    np.testing.assert_array_equal(z, [[0, 1, 2, 0.5], [1, 2, 3, 0.6], [2, 3, 0, 0.7]])
+    """n = 3, window 1: site i sees (x_{i-1}, x_i, x_{i+1}, e_{i-1}, e_i, e_{i+1}, U_i),
+    zeros off the ends."""
+    z = mlp.site_inputs(np.array([[1.0, 2.0, 3.0]]), np.array([0.5, 0.6, 0.7]), np.array([-1.0, 0.25, 2.0]), 1)
+    np.testing.assert_array_equal(z, [[0, 1, 2, 0, -1.0, 0.25, 0.5],
+                                      [1, 2, 3, -1.0, 0.25, 2.0, 0.6],
+                                      [2, 3, 0, 0.25, 2.0, 0, 0.7]])
 
 
 def test_mlp_site_inputs_wide_window_brute_force():
     """A window wider than the system (w = 5, n = 3) and a ragged case, against
-    the definition entry by entry: z[(b, i), d + w] = x_b,i+d inside, 0 outside."""
+    the definition entry by entry: z[(b, i), d + w] = x_b,i+d and
+    z[(b, i), 2w + 1 + d + w] = e_i+d inside, 0 outside."""
     rng = np.random.default_rng(4)
     for n, w in ((3, 5), (6, 2), (1, 0)):
-        x, u = rng.normal(size=(2, n)), rng.uniform(0.5, 1.5, size=n)
-        z = mlp.site_inputs(x, u, w)
-        assert z.shape == (2 * n, 2 * w + 2)
+        x, u, e = rng.normal(size=(2, n)), rng.uniform(0.5, 1.5, size=n), rng.uniform(-1, 1, size=n)
+        z = mlp.site_inputs(x, u, e, w)
+        assert z.shape == (2 * n, 4 * w + 3)
         for b in range(2):
             for i in range(n):
                 row = z[b * n + i]
                 for d in range(-w, w + 1):
-                    assert row[d + w] == (x[b, i + d] if 0 <= i + d < n else 0.0)
+                    inside = 0 <= i + d < n
+                    assert row[d + w] == (x[b, i + d] if inside else 0.0)
+                    assert row[2 * w + 1 + d + w] == (e[i + d] if inside else 0.0)
                 assert row[-1] == u[i]
 
 
 def test_mlp_hand_example():
-    """window 0, h = 1: y_i = w2 tanh(w1 . (x_i, U_i) + b1) + b2."""
-    p = np.array([0.7, -0.4, -0.2, 1.5, 0.1])   # W1 = [0.7, -0.4], b1, w2, b2
-    y, _, _ = mlp.forward(p, np.array([[0.3, -1.0]]), np.array([1.2, 0.8]), 0, 1)
-    want = [1.5 * np.tanh(0.7 * 0.3 - 0.4 * 1.2 - 0.2) + 0.1, 1.5 * np.tanh(-0.7 - 0.4 * 0.8 - 0.2) + 0.1]
+    """window 0, h = 1: y_i = w2 tanh(w1 . (x_i, e_i, U_i) + b1) + b2."""
+    p = np.array([0.7, 0.3, -0.4, -0.2, 1.5, 0.1])   # W1 = [0.7, 0.3, -0.4], b1, w2, b2
+    y, _, _ = mlp.forward(p, np.array([[0.3, -1.0]]), np.array([1.2, 0.8]), np.array([0.5, -2.0]), 0, 1)
+    want = [1.5 * np.tanh(0.7 * 0.3 + 0.3 * 0.5 - 0.4 * 1.2 - 0.2) + 0.1,
+            1.5 * np.tanh(-0.7 - 0.6 - 0.4 * 0.8 - 0.2) + 0.1]
     np.testing.assert_allclose(y[0], want, rtol=1e-15)
 
 
@@ -105,12 +112,13 @@ def test_mlp_gradient_matches_finite_differences():
     x = rng.normal(size=(b, n))
     t = rng.normal(size=(b, n))
     u = rng.uniform(0.5, 1.5, size=n)
-    _, g = mlp.loss_grad(p, x, t, u, w, h)
+    e = rng.uniform(-1, 1, size=n)
+    _, g = mlp.loss_grad(p, x, t, u, e, w, h)
     step = 1e-6
     for i in range(p.size):
-        e = np.zeros_like(p)
-        e[i] = step
-        fd = (mlp.loss_grad(p + e, x, t, u, w, h)[0] - mlp.loss_grad(p - e, x, t, u, w, h)[0]) / (2 * step)
+        d = np.zeros_like(p)
+        d[i] = step
+        fd = (mlp.loss_grad(p + d, x, t, u, e, w, h)[0] - mlp.loss_grad(p - d, x, t, u, e, w, h)[0]) / (2 * step)
         assert abs(fd - g[i]) <= 1e-8 * max(1.0, abs(fd)), i
 
 
