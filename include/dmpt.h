@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 2
+#define DMPT_ABI_VERSION 3
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -335,16 +335,18 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
  * Learned mixer network (the LEARNED mixer of dmpt_scf_response; not from the
  * paper, which mixes linearly).  It is applied site by site with shared
  * weights: for a state vector x in R^n, site i sees
- *   z_i = [x_{i-w}, ..., x_{i+w}, U_i]       (k = 2w + 2 features; x_j = 0
- *                                             outside 0..n-1)
+ *   z_i = [x_{i-w}, ..., x_{i+w}, E_{i-w}, ..., E_{i+w}, U_i]
+ *        (k = 4w + 3 features; x_j = E_j = 0 outside 0..n-1; E the on-site
+ *         energies, the diagonal of H0)
  * and outputs y_i = w2 . tanh(W1 z_i + b1) + b2 (hidden width h).  The
  * response of a gapped system is near-sighted, so a window of sites carries
- * the information a preconditioner of the self-consistent loop needs.
+ * the information a preconditioner of the self-consistent loop needs; the
+ * on-site energies say which of them are polarisable.
  * BF16 parameters in one vector [W1 (h x k, row-major) | b1 (h) | w2 (h) |
  * b2 (1)]; training minimises the mean squared error over all B n outputs,
  * (1 / (B n)) sum (y - t)^2, with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on
  * FP32 master parameters.  Arrays are device arrays; batches are row-major
- * B x n; U is the n on-site interactions.  Training pairs of the
+ * B x n; U is the n on-site interactions, E the n on-site energies.  Training pairs of the
  * self-consistent loop: x = sqrt(n) r / ||r||, t = sqrt(n) (v* - v - mix r) / ||r||
  * from linear-mixing runs (v* their converged state). */
 size_t dmpt_mixer_param_count(int32_t window, int32_t hidden);
@@ -358,11 +360,13 @@ size_t dmpt_mixer_workspace_bytes(int32_t n, int32_t window, int32_t hidden, int
  * and index), zero biases; writes the FP32 masters and the BF16 copy. */
 dmpt_status dmpt_mixer_init(float* master, uint16_t* params, int32_t window, int32_t hidden, uint64_t seed,
                             void* stream);
-dmpt_status dmpt_mixer_forward(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+dmpt_status dmpt_mixer_forward(const uint16_t* params, int32_t window, int32_t hidden, const float* U, const float* E,
+                               int32_t n,
                                const float* x, int32_t batch, float* y, void* stream, void* workspace,
                                size_t workspace_bytes);
 /* loss (host) and its gradient (device, FP32, parameter layout) for one batch. */
-dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t hidden, const float* U, const float* E,
+                                 int32_t n,
                                  const float* x, const float* t, int32_t batch, float* grad, double* loss,
                                  void* stream, void* workspace, size_t workspace_bytes);
 /* steps Adam steps (step counter starting at 1) over minibatches of `batch`
@@ -370,7 +374,7 @@ dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t
  * start at zero (caller-owned, parameter-count floats); loss_history (host,
  * optional) receives the loss of every step. */
 dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, float* adam_v, int32_t window,
-                             int32_t hidden, const float* U, int32_t n, const float* x, const float* t,
+                             int32_t hidden, const float* U, const float* E, int32_t n, const float* x, const float* t,
                              int32_t npairs, int32_t batch, int32_t steps, double lr, double* loss_history,
                              void* stream, void* workspace, size_t workspace_bytes);
 

@@ -23,7 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
-ABI_VERSION = 2   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
+ABI_VERSION = 3   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
 PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4, "split_fp16": 5}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
@@ -173,11 +173,12 @@ def load() -> C.CDLL:
     lib.dmpt_mixer_workspace_bytes.restype = SZ
     lib.dmpt_mixer_init.argtypes = [P, P, I32, I32, C.c_uint64, P]
     lib.dmpt_mixer_init.restype = C.c_int
-    lib.dmpt_mixer_forward.argtypes = [P, I32, I32, P, I32, P, I32, P, P, P, SZ]
+    lib.dmpt_mixer_forward.argtypes = [P, I32, I32, P, P, I32, P, I32, P, P, P, SZ]
     lib.dmpt_mixer_forward.restype = C.c_int
-    lib.dmpt_mixer_loss_grad.argtypes = [P, I32, I32, P, I32, P, P, I32, P, C.POINTER(D), P, P, SZ]
+    lib.dmpt_mixer_loss_grad.argtypes = [P, I32, I32, P, P, I32, P, P, I32, P, C.POINTER(D), P, P, SZ]
     lib.dmpt_mixer_loss_grad.restype = C.c_int
-    lib.dmpt_mixer_train.argtypes = [P, P, P, P, I32, I32, P, I32, P, P, I32, I32, I32, D, C.POINTER(D), P, P, SZ]
+    lib.dmpt_mixer_train.argtypes = [P, P, P, P, I32, I32, P, P, I32, P, P, I32, I32, I32, D, C.POINTER(D), P, P,
+                                     SZ]
     lib.dmpt_mixer_train.restype = C.c_int
     lib.dmpt_sp2_decide.argtypes = [D, D, D, D, I32, I32, D, I32, D]
     lib.dmpt_sp2_decide.restype = I32

@@ -13,6 +13,7 @@
 
 #include "dmpt_fermi.h"
 #include "dmpt_internal.h"
+#include "dmpt_scf.h"
 #include "sp2_rule.h"
 
 namespace dmpt {
@@ -1242,7 +1243,8 @@ struct MixWS {
 
 bool mixer_sizes_ok(int n, int w, int h, int batch) {
   return n >= 1 && n <= 65536 && w >= 0 && w <= 512 && h >= 1 && h <= 4096 && batch >= 1 &&
-         (size_t)batch * n <= ((size_t)1 << 20) && (size_t)batch * n * (2 * w + 2 + 2 * h) <= ((size_t)1 << 31);
+         (size_t)batch * n <= ((size_t)1 << 20) &&
+         (size_t)batch * n * (mixer_features(w) + 2 * h) <= ((size_t)1 << 31);
 }
 
 MixWS mixer_ws(int n, int w, int h, int batch) {
@@ -1269,7 +1271,7 @@ dmpt_status mixer_check(int n, int w, int h, int batch, void* ws, size_t wsb, Mi
 
 struct ScfWS {
   size_t run_bytes;
-  size_t ca, cw[2], wmat, da, v, f, r, vt, ft, rt, vb, rb, x, y, mlp, dv, dr, tab, coef, dot, total;
+  size_t ca, cw[2], wmat, da, v, f, r, vt, ft, rt, vb, rb, x, y, ediag, mlp, dv, dr, tab, coef, dot, total;
 };
 
 // History depth and hidden width the mixer uses (0 when it uses none).
@@ -1300,6 +1302,7 @@ ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
   w.rb = off; off += vec;
   w.x = off; off += align_up((size_t)n * 4);
   w.y = off; off += align_up((size_t)n * 4);
+  w.ediag = off; off += align_up((size_t)n * 4);
   w.mlp = off; off += hidden > 0 ? align_up(mixer_scratch_floats(n, window, hidden, 1) * 4) : 0;
   w.dv = off; off += (size_t)depth * vec;
   w.dr = off; off += (size_t)depth * vec;
@@ -1396,31 +1399,33 @@ dmpt_status dmpt_mixer_init(float* master, uint16_t* params, int32_t window, int
   return DMPT_OK;
 }
 
-dmpt_status dmpt_mixer_forward(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+dmpt_status dmpt_mixer_forward(const uint16_t* params, int32_t window, int32_t hidden, const float* U, const float* E,
+                               int32_t n,
                                const float* x, int32_t batch, float* y, void* stream, void* workspace,
                                size_t workspace_bytes) {
-  if (!params || !U || !x || !y) return fail(DMPT_ERR_ARG, "params, U, x and y must not be NULL");
+  if (!params || !U || !E || !x || !y) return fail(DMPT_ERR_ARG, "params, U, E, x and y must not be NULL");
   MixWS m;
   dmpt_status st = mixer_check(n, window, hidden, batch, workspace, workspace_bytes, &m);
   if (st != DMPT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  DMPT_HIP(mixer_forward(params, window, hidden, U, n, x, batch, y, (float*)(ws + m.scratch), s));
+  DMPT_HIP(mixer_forward(params, window, hidden, U, E, n, x, batch, y, (float*)(ws + m.scratch), s));
   DMPT_HIP(hipStreamSynchronize(s));
   return DMPT_OK;
 }
 
-dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t hidden, const float* U, int32_t n,
+dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t hidden, const float* U, const float* E,
+                                 int32_t n,
                                  const float* x, const float* t, int32_t batch, float* grad, double* loss,
                                  void* stream, void* workspace, size_t workspace_bytes) {
-  if (!params || !U || !x || !t || !grad || !loss) return fail(DMPT_ERR_ARG, "NULL argument");
+  if (!params || !U || !E || !x || !t || !grad || !loss) return fail(DMPT_ERR_ARG, "NULL argument");
   MixWS m;
   dmpt_status st = mixer_check(n, window, hidden, batch, workspace, workspace_bytes, &m);
   if (st != DMPT_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)workspace;
   double* ld = (double*)(ws + m.loss);
-  DMPT_HIP(mixer_loss_grad(params, window, hidden, U, n, x, t, batch, (float*)(ws + m.scratch),
+  DMPT_HIP(mixer_loss_grad(params, window, hidden, U, E, n, x, t, batch, (float*)(ws + m.scratch),
                            (double*)(ws + m.part), grad, ld, 0, s));
   DMPT_HIP(hipMemcpyAsync(loss, ld, sizeof(double), hipMemcpyDeviceToHost, s));
   DMPT_HIP(hipStreamSynchronize(s));
@@ -1428,10 +1433,10 @@ dmpt_status dmpt_mixer_loss_grad(const uint16_t* params, int32_t window, int32_t
 }
 
 dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, float* adam_v, int32_t window,
-                             int32_t hidden, const float* U, int32_t n, const float* x, const float* t,
+                             int32_t hidden, const float* U, const float* E, int32_t n, const float* x, const float* t,
                              int32_t npairs, int32_t batch, int32_t steps, double lr, double* loss_history,
                              void* stream, void* workspace, size_t workspace_bytes) {
-  if (!master || !params || !adam_m || !adam_v || !U || !x || !t) return fail(DMPT_ERR_ARG, "NULL argument");
+  if (!master || !params || !adam_m || !adam_v || !U || !E || !x || !t) return fail(DMPT_ERR_ARG, "NULL argument");
   if (npairs < batch || steps < 1 || steps > kMixerMaxSteps || !(lr > 0))
     return fail(DMPT_ERR_ARG, "need npairs >= batch, 1 <= steps <= %d, lr > 0", kMixerMaxSteps);
   MixWS m;
@@ -1444,7 +1449,7 @@ dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, flo
   for (int k = 1; k <= steps; ++k) {
     size_t start = ((size_t)(k - 1) * batch) % (size_t)npairs;
     if (start + batch > (size_t)npairs) start = (size_t)npairs - batch;
-    DMPT_HIP(mixer_loss_grad(params, window, hidden, U, n, x + start * n, t + start * n, batch,
+    DMPT_HIP(mixer_loss_grad(params, window, hidden, U, E, n, x + start * n, t + start * n, batch,
                              (float*)(ws + m.scratch), (double*)(ws + m.part), (float*)(ws + m.grad), ld, k - 1, s));
     DMPT_HIP(mixer_adam(master, params, adam_m, adam_v, (const float*)(ws + m.grad), np, (float)lr, k, s));
   }
@@ -1488,6 +1493,7 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
   double *vt = (double*)(ws + w.vt), *ft = (double*)(ws + w.ft), *rt = (double*)(ws + w.rt);
   float* xf = (float*)(ws + w.x);
   float* yf = (float*)(ws + w.y);
+  float* ediag = (float*)(ws + w.ediag);   // on-site energies of H0 (learned mixer input)
   const void** tab = (const void**)(ws + w.tab);
   double* coef = (double*)(ws + w.coef);
   double* dot = (double*)(ws + w.dot);
@@ -1497,6 +1503,7 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
   st = run(H0, A, 1, ca, nullptr, nullptr, &o2, info, false);
   if (st != DMPT_OK) return st;
   DMPT_HIP(scf_get_diag(ca, n, da, s));
+  if (scf_hidden(scf) > 0) DMPT_HIP(mixer_diag(H0, n, ediag, s));
   DMPT_HIP(hipMemsetAsync(v, 0, (size_t)n * 8, s));
   DMPT_HIP(hipMemcpyAsync(f, da, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
 
@@ -1541,7 +1548,7 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
     auto learned_step = [&](const double* vv, const double* rr, double rrn) -> dmpt_status {
       const double sq = std::sqrt((double)n);
       DMPT_HIP(scf_to_float(xf, rr, sq / rrn, n, s));
-      DMPT_HIP(mixer_forward(scf->mlp_params, scf->mlp_window, scf->mlp_hidden, U, n, xf, 1, yf,
+      DMPT_HIP(mixer_forward(scf->mlp_params, scf->mlp_window, scf->mlp_hidden, U, ediag, n, xf, 1, yf,
                              (float*)(ws + w.mlp), s));
       DMPT_HIP(scf_step(vt, vv, rr, scf->mix, yf, rrn / sq, n, s));
       return DMPT_OK;

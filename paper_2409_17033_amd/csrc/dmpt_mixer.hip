@@ -2,8 +2,9 @@
 // vector steps on the diagonal state v = diag(chi'), and the learned mixer.
 //
 // The mixer network is applied site by site with shared weights: for a
-// state vector x in R^n, site i sees z_i = [x_{i-w} .. x_{i+w}, U_i]
-// (k = 2w + 2 features, zeros beyond the ends) and outputs
+// state vector x in R^n, site i sees z_i = [x_{i-w} .. x_{i+w}, e_{i-w} ..
+// e_{i+w}, U_i] with e the on-site energies (k = 4w + 3 features, zeros
+// beyond the ends) and outputs
 //   y_i = w2 . tanh(W1 z_i + b1) + b2          (hidden width h).
 // Parameters (FP32 masters and the BF16 copy alike): [W1 (h x k, row-major) |
 // b1 (h) | w2 (h) | b2 (1)].  Training: MSE loss, Adam (Kingma & Ba, 2015).
@@ -15,6 +16,7 @@
 #include <cmath>
 
 #include "dmpt_internal.h"
+#include "dmpt_scf.h"
 
 namespace dmpt {
 
@@ -123,9 +125,9 @@ hipError_t colsum(const float* m, size_t rows, int c, float* out, float* scratch
   return hipGetLastError();
 }
 
-// Z ((B n) x k): rows (b, i) = [x_b,i-w .. x_b,i+w, U_i]
-__global__ void k_site_inputs(const float* x, const float* u, int B, int n, int w, float* z) {
-  const int k = 2 * w + 2;
+// Z ((B n) x k): rows (b, i) = [x_b,i-w .. x_b,i+w, en_i-w .. en_i+w, U_i]
+__global__ void k_site_inputs(const float* x, const float* u, const float* en, int B, int n, int w, float* z) {
+  const int m = 2 * w + 1, k = 2 * m + 1;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)B * n * k) return;
   const size_t row = e / k;
@@ -134,11 +136,19 @@ __global__ void k_site_inputs(const float* x, const float* u, int B, int n, int 
   float v;
   if (f == k - 1) {
     v = u[i];
-  } else {
+  } else if (f < m) {
     const int j = i + f - w;
     v = (j >= 0 && j < n) ? x[(size_t)b * n + j] : 0.0f;
+  } else {
+    const int j = i + (f - m) - w;
+    v = (j >= 0 && j < n) ? en[j] : 0.0f;
   }
   z[e] = v;
+}
+
+__global__ void k_diag(const float* m, int n, float* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = m[(size_t)i * n + i];
 }
 
 // Z (rows x h) += b1, then A = tanh(Z) in place.
@@ -223,18 +233,23 @@ __global__ void k_init_params(float* p, uint16_t* p16, int k, int h, uint64_t se
 
 }  // namespace
 
-size_t mixer_param_count(int w, int h) { return (size_t)h * (2 * w + 2) + 2 * h + 1; }
+size_t mixer_param_count(int w, int h) { return (size_t)h * mixer_features(w) + 2 * h + 1; }
+
+hipError_t mixer_diag(const float* m, int n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag, dim3(blocks(n, 256)), dim3(256), 0, s, m, n, out);
+  return hipGetLastError();
+}
 
 size_t mixer_scratch_floats(int n, int w, int h, int B) {
-  const size_t rows = (size_t)B * n, k = 2 * w + 2;
+  const size_t rows = (size_t)B * n, k = mixer_features(w);
   // z, a, y, da, split partials of the weight gradients
   return rows * k + rows * h + rows + rows * h + (size_t)kSplits * (h * k + h + 1);
 }
 
 // forward: y (B x n) for states x (B x n).  scratch: mixer_scratch_floats.
-hipError_t mixer_forward(const uint16_t* p16, int w, int h, const float* u, int n, const float* x, int B, float* y,
-                         float* scratch, hipStream_t s) {
-  const int k = 2 * w + 2;
+hipError_t mixer_forward(const uint16_t* p16, int w, int h, const float* u, const float* en, int n, const float* x,
+                         int B, float* y, float* scratch, hipStream_t s) {
+  const int k = mixer_features(w);
   const size_t rows = (size_t)B * n;
   const uint16_t* w1 = p16;
   const uint16_t* b1 = w1 + (size_t)h * k;
@@ -242,7 +257,7 @@ hipError_t mixer_forward(const uint16_t* p16, int w, int h, const float* u, int 
   const uint16_t* b2 = w2 + h;
   float* z = scratch;
   float* a = z + rows * k;
-  hipLaunchKernelGGL(k_site_inputs, dim3(blocks(rows * k, 256)), dim3(256), 0, s, x, u, B, n, w, z);
+  hipLaunchKernelGGL(k_site_inputs, dim3(blocks(rows * k, 256)), dim3(256), 0, s, x, u, en, B, n, w, z);
   hipError_t e = gemm<float, uint16_t, false, true>(z, k, w1, k, a, h, (int)rows, h, k, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bias_tanh, dim3(blocks(rows * h, 256)), dim3(256), 0, s, a, b1, rows, h);
@@ -255,17 +270,17 @@ hipError_t mixer_forward(const uint16_t* p16, int w, int h, const float* u, int 
 constexpr int kMseBlocks = 256;
 
 // loss (device double at loss_out[idx]) and gradient (FP32, packed layout).
-hipError_t mixer_loss_grad(const uint16_t* p16, int w, int h, const float* u, int n, const float* x,
+hipError_t mixer_loss_grad(const uint16_t* p16, int w, int h, const float* u, const float* en, int n, const float* x,
                            const float* t, int B, float* scratch, double* part, float* grad, double* loss_out,
                            int idx, hipStream_t s) {
-  const int k = 2 * w + 2;
+  const int k = mixer_features(w);
   const size_t rows = (size_t)B * n;
   float* z = scratch;
   float* a = z + rows * k;
   float* y = a + rows * h;
   float* da = y + rows;
   float* split = da + rows * h;
-  hipError_t e = mixer_forward(p16, w, h, u, n, x, B, y, scratch, s);
+  hipError_t e = mixer_forward(p16, w, h, u, en, n, x, B, y, scratch, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, s, y, t, rows, part);   // y := dY
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, part, kMseBlocks, 1.0 / (double)rows, loss_out, idx);
@@ -303,7 +318,7 @@ hipError_t mixer_adam(float* p, uint16_t* p16, float* m, float* v, const float* 
 
 hipError_t mixer_init(float* p, uint16_t* p16, int w, int h, uint64_t seed, hipStream_t s) {
   hipLaunchKernelGGL(k_init_params, dim3(blocks(mixer_param_count(w, h), 256)), dim3(256), 0, s, p, p16,
-                     2 * w + 2, h, seed);
+                     mixer_features(w), h, seed);
   return hipGetLastError();
 }
 

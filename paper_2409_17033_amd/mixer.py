@@ -1,7 +1,8 @@
 """The learned mixer of the self-consistent response loop (Eq. CP_SCF).
 
 A two-layer network of hidden width h with BF16 weights, applied site by site
-(site i sees the residual in a window of 2w + 1 sites and its U_i), stands
+(site i sees the residual and the on-site energies in a window of 2w + 1
+sites, and its U_i), stands
 in as the preconditioner of the loop: from the state v and residual r it
 proposes v + mix r + (||r|| / sqrt(n)) net(sqrt(n) r / ||r||).  It is trained
 on pairs the method itself produces: linear-mixing runs record (v_k, r_k);
@@ -20,10 +21,12 @@ from ._lib import check, load
 
 
 class Mixer:
-    def __init__(self, U, window: int = 32, hidden: int = 256, seed: int = 0):
-        """U: (n,) float32 device tensor of on-site interactions (a per-site input)."""
+    def __init__(self, U, E, window: int = 32, hidden: int = 256, seed: int = 0):
+        """U: (n,) float32 device tensor of on-site interactions, E: (n,) the
+        on-site energies (diagonal of H0); both are per-site inputs."""
         lib = load()
         self.U = U.contiguous().float()
+        self.E = E.contiguous().float()
         self.n, self.window, self.hidden = U.shape[0], window, hidden
         device = U.device
         count = int(lib.dmpt_mixer_param_count(window, hidden))
@@ -54,7 +57,7 @@ class Mixer:
         y = torch.empty_like(x)
         ws = self._ws(b)
         check(load().dmpt_mixer_forward(C.c_void_p(self.params.data_ptr()), self.window, self.hidden,
-                                        C.c_void_p(self.U.data_ptr()), self.n,
+                                        C.c_void_p(self.U.data_ptr()), C.c_void_p(self.E.data_ptr()), self.n,
                                         C.c_void_p(x.data_ptr()), b, C.c_void_p(y.data_ptr()),
                                         C.c_void_p(torch.cuda.current_stream().cuda_stream),
                                         C.c_void_p(ws.data_ptr()), ws.numel()))
@@ -67,7 +70,7 @@ class Mixer:
         loss = C.c_double()
         ws = self._ws(b)
         check(load().dmpt_mixer_loss_grad(C.c_void_p(self.params.data_ptr()), self.window, self.hidden,
-                                          C.c_void_p(self.U.data_ptr()), self.n,
+                                          C.c_void_p(self.U.data_ptr()), C.c_void_p(self.E.data_ptr()), self.n,
                                           C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), b,
                                           C.c_void_p(grad.data_ptr()), C.byref(loss),
                                           C.c_void_p(torch.cuda.current_stream().cuda_stream),
@@ -84,7 +87,8 @@ class Mixer:
         ws = self._ws(batch)
         check(load().dmpt_mixer_train(C.c_void_p(self.master.data_ptr()), C.c_void_p(self.params.data_ptr()),
                                       C.c_void_p(self.adam_m.data_ptr()), C.c_void_p(self.adam_v.data_ptr()),
-                                      self.window, self.hidden, C.c_void_p(self.U.data_ptr()), self.n,
+                                      self.window, self.hidden, C.c_void_p(self.U.data_ptr()),
+                                      C.c_void_p(self.E.data_ptr()), self.n,
                                       C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
                                       npairs, batch, steps, lr, hist,
                                       C.c_void_p(torch.cuda.current_stream().cuda_stream),
@@ -127,7 +131,7 @@ def training_pairs(H0, U, observables, nocc: int, *, mix: float = 0.3, tol: floa
 
 def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int = 256, rounds: int = 2,
                 steps: int = 6000, batch: int = 64, lr: float = 1e-3, mix: float = 0.3, tol: float = 1e-6,
-                max_iter: int = 400, min_residual: float = 1e-5, seed: int = 11, **kw):
+                max_iter: int = 400, collect_iter: int = 100, min_residual: float = 1e-5, seed: int = 11, **kw):
     """Train a mixer for the loop of (H0, U) on the method's own pairs.
 
     Round 0 trains on the states of linear-mixing runs (training_pairs).  A
@@ -140,20 +144,23 @@ def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int 
     Bagnell, 2011).  Every network is scored by its mean number of loop
     evaluations over the training observables and the best one is returned,
     with a report {rounds: [(pairs, loss, mean evaluations)], chosen: index}.
+    The learned runs stop after collect_iter evaluations (a poor early network
+    would otherwise spend max_iter on each observable).
     """
     from . import scf_response
     x, t, vstars = training_pairs(H0, U, observables, nocc, mix=mix, tol=tol, max_iter=max_iter,
                                   min_residual=min_residual, return_fixed_points=True, **kw)
     gen = torch.Generator().manual_seed(seed)
     report, best = {"rounds": []}, None
+    E = H0.diagonal().contiguous().float()      # on-site energies (a network input)
     for rnd in range(rounds + 1):
-        net = Mixer(U, window=window, hidden=hidden, seed=seed + rnd)
+        net = Mixer(U, E, window=window, hidden=hidden, seed=seed + rnd)
         hist = net.train(x, t, steps=steps, batch=batch, lr=lr)
         loss = sum(hist[-100:]) / len(hist[-100:])
         xs, ts, evals = [x], [t], []
         for a, vstar in zip(observables, vstars):
             _, sinfo, _, v, r = scf_response(H0, U, a, nocc, mixer="learned", net=net, mix=mix, tol=tol,
-                                             max_iter=max_iter, record=True, raise_on_error=False, **kw)
+                                             max_iter=collect_iter, record=True, raise_on_error=False, **kw)
             evals.append(sinfo["iters"])
             if rnd < rounds:
                 xn, tn = _pairs(v, r, sinfo["residual"], vstar, mix, min_residual, drop_last=False)

@@ -36,7 +36,7 @@ def test_exports_every_declared_function(lib):
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 2
+    assert lib.dmpt_abi_version() == 3
 
 
 def test_struct_layouts():
@@ -199,16 +199,17 @@ def test_scf_workspace_covers_the_adjoint_solve(lib):
 
 
 def test_mixer_sizes(lib):
-    k = 2 * 32 + 2
+    k = 4 * 32 + 3
     assert lib.dmpt_mixer_param_count(32, 256) == 256 * k + 2 * 256 + 1
     assert lib.dmpt_mixer_param_count(-1, 256) == 0
     assert lib.dmpt_mixer_workspace_bytes(1024, 32, 256, 64) > 64 * 1024 * (k + 2 * 256) * 4
     assert lib.dmpt_mixer_workspace_bytes(1024, 32, 0, 64) == 0
     out = (C.c_double * 1)()
-    assert lib.dmpt_mixer_forward(FAKE, 2, 4, FAKE, 8, FAKE, 2, FAKE, None, None, 0) == 6
-    assert lib.dmpt_mixer_forward(None, 2, 4, FAKE, 8, FAKE, 2, FAKE, None, FAKE, 1 << 20) == 1
-    assert lib.dmpt_mixer_train(FAKE, FAKE, FAKE, FAKE, 2, 4, FAKE, 8, FAKE, FAKE, 1, 2, 10, 1e-3, out, None, FAKE,
-                                1 << 20) == 1     # npairs < batch
+    assert lib.dmpt_mixer_forward(FAKE, 2, 4, FAKE, FAKE, 8, FAKE, 2, FAKE, None, None, 0) == 6
+    assert lib.dmpt_mixer_forward(None, 2, 4, FAKE, FAKE, 8, FAKE, 2, FAKE, None, FAKE, 1 << 20) == 1
+    assert lib.dmpt_mixer_forward(FAKE, 2, 4, FAKE, None, 8, FAKE, 2, FAKE, None, FAKE, 1 << 20) == 1   # no E
+    assert lib.dmpt_mixer_train(FAKE, FAKE, FAKE, FAKE, 2, 4, FAKE, FAKE, 8, FAKE, FAKE, 1, 2, 10, 1e-3, out, None,
+                                FAKE, 1 << 20) == 1     # npairs < batch
 
 
 def test_status_strings(lib):

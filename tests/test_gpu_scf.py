@@ -29,6 +29,12 @@ def _u(n, seed):
     return 0.5 + torch.rand(n, generator=g)
 
 
+def _e(n, seed):
+    import torch
+    g = torch.Generator().manual_seed(seed + 100)
+    return 2.0 * torch.rand(n, generator=g) - 1.0
+
+
 @pytest.mark.parametrize("n,w,h,b", [(256, 8, 64, 16), (1024, 32, 256, 8), (37, 40, 16, 3)])
 def test_mixer_forward_and_gradient(gpu, n, w, h, b):
     """Site-local network on (B, n) states: forward, loss and gradient
@@ -37,18 +43,18 @@ def test_mixer_forward_and_gradient(gpu, n, w, h, b):
     import torch
 
     from paper_2409_17033_amd.mixer import Mixer
-    u = _u(n, 9)
-    net = Mixer(u.to(gpu), window=w, hidden=h, seed=3)
+    u, en = _u(n, 9), _e(n, 9)
+    net = Mixer(u.to(gpu), en.to(gpu), window=w, hidden=h, seed=3)
     g = torch.Generator().manual_seed(1)
     x = torch.randn(b, n, generator=g).to(gpu)
     t = torch.randn(b, n, generator=g).to(gpu)
     p = _bf16(net.params)
-    un = u.double().numpy()
+    un, enn = u.double().numpy(), en.double().numpy()
     y = net.forward(x).double().cpu().numpy()
-    yref, _, _ = omlp.forward(p, x.double().cpu().numpy(), un, w, h)
+    yref, _, _ = omlp.forward(p, x.double().cpu().numpy(), un, enn, w, h)
     assert cf.rel_frobenius(y, yref) <= 1e-5
     loss, grad = net.loss_grad(x, t)
-    lref, gref = omlp.loss_grad(p, x.double().cpu().numpy(), t.double().cpu().numpy(), un, w, h)
+    lref, gref = omlp.loss_grad(p, x.double().cpu().numpy(), t.double().cpu().numpy(), un, enn, w, h)
     assert abs(loss - lref) <= 1e-5 * lref
     assert cf.rel_frobenius(grad.double().cpu().numpy(), gref) <= 1e-4
 
@@ -58,14 +64,14 @@ def test_mixer_adam_step(gpu):
 
     from paper_2409_17033_amd.mixer import Mixer
     n, w, h, b = 128, 4, 32, 8
-    u = _u(n, 4)
-    net = Mixer(u.to(gpu), window=w, hidden=h, seed=5)
+    u, en = _u(n, 4), _e(n, 4)
+    net = Mixer(u.to(gpu), en.to(gpu), window=w, hidden=h, seed=5)
     g = torch.Generator().manual_seed(2)
     x = torch.randn(b, n, generator=g).to(gpu)
     t = torch.randn(b, n, generator=g).to(gpu)
     p0 = net.master.double().cpu().numpy()
     _, gref = omlp.loss_grad(_bf16(net.params), x.double().cpu().numpy(), t.double().cpu().numpy(),
-                             u.double().numpy(), w, h)
+                             u.double().numpy(), en.double().numpy(), w, h)
     net.train(x, t, steps=1, batch=b, lr=1e-3)
     p1 = net.master.double().cpu().numpy()
     pref, _, _ = omlp.adam_step(p0, gref, np.zeros_like(p0), np.zeros_like(p0), 1, lr=1e-3)
@@ -80,7 +86,7 @@ def test_training_reduces_loss(gpu):
 
     from paper_2409_17033_amd.mixer import Mixer
     n, w, h = 64, 3, 32
-    net = Mixer(_u(n, 6).to(gpu), window=w, hidden=h, seed=7)
+    net = Mixer(_u(n, 6).to(gpu), _e(n, 6).to(gpu), window=w, hidden=h, seed=7)
     g = torch.Generator().manual_seed(3)
     x = torch.randn(256, n, generator=g)
     kern = torch.tensor([0.1, -0.3, 0.5, 1.0, 0.5, -0.3, 0.1])
@@ -173,4 +179,5 @@ def test_learned_mixer_gain_config4(gpu, c4):
     print("evaluations to 1e-6 on held-out observables: " + "; ".join(f"{k} {v}" for k, v in ev.items()))
     assert report["rounds"][-1][0] >= 2000
     assert sum(ev["learned"]) < 0.75 * sum(ev["linear"])
-    assert sum(ev["learned_anderson"]) < 0.75 * sum(ev["linear"])
+    # the network as Anderson's preconditioner beats Anderson itself
+    assert sum(ev["learned_anderson"]) < 0.85 * sum(ev["anderson"])
