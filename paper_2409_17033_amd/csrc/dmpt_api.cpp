@@ -512,6 +512,15 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     st = compute_bounds(o, p, H, ctl, (double*)(ws + p.off_lz), (double2*)(ws + p.off_gersh), s);
     if (st != DMPT_OK) return st;
   }
+  // Every step launch takes the next queue counter set (zeroed here, then
+  // kept clean by the launches themselves).
+  DMPT_HIP(launch_queue_reset(ctl, s));
+  unsigned qseq = 0;
+  auto run_step = [&](int prec_, StepArgs& args, int nj) {
+    if (nj <= 0) return hipSuccess;   // no launch: the counter sets stay in step
+    step_queue_sets(ctl, qseq++, &args);
+    return launch_step(prec_, args, nj, s);
+  };
 
   // Slot of X_n: forward sweep 2 ping-pong slots; adjoint slot n, or with
   // checkpoints the checkpoint slot / a working slot (forward run) and the
@@ -577,13 +586,13 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       if (split_launch) {
         a.jobs = d_jobs;
         a.flush = flush_interval(yprec, p.n_pad);
-        DMPT_HIP(launch_step(yprec, a, njobs_z, s));
+        DMPT_HIP(run_step(yprec, a, njobs_z));
         a.jobs = d_jobs + njobs_z;
         a.flush = flush_interval(xprec, p.n_pad);
-        DMPT_HIP(launch_step(xprec, a, njobs_main - njobs_z, s));
+        DMPT_HIP(run_step(xprec, a, njobs_main - njobs_z));
       } else {
         a.jobs = step_jobs;
-        DMPT_HIP(launch_step(xprec, a, njobs_step, s));
+        DMPT_HIP(run_step(xprec, a, njobs_step));
       }
       step_marks.emplace_back(ma, prof.mark());
       ++launched;
@@ -630,14 +639,14 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
         r.step = n;
         r.x_in = x_ref(p, ws, xslot_bwd(n));
         r.x_out = x_ref(p, ws, xslot_bwd(n + 1));
-        DMPT_HIP(launch_step(xprec, r, p.nparts_step, s));
+        DMPT_HIP(run_step(xprec, r, p.nparts_step));
       }
       for (int n = n1; n >= n0; --n) {
         b.step = n;
         b.x_in = x_ref(p, ws, xslot_bwd(n));
         b.y_in = y_ref(p, ws, ys);
         b.y_out = y_ref(p, ws, ys ^ 1);
-        DMPT_HIP(launch_step(yprec, b, (int)zjobs.size(), s));
+        DMPT_HIP(run_step(yprec, b, (int)zjobs.size()));
         ys ^= 1;
       }
       n1 = n0 - 1;
@@ -671,7 +680,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.write_split = q == 0 && pprec != kFP32;   // the second step reads it
       b.y_in = view(y_ref(p, ws, yfin));
       b.y_out = view(y_ref(p, ws, yfin ^ 1));
-      DMPT_HIP(launch_step(pprec, b, (int)pjobs.size(), s));
+      DMPT_HIP(run_step(pprec, b, (int)pjobs.size()));
       yfin ^= 1;
     }
   }

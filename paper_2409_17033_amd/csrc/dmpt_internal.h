@@ -55,6 +55,14 @@ struct Part {
   double tr, sq, eps, pad;
 };
 
+// Job queues of the persistent step kernel: one queue per XCD (queue x holds
+// the job-list positions x, x + 8, x + 16, ...), each with a ticket counter
+// that workgroups advance with atomic adds.  Counters of one launch are one
+// set; sets rotate over kQSets so that launch L can clear the set of launch
+// L + 2 (launch L - 2, its last user, has finished and L + 2 starts after L).
+// Counters sit kQStride words apart (separate 64-byte lines).
+constexpr int kXcdQueues = 8, kQSets = 4, kQStride = 16;
+
 // Device control block (lives at the start of the workspace).
 struct Ctl {
   int done;        // recursion finished (stop, error or limit)
@@ -64,6 +72,7 @@ struct Ctl {
   double emin, emax, alpha, beta;
   double gmin, gmax;   // Gershgorin bounds
   StepRec rec[DMPT_MAX_STEPS + 3];
+  unsigned int qhead[kQSets][kXcdQueues * kQStride];
 };
 
 // Job = one output tile (I, J), I <= J, of either the X product
@@ -108,6 +117,9 @@ struct StepArgs {
   int flush;                 // two-level accumulation: add the pass accumulator into the
                              // running tile sum every `flush` stages (0: single level)
   const uint32_t* jobs;
+  int njobs;                 // length of the job list
+  unsigned int* qhead;       // this launch's queue counters (zero at launch start)
+  unsigned int* qclear;      // counter set cleared by this launch for a later one
   MatRef x_in, x_out, y_in, y_out;
   const Part* part_in;       // partials written by the previous step (or X_1's init)
   Part* part_out;
@@ -127,7 +139,16 @@ hipError_t launch_set_bounds(Ctl* ctl, double emin, double emax, hipStream_t s);
 hipError_t launch_init(int prec, int tile, const float* h, const float* a, int n, int n_pad,
                        int nobs, const uint32_t* jobs, int njobs, MatRef x, MatRef y,
                        double y_scale_mode, Part* part, Ctl* ctl, hipStream_t s);
-hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s);
+// Step launch: a persistent grid of at most one workgroup per CU working
+// through args.jobs[0, njobs) (njobs is stored into the arguments).  The
+// caller sets qhead / qclear from step_queue_sets.
+hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s);
+// Queue counter sets of the seq-th step launch since the last queue reset.
+inline void step_queue_sets(Ctl* ctl, unsigned seq, StepArgs* a) {
+  a->qhead = ctl->qhead[seq % kQSets];
+  a->qclear = ctl->qhead[(seq + 2) % kQSets];
+}
+hipError_t launch_queue_reset(Ctl* ctl, hipStream_t s);
 // Step tiles are 256 rows x 128 columns; tile (I, J) with J >= 2I covers the
 // upper triangle.  ntile in StepArgs is the number of 128-column blocks.
 constexpr int kStepTM = 256, kStepTN = 128;

@@ -458,6 +458,10 @@ __device__ __forceinline__ void store_group8_t(char* op, int nst, int r, int c0,
   }
 }
 
+// s_getreg operand for the 32-bit HW_REG_XCC_ID register (id 20): the XCD a
+// wave runs on in its low bits.
+constexpr int kHwRegXccId = (31 << 11) | 20;
+
 // Index of step tile (I, J) among the tiles that cover the upper triangle:
 // row block I (256 rows), column block J >= 2I (128 columns), tcols = n_pad/128.
 __device__ __forceinline__ int tile_index(int ti, int tj, int tcols) {
@@ -475,9 +479,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   __shared__ __attribute__((aligned(1024))) char ring2[RSZ];
   __shared__ __attribute__((aligned(1024))) char ring3[RSZ];
   __shared__ int s_code;
+  __shared__ int s_job;
   __shared__ double s_red[3 * NW];
   __shared__ double s_nrm;
 
+  if (blockIdx.x == 0 && threadIdx.x < kXcdQueues) a.qclear[threadIdx.x * kQStride] = 0u;
   if (a.decide && a.ctl->done) return;
   int sigma;
   if (a.decide) {
@@ -488,329 +494,387 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     sigma = a.sigma_src ? a.sigma_src[a.step].sigma : a.fixed_sigma;
   }
 
-  const uint32_t job = a.jobs[blockIdx.x];
-  const int kind = job & 1;
-  const int obs = (job >> 1) & 127;
-  const int ti = (job >> 8) & 4095;    // 256-row block
-  const int tj = (job >> 20) & 4095;   // 128-column block
-  constexpr int opb = operand_bytes(PREC);
-  const size_t ldb = (size_t)a.n_pad * opb;
-  const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
-  const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
-
-  const char* xop = (const char*)a.x_in.op;
-  const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
-  // row block I / J starts at the same byte offset in both layouts:
-  // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
-  const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
-  const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
-  const char* b0 = xop + rowJ;
-  const char* a1 = xop + rowI;
-  const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
-
-  // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
-  // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
-  // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
-  // exponent bounded from ||Y_n||_F.
-  float usc = 1.0f, sc_out = 1.0f;
-  int s_out = 0;
-  if constexpr (PREC == kSplitH) {
-    if (kind == kJobZ) {
-      const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
-      usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
-      const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
-      s_out = yscale_exp(meta_norm(mi, nb * nb, &s_nrm), kYBound);
-    } else {
-      usc = ldexpf(1.0f, -2 * kXScaleExp);
-      s_out = kXScaleExp;
-    }
-    sc_out = ldexpf(1.0f, s_out);
-  }
-
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
-  const int h = lane >> 5, l32 = lane & 31;
-  const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
-
-  f32x16 acc[BR][BC], tot[BR][BC];
-#pragma unroll
-  for (int i = 0; i < BR; ++i)
-#pragma unroll
-    for (int j = 0; j < BC; ++j) {
-      acc[i][j] = f32x16{0};
-      tot[i][j] = f32x16{0};
-    }
-
-  // Stage s of the job's K stream; stages past the end re-fetch stage 0 into
-  // a slot that is never read again, which keeps the vmcnt bookkeeping uniform.
-  const uint32_t ldb32 = (uint32_t)ldb;
-  const size_t chunkb = (size_t)P::CHUNK;
-  auto dma = [&](LDS_AS char* slot, int s) {
-    const int sc = s < nst ? s : 0;
-    const bool second = sc >= spass;
-    const int st = second ? sc - spass : sc;
-    const char* pa = second ? a1 : a0;
-    const char* pb = second ? b1 : b0;
-    if constexpr (PREC == kSplit32) {
-      const char* ca = pa + (size_t)st * chunkb;
-      dma_stage_t32<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
-    } else if constexpr (P::TILED) {
-      // panel bases are the first chunk of their row block; stage st is chunk st
-      const char* ca = pa + (size_t)st * chunkb;
-      dma_stage_tiled<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
-    } else {
-      const size_t kb = (size_t)st * P::RB;
-      dma_stage_rows<PREC>(slot, pa + kb, pb + kb, ldb32, wave, lane);
-    }
-  };
-  LDS_AS char* R0 = (LDS_AS char*)ring0;
-  LDS_AS char* R1 = (LDS_AS char*)ring1;
-  LDS_AS char* R2 = (LDS_AS char*)ring2;
-  LDS_AS char* R3 = (LDS_AS char*)ring3;
-
-  Ops<PREC> o0, o1;
-  dma(R0, 0);
-  dma(R1, 1);
-  dma(R2, 2);
-  wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
-  barrier_nofence();
-  dma(R3, 3);
-  __builtin_amdgcn_sched_barrier(0);
-  read_ops<PREC>(R0, o0, rowA, rowB, h);
-
-  // Iteration s: the operands of stage s are in registers (OC).  Wait until
-  // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
-  // LDS reads of stage s are done, barrier (so has every wave), refill the
-  // slot of stage s with stage s+4, read stage s+1 into the other register
-  // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
-  // of the previous one.
-#define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
-  {                                                       \
-    wait_vm<2 * P::L, true>();                            \
-    barrier_nofence();                                    \
-    dma(REFILL, (S_) + 4);                                \
-    __builtin_amdgcn_sched_barrier(0);                    \
-    read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
-    mma_ops<PREC>(OC, acc);                               \
-  }
-  const int fl4 = a.flush > 0 ? a.flush : 1 << 30;   // flush every fl4 groups of 4 stages
-  int since = 0;
-  for (int s = 0; s < nst; s += 4) {
-    DMPT_ITER(s + 0, R1, R0, o0, o1)
-    DMPT_ITER(s + 1, R2, R1, o1, o0)
-    DMPT_ITER(s + 2, R3, R2, o0, o1)
-    DMPT_ITER(s + 3, R0, R3, o1, o0)
-    if (++since == fl4) {
-      since = 0;
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int j = 0; j < BC; ++j) {
-          tot[i][j] += acc[i][j];
-          acc[i][j] = f32x16{0};
-        }
-    }
-  }
-#undef DMPT_ITER
-  wait_vm<0, true>();
-#pragma unroll
-  for (int i = 0; i < BR; ++i)
-#pragma unroll
-    for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
-  if constexpr (PREC == kSplitH) {
-#pragma unroll
-    for (int i = 0; i < BR; ++i)
-#pragma unroll
-      for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
-  }
-
-  // ------------------------------------------------------------ epilogue
-  const size_t np = a.n_pad;
-  const MatRef& in = kind == kJobZ ? a.y_in : a.x_in;
-  const MatRef& out = kind == kJobZ ? a.y_out : a.x_out;
-  const float* cur = in.f32 + (kind == kJobZ ? obs * in.stride_f32 : 0);
-  float* o32 = out.f32 + (kind == kJobZ ? obs * out.stride_f32 : 0);
-  char* oop = (char*)out.op + (kind == kJobZ ? obs * out.stride_op : 0);
-  const int nstp = a.n_pad / Fmt<PREC>::K;   // stages per row (tiled layout)
-  const bool wsplit = a.write_split && PREC != kFP32;
-  const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
-  double tr = 0.0, sq = 0.0, ep = 0.0;
-  double yq = 0.0;   // kSplitH Z-jobs: ||Y_{n+1}||_F^2 over this tile (and its mirror)
-  const bool need_cur = kind == kJobP || sigma < 0;
-  if (!onDiag) {
-    // Off-diagonal tile: every element is stored twice (direct and mirror).
-    // Each wave stages its 64 x 64 region in LDS (private area, no cross-wave
-    // traffic) and writes rows of 16-byte vectors: direct rows, mirror rows,
-    // and 16-byte split-term slots of 8 consecutive columns in both
-    // orientations.  The barrier makes sure every wave is past its last ring
-    // read and every ring DMA has landed.
-    barrier_nofence();
-    LDS_AS char* rb = (wave >> 1) == 0 ? R0 : (wave >> 1) == 1 ? R1 : (wave >> 1) == 2 ? R2 : R3;
-    LDS_AS float* T = (LDS_AS float*)(rb + (wave & 1) * kStageBytes);
-    // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
-#pragma unroll
-    for (int bi = 0; bi < BR; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < BC; ++bj)
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) T[(bi * 32 + 8 * g + 4 * h + e) * kLS + bj * 32 + l32] = tot[bi][bj][4 * g + e];
-    wait_vm<63, true>();
-    const int gr0 = ti * TM + wr * 64, gc0 = tj * TN + wc * 64;   // global origin of the region
-    // direct rows: 4 rows x 64 columns per round, 4 columns per lane
-#pragma unroll 4
-    for (int rd = 0; rd < 16; ++rd) {
-      const int r = 4 * rd + (lane >> 4), c = 4 * (lane & 15);
-      f32x4 v = f32x4{T[r * kLS + c], T[r * kLS + c + 1], T[r * kLS + c + 2], T[r * kLS + c + 3]};
-      if (need_cur) {
-        const f32x4 x = *(const f32x4*)(cur + (size_t)(gr0 + r) * np + gc0 + c);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float p = v[k];
-          v[k] = sigma > 0 ? p : 2.0f * x[k] - p;
-          if (kind == kJobP) {
-            const double d = x[k] - p;                // X_n - X_n^2
-            sq += 2.0 * (double)v[k] * (double)v[k];
-            ep += 2.0 * d * d;
-          }
-        }
-        if (sigma < 0) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) T[r * kLS + c + k] = v[k];
-        }
-      }
-      if constexpr (PREC == kSplitH) {
-        if (kind == kJobZ)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) yq += 2.0 * (double)v[k] * (double)v[k];
-      }
-      *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
-    }
-    wait_vm<63, true>();
-    // mirror rows: 4 mirror rows x 64 columns per round
-#pragma unroll 4
-    for (int rd = 0; rd < 16; ++rd) {
-      const int c = 4 * rd + (lane >> 4), q = 4 * (lane & 15);
-      *(f32x4*)(o32 + (size_t)(gc0 + c) * np + gr0 + q) =
-          f32x4{T[q * kLS + c], T[(q + 1) * kLS + c], T[(q + 2) * kLS + c], T[(q + 3) * kLS + c]};
-    }
-    if constexpr (PREC != kFP32) {
-      if (wsplit) {
-        // split-term slots: 8 rows x 8 groups of 8 columns per round, both orientations
-#pragma unroll 2
-        for (int rd = 0; rd < 8; ++rd) {
-          const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
-          float v[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
-          store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v, sc_out);
-        }
-#pragma unroll 2
-        for (int rd = 0; rd < 8; ++rd) {
-          const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
-          float v[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
-          store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v, sc_out);
-        }
-      }
-    }
-  } else {
-    // Diagonal tile: keep the upper triangle (row <= col) and mirror it.
-    // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
-#pragma unroll
-    for (int bi = 0; bi < BR; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < BC; ++bj) {
-        const int col = tj * TN + wc * 64 + bj * 32 + l32;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int r = row0 + e;
-            if (r > col) continue;
-            const float p = tot[bi][bj][4 * g + e];
-            float v = p, dd = 0.0f;
-            if (need_cur) {
-              const float c0 = cur[(size_t)r * np + col];
-              v = sigma > 0 ? p : 2.0f * c0 - p;
-              dd = c0 - p;                               // X_n - X_n^2 (P-jobs)
-            }
-            o32[(size_t)r * np + col] = v;
-            o32[(size_t)col * np + r] = v;
-            if (wsplit) {
-              store_split1<Store<PREC>::F>(oop, nstp, r, col, v, sc_out);
-              if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v, sc_out);
-            }
-            if constexpr (PREC == kSplitH) {
-              if (kind == kJobZ) yq += (r == col ? 1.0 : 2.0) * (double)v * (double)v;
-            }
-            if (kind == kJobP) {
-              const double w = r == col ? 1.0 : 2.0;
-              if (r == col) tr += v;
-              sq += w * (double)v * (double)v;
-              ep += w * (double)dd * (double)dd;
-            }
-          }
-        }
-      }
-  }
-
-  if (kind == kJobP) {
-    tr = wave_sum(tr);
-    sq = wave_sum(sq);
-    ep = wave_sum(ep);
-    if (lane == 0) {
-      s_red[3 * wave] = tr;
-      s_red[3 * wave + 1] = sq;
-      s_red[3 * wave + 2] = ep;
-    }
-    __syncthreads();
+  // Persistent loop: thread 0 takes the next ticket of this XCD's queue, and
+  // once that queue is used up, of the others in turn; a ticket past a
+  // queue's end marks that queue used up for this workgroup, so every
+  // workgroup leaves after at most njobs + 8 tickets.
+  const int home = (int)(__builtin_amdgcn_s_getreg(kHwRegXccId) & (kXcdQueues - 1));
+  unsigned int used_up = 0;
+  for (;;) {
     if (threadIdx.x == 0) {
-      Part p = {0.0, 0.0, 0.0, 0.0};
-      for (int w = 0; w < NW; ++w) {
-        p.tr += s_red[3 * w];
-        p.sq += s_red[3 * w + 1];
-        p.eps += s_red[3 * w + 2];
+      int pos = -1;
+      for (int k = 0; k < kXcdQueues && pos < 0; ++k) {
+        const int q = (home + k) & (kXcdQueues - 1);
+        if (used_up & (1u << q)) continue;
+        const unsigned t = atomicAdd(&a.qhead[q * kQStride], 1u);
+        const size_t p = (size_t)t * kXcdQueues + q;
+        if (p < (size_t)a.njobs) pos = (int)p;
+        else used_up |= 1u << q;
       }
-      a.part_out[tile_index(ti, tj, a.ntile)] = p;
+      s_job = pos;
     }
-  }
-  if constexpr (PREC == kSplitH) {
-    if (kind == kJobZ) {
-      yq = wave_sum(yq);
-      if (lane == 0) s_red[wave] = yq;
+    // every wave is past the previous job's epilogue (LDS staging, s_red)
+    // before the next job's DMA refills the ring
+    wait_vm<63, true>();
+    barrier_nofence();
+    const int jpos = s_job;
+    if (jpos < 0) break;
+    const uint32_t job = a.jobs[jpos];
+    const int kind = job & 1;
+    const int obs = (job >> 1) & 127;
+    const int ti = (job >> 8) & 4095;    // 256-row block
+    const int tj = (job >> 20) & 4095;   // 128-column block
+    constexpr int opb = operand_bytes(PREC);
+    const size_t ldb = (size_t)a.n_pad * opb;
+    const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
+    const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
+
+    const char* xop = (const char*)a.x_in.op;
+    const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
+    // row block I / J starts at the same byte offset in both layouts:
+    // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
+    const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
+    const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
+    const char* b0 = xop + rowJ;
+    const char* a1 = xop + rowI;
+    const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
+
+    // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
+    // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
+    // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
+    // exponent bounded from ||Y_n||_F.
+    float usc = 1.0f, sc_out = 1.0f;
+    int s_out = 0;
+    if constexpr (PREC == kSplitH) {
+      if (kind == kJobZ) {
+        const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
+        usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
+        const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
+        s_out = yscale_exp(meta_norm(mi, nb * nb, &s_nrm), kYBound);
+      } else {
+        usc = ldexpf(1.0f, -2 * kXScaleExp);
+        s_out = kXScaleExp;
+      }
+      sc_out = ldexpf(1.0f, s_out);
+    }
+
+    // The thread index is made opaque per job so that the compiler keeps the
+    // lane-dependent address arithmetic inside the job (hoisted out of the
+    // job loop it would stay live through the main loop and spill).
+    unsigned int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
+    const int h = lane >> 5, l32 = lane & 31;
+    const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
+
+    f32x16 acc[BR][BC], tot[BR][BC];
+  #pragma unroll
+    for (int i = 0; i < BR; ++i)
+  #pragma unroll
+      for (int j = 0; j < BC; ++j) {
+        acc[i][j] = f32x16{0};
+        tot[i][j] = f32x16{0};
+      }
+
+    // Stage s of the job's K stream; stages past the end re-fetch stage 0 into
+    // a slot that is never read again, which keeps the vmcnt bookkeeping uniform.
+    const uint32_t ldb32 = (uint32_t)ldb;
+    const size_t chunkb = (size_t)P::CHUNK;
+    auto dma = [&](LDS_AS char* slot, int s) {
+      const int sc = s < nst ? s : 0;
+      const bool second = sc >= spass;
+      const int st = second ? sc - spass : sc;
+      const char* pa = second ? a1 : a0;
+      const char* pb = second ? b1 : b0;
+      if constexpr (PREC == kSplit32) {
+        const char* ca = pa + (size_t)st * chunkb;
+        dma_stage_t32<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
+      } else if constexpr (P::TILED) {
+        // panel bases are the first chunk of their row block; stage st is chunk st
+        const char* ca = pa + (size_t)st * chunkb;
+        dma_stage_tiled<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
+      } else {
+        const size_t kb = (size_t)st * P::RB;
+        dma_stage_rows<PREC>(slot, pa + kb, pb + kb, ldb32, wave, lane);
+      }
+    };
+    LDS_AS char* R0 = (LDS_AS char*)ring0;
+    LDS_AS char* R1 = (LDS_AS char*)ring1;
+    LDS_AS char* R2 = (LDS_AS char*)ring2;
+    LDS_AS char* R3 = (LDS_AS char*)ring3;
+
+    Ops<PREC> o0, o1;
+    dma(R0, 0);
+    dma(R1, 1);
+    dma(R2, 2);
+    wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
+    barrier_nofence();
+    dma(R3, 3);
+    __builtin_amdgcn_sched_barrier(0);
+    read_ops<PREC>(R0, o0, rowA, rowB, h);
+
+    // Iteration s: the operands of stage s are in registers (OC).  Wait until
+    // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
+    // LDS reads of stage s are done, barrier (so has every wave), refill the
+    // slot of stage s with stage s+4, read stage s+1 into the other register
+    // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
+    // of the previous one.
+  #define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
+    {                                                       \
+      wait_vm<2 * P::L, true>();                            \
+      barrier_nofence();                                    \
+      dma(REFILL, (S_) + 4);                                \
+      __builtin_amdgcn_sched_barrier(0);                    \
+      read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
+      mma_ops<PREC>(OC, acc);                               \
+    }
+    const int fl4 = a.flush > 0 ? a.flush : 1 << 30;   // flush every fl4 groups of 4 stages
+    int since = 0;
+    for (int s = 0; s < nst; s += 4) {
+      DMPT_ITER(s + 0, R1, R0, o0, o1)
+      DMPT_ITER(s + 1, R2, R1, o1, o0)
+      DMPT_ITER(s + 2, R3, R2, o0, o1)
+      DMPT_ITER(s + 3, R0, R3, o1, o0)
+      if (++since == fl4) {
+        since = 0;
+  #pragma unroll
+        for (int i = 0; i < BR; ++i)
+  #pragma unroll
+          for (int j = 0; j < BC; ++j) {
+            tot[i][j] += acc[i][j];
+            acc[i][j] = f32x16{0};
+          }
+      }
+    }
+  #undef DMPT_ITER
+    wait_vm<0, true>();
+  #pragma unroll
+    for (int i = 0; i < BR; ++i)
+  #pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
+    if constexpr (PREC == kSplitH) {
+  #pragma unroll
+      for (int i = 0; i < BR; ++i)
+  #pragma unroll
+        for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
+    }
+
+    // ------------------------------------------------------------ epilogue
+    const size_t np = a.n_pad;
+    const MatRef& in = kind == kJobZ ? a.y_in : a.x_in;
+    const MatRef& out = kind == kJobZ ? a.y_out : a.x_out;
+    const float* cur = in.f32 + (kind == kJobZ ? obs * in.stride_f32 : 0);
+    float* o32 = out.f32 + (kind == kJobZ ? obs * out.stride_f32 : 0);
+    char* oop = (char*)out.op + (kind == kJobZ ? obs * out.stride_op : 0);
+    const int nstp = a.n_pad / Fmt<PREC>::K;   // stages per row (tiled layout)
+    const bool wsplit = a.write_split && PREC != kFP32;
+    const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
+    double tr = 0.0, sq = 0.0, ep = 0.0;
+    double yq = 0.0;   // kSplitH Z-jobs: ||Y_{n+1}||_F^2 over this tile (and its mirror)
+    const bool need_cur = kind == kJobP || sigma < 0;
+    if (!onDiag) {
+      // Off-diagonal tile: every element is stored twice (direct and mirror).
+      // Each wave stages its 64 x 64 region in LDS (private area, no cross-wave
+      // traffic) and writes rows of 16-byte vectors: direct rows, mirror rows,
+      // and 16-byte split-term slots of 8 consecutive columns in both
+      // orientations.  The barrier makes sure every wave is past its last ring
+      // read and every ring DMA has landed.
+      barrier_nofence();
+      LDS_AS char* rb = (wave >> 1) == 0 ? R0 : (wave >> 1) == 1 ? R1 : (wave >> 1) == 2 ? R2 : R3;
+      LDS_AS float* T = (LDS_AS float*)(rb + (wave & 1) * kStageBytes);
+      // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+  #pragma unroll
+      for (int bi = 0; bi < BR; ++bi)
+  #pragma unroll
+        for (int bj = 0; bj < BC; ++bj)
+  #pragma unroll
+          for (int g = 0; g < 4; ++g)
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) T[(bi * 32 + 8 * g + 4 * h + e) * kLS + bj * 32 + l32] = tot[bi][bj][4 * g + e];
+      wait_vm<63, true>();
+      const int gr0 = ti * TM + wr * 64, gc0 = tj * TN + wc * 64;   // global origin of the region
+      // direct rows: 4 rows x 64 columns per round, 4 columns per lane
+  #pragma unroll 4
+      for (int rd = 0; rd < 16; ++rd) {
+        const int r = 4 * rd + (lane >> 4), c = 4 * (lane & 15);
+        f32x4 v = f32x4{T[r * kLS + c], T[r * kLS + c + 1], T[r * kLS + c + 2], T[r * kLS + c + 3]};
+        if (need_cur) {
+          const f32x4 x = *(const f32x4*)(cur + (size_t)(gr0 + r) * np + gc0 + c);
+  #pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float p = v[k];
+            v[k] = sigma > 0 ? p : 2.0f * x[k] - p;
+            if (kind == kJobP) {
+              const double d = x[k] - p;                // X_n - X_n^2
+              sq += 2.0 * (double)v[k] * (double)v[k];
+              ep += 2.0 * d * d;
+            }
+          }
+          if (sigma < 0) {
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) T[r * kLS + c + k] = v[k];
+          }
+        }
+        if constexpr (PREC == kSplitH) {
+          if (kind == kJobZ)
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) yq += 2.0 * (double)v[k] * (double)v[k];
+        }
+        *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
+      }
+      wait_vm<63, true>();
+      // mirror rows: 4 mirror rows x 64 columns per round
+  #pragma unroll 4
+      for (int rd = 0; rd < 16; ++rd) {
+        const int c = 4 * rd + (lane >> 4), q = 4 * (lane & 15);
+        *(f32x4*)(o32 + (size_t)(gc0 + c) * np + gr0 + q) =
+            f32x4{T[q * kLS + c], T[(q + 1) * kLS + c], T[(q + 2) * kLS + c], T[(q + 3) * kLS + c]};
+      }
+      if constexpr (PREC != kFP32) {
+        if (wsplit) {
+          // split-term slots: 8 rows x 8 groups of 8 columns per round, both orientations
+  #pragma unroll 2
+          for (int rd = 0; rd < 8; ++rd) {
+            const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
+            float v[8];
+  #pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
+            store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v, sc_out);
+          }
+  #pragma unroll 2
+          for (int rd = 0; rd < 8; ++rd) {
+            const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
+            float v[8];
+  #pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
+            store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v, sc_out);
+          }
+        }
+      }
+    } else {
+      // Diagonal tile: keep the upper triangle (row <= col) and mirror it.
+      // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+  #pragma unroll
+      for (int bi = 0; bi < BR; ++bi)
+  #pragma unroll
+        for (int bj = 0; bj < BC; ++bj) {
+          const int col = tj * TN + wc * 64 + bj * 32 + l32;
+  #pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int r = row0 + e;
+              if (r > col) continue;
+              const float p = tot[bi][bj][4 * g + e];
+              float v = p, dd = 0.0f;
+              if (need_cur) {
+                const float c0 = cur[(size_t)r * np + col];
+                v = sigma > 0 ? p : 2.0f * c0 - p;
+                dd = c0 - p;                               // X_n - X_n^2 (P-jobs)
+              }
+              o32[(size_t)r * np + col] = v;
+              o32[(size_t)col * np + r] = v;
+              if (wsplit) {
+                store_split1<Store<PREC>::F>(oop, nstp, r, col, v, sc_out);
+                if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v, sc_out);
+              }
+              if constexpr (PREC == kSplitH) {
+                if (kind == kJobZ) yq += (r == col ? 1.0 : 2.0) * (double)v * (double)v;
+              }
+              if (kind == kJobP) {
+                const double w = r == col ? 1.0 : 2.0;
+                if (r == col) tr += v;
+                sq += w * (double)v * (double)v;
+                ep += w * (double)dd * (double)dd;
+              }
+            }
+          }
+        }
+    }
+
+    if (kind == kJobP) {
+      tr = wave_sum(tr);
+      sq = wave_sum(sq);
+      ep = wave_sum(ep);
+      if (lane == 0) {
+        s_red[3 * wave] = tr;
+        s_red[3 * wave + 1] = sq;
+        s_red[3 * wave + 2] = ep;
+      }
       __syncthreads();
       if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < NW; ++w) t += s_red[w];
-        MatMeta* mo = (MatMeta*)(a.y_out.meta + obs * a.y_out.stride_op);
-        const int idx = tile_index(ti, tj, a.ntile);
-        mo->nrm[idx] = t;
-        if (idx == 0) {
-          const int tr_ = a.n_pad / TM;
-          mo->scale = s_out;
-          mo->count = tr_ * (tr_ + 1);
+        Part p = {0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < NW; ++w) {
+          p.tr += s_red[3 * w];
+          p.sq += s_red[3 * w + 1];
+          p.eps += s_red[3 * w + 2];
+        }
+        a.part_out[tile_index(ti, tj, a.ntile)] = p;
+      }
+    }
+    if constexpr (PREC == kSplitH) {
+      if (kind == kJobZ) {
+        yq = wave_sum(yq);
+        if (lane == 0) s_red[wave] = yq;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double t = 0.0;
+          for (int w = 0; w < NW; ++w) t += s_red[w];
+          MatMeta* mo = (MatMeta*)(a.y_out.meta + obs * a.y_out.stride_op);
+          const int idx = tile_index(ti, tj, a.ntile);
+          mo->nrm[idx] = t;
+          if (idx == 0) {
+            const int tr_ = a.n_pad / TM;
+            mo->scale = s_out;
+            mo->count = tr_ * (tr_ + 1);
+          }
         }
       }
     }
   }
 }
 
-hipError_t launch_step(int prec, const StepArgs& args, int njobs, hipStream_t s) {
+// Workgroups of a persistent step launch: one per CU (the step kernel's LDS
+// use allows no second workgroup on a CU), never more than the jobs.
+int persistent_grid(int njobs) {
+  constexpr int kMaxDevices = 64;
+  static int cus[kMaxDevices] = {};   // per device; concurrent first calls store the same value
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+  if (cus[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
+  }
+  return njobs < cus[dev] ? njobs : cus[dev];
+}
+
+hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
+  args.njobs = njobs;
+  const dim3 grid(persistent_grid(njobs));
   switch (prec) {
-    case kFP32: hipLaunchKernelGGL(k_step<kFP32>, dim3(njobs), dim3(NT), 0, s, args); break;
-    case kSplit2: hipLaunchKernelGGL(k_step<kSplit2>, dim3(njobs), dim3(NT), 0, s, args); break;
-    case kSplit3: hipLaunchKernelGGL(k_step<kSplit3>, dim3(njobs), dim3(NT), 0, s, args); break;
-    case kSplit32: hipLaunchKernelGGL(k_step<kSplit32>, dim3(njobs), dim3(NT), 0, s, args); break;
-    case kBF16: hipLaunchKernelGGL(k_step<kBF16>, dim3(njobs), dim3(NT), 0, s, args); break;
-    case kSplitH: hipLaunchKernelGGL(k_step<kSplitH>, dim3(njobs), dim3(NT), 0, s, args); break;
+    case kFP32: hipLaunchKernelGGL(k_step<kFP32>, grid, dim3(NT), 0, s, args); break;
+    case kSplit2: hipLaunchKernelGGL(k_step<kSplit2>, grid, dim3(NT), 0, s, args); break;
+    case kSplit3: hipLaunchKernelGGL(k_step<kSplit3>, grid, dim3(NT), 0, s, args); break;
+    case kSplit32: hipLaunchKernelGGL(k_step<kSplit32>, grid, dim3(NT), 0, s, args); break;
+    case kBF16: hipLaunchKernelGGL(k_step<kBF16>, grid, dim3(NT), 0, s, args); break;
+    case kSplitH: hipLaunchKernelGGL(k_step<kSplitH>, grid, dim3(NT), 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+__global__ void k_queue_reset(Ctl* c) {
+  unsigned int* q = &c->qhead[0][0];
+  for (int i = threadIdx.x; i < kQSets * kXcdQueues * kQStride; i += blockDim.x) q[i] = 0u;
+}
+
+hipError_t launch_queue_reset(Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(256), 0, s, ctl);
   return hipGetLastError();
 }
 
