@@ -364,6 +364,35 @@ __device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC
     }
 }
 
+// Issue order inside one pipeline stage: the R LDS reads of the next stage
+// are spread among the M MFMAs of this one (a read, then M / R MFMAs; when R
+// does not divide M, a read per MFMA and the remaining MFMAs last).  Left to
+// itself the scheduler puts some reads at the end of the stage, where their
+// latency, queued behind every wave's reads, stalls the stage's barrier.
+template <int PREC> struct StageMix {
+  static constexpr int R = (BR + BC) * (PREC == kSplit3 ? 3 : 2);   // ds_read_b128 per stage
+  static constexpr int M = BR * BC * (PREC == kSplit3 ? 6 : (PREC == kSplit2 || PREC == kSplit32 || PREC == kSplitH) ? 3 :
+                                      PREC == kBF16 ? 2 : 8);           // MFMAs per stage
+};
+template <int PREC>
+__device__ __forceinline__ void stage_order() {
+  constexpr int R = StageMix<PREC>::R, M = StageMix<PREC>::M;
+  if constexpr (M % R == 0) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);       // DS read
+      __builtin_amdgcn_sched_group_barrier(0x008, M / R, 0);   // MFMA
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, M - R, 0);
+  }
+}
+
 // ---------------------------------------------------------------- step kernel
 
 // Launch k of the step kernel: wave 0 reduces the partials the previous
@@ -629,6 +658,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       __builtin_amdgcn_sched_barrier(0);                    \
       read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
       mma_ops<PREC>(OC, acc);                               \
+      stage_order<PREC>();                                  \
     }
     const int fl4 = a.flush > 0 ? a.flush : 1 << 30;   // flush every fl4 groups of 4 stages
     int since = 0;
@@ -965,6 +995,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     __builtin_amdgcn_sched_barrier(0);                    \
     read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
     mma_ops<PREC>(OC, acc);                               \
+    stage_order<PREC>();                                  \
   }
   const int fl4 = flush > 0 ? flush : 1 << 30;
   int since = 0;
