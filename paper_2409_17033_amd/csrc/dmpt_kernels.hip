@@ -230,6 +230,15 @@ __device__ __forceinline__ void dma_stage_tiled(LDS_AS char* slot, const char* a
                                                 int wave, int lane) {
   using P = Pipe<PREC>;
   constexpr int NC = P::CHUNK / 1024;   // instructions per chunk
+  if constexpr (P::NI == 3 * NW && NC == NW) {
+    // one instruction per wave in each of the three chunks: instruction
+    // j = wave + jj NW copies kilobyte `wave` of chunk jj
+    const size_t off = (size_t)wave * 1024 + (size_t)lane * 16;
+    __builtin_amdgcn_global_load_lds((const GLB_AS void*)(a0 + off), (LDS_AS void*)(slot + wave * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const GLB_AS void*)(a1 + off), (LDS_AS void*)(slot + (wave + NW) * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const GLB_AS void*)(b + off), (LDS_AS void*)(slot + (wave + 2 * NW) * 1024), 16, 0, 0);
+    return;
+  }
 #pragma unroll
   for (int jj = 0; jj < P::L; ++jj) {
     const int jv = wave + jj * NW;
@@ -615,27 +624,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         tot[i][j] = f32x16{0};
       }
 
-    // Stage s of the job's K stream; stages past the end re-fetch stage 0 into
-    // a slot that is never read again, which keeps the vmcnt bookkeeping uniform.
+    // The stages of the job's K stream are fetched in order, each call of dma
+    // the next one: cA / cB address stage cs of the A / B panel (tiled: its
+    // chunk, which advances by one chunk per stage; row-major: its column
+    // offset).  A Z-job's stream switches to the second product at stage
+    // spass; stages past the end re-fetch stage 0 into a slot that is never
+    // read again, which keeps the vmcnt bookkeeping uniform.
     const uint32_t ldb32 = (uint32_t)ldb;
     const size_t chunkb = (size_t)P::CHUNK;
-    auto dma = [&](LDS_AS char* slot, int s) {
-      const int sc = s < nst ? s : 0;
-      const bool second = sc >= spass;
-      const int st = second ? sc - spass : sc;
-      const char* pa = second ? a1 : a0;
-      const char* pb = second ? b1 : b0;
-      if constexpr (PREC == kSplit32) {
-        const char* ca = pa + (size_t)st * chunkb;
-        dma_stage_t32<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
-      } else if constexpr (P::TILED) {
-        // panel bases are the first chunk of their row block; stage st is chunk st
-        const char* ca = pa + (size_t)st * chunkb;
-        dma_stage_tiled<PREC>(slot, ca, ca + (size_t)spass * chunkb, pb + (size_t)st * chunkb, wave, lane);
-      } else {
-        const size_t kb = (size_t)st * P::RB;
-        dma_stage_rows<PREC>(slot, pa + kb, pb + kb, ldb32, wave, lane);
-      }
+    const size_t step_b = P::TILED ? chunkb : (size_t)P::RB;   // bytes from one stage to the next
+    const size_t a_hi = (size_t)spass * chunkb;                // tiled: A rows 128-255 (next row block)
+    const char* cA = a0;
+    const char* cB = b0;
+    int cs = 0;
+    auto dma = [&](LDS_AS char* slot) {
+      if constexpr (PREC == kSplit32) dma_stage_t32<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
+      else if constexpr (P::TILED) dma_stage_tiled<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
+      else dma_stage_rows<PREC>(slot, cA, cB, ldb32, wave, lane);
+      ++cs;   // selects, not branches: the stage body stays one basic block
+      const bool wrap = cs >= nst, second = cs == spass;
+      cA = wrap ? a0 : second ? a1 : cA + step_b;
+      cB = wrap ? b0 : second ? b1 : cB + step_b;
     };
     LDS_AS char* R0 = (LDS_AS char*)ring0;
     LDS_AS char* R1 = (LDS_AS char*)ring1;
@@ -643,12 +652,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     LDS_AS char* R3 = (LDS_AS char*)ring3;
 
     Ops<PREC> o0, o1;
-    dma(R0, 0);
-    dma(R1, 1);
-    dma(R2, 2);
+    dma(R0);
+    dma(R1);
+    dma(R2);
     wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
     barrier_nofence();
-    dma(R3, 3);
+    dma(R3);
     __builtin_amdgcn_sched_barrier(0);
     read_ops<PREC>(R0, o0, rowA, rowB, h);
 
@@ -662,7 +671,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     {                                                       \
       wait_vm<2 * P::L, true>();                            \
       barrier_nofence();                                    \
-      dma(REFILL, (S_) + 4);                                \
+      dma(REFILL);   /* stage (S_) + 4 */                   \
       __builtin_amdgcn_sched_barrier(0);                    \
       read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
       mma_ops<PREC>(OC, acc);                               \
