@@ -13,16 +13,21 @@
 //   fixed point of x^2 and 2x - x^2 and contributes nothing to any trace.
 //
 // Step kernel (one launch per SP2 step n)
-//   grid = list of jobs; a job is one 256 x 128 output tile (I, J >= 2I) of
+//   A job is one 256 x 128 output tile (I, J >= 2I) of
 //     P = X_n X_n                    (kind P; symmetric, so X_n rows serve as
 //                                      both operands: P_IJ = X_I X_J^T)
 //     Z = Y_n X_n + X_n Y_n          (kind Z; = Y_I X_J^T + X_I Y_J^T, the two
 //                                      products K-concatenated)
+//   The grid is persistent (one workgroup per CU): workgroups take jobs from
+//   per-XCD queues with atomic tickets and steal from the other queues when
+//   their own runs dry.
 //   Operands stream HBM -> LDS with global_load_lds_dwordx4 (no VGPR staging)
 //   through a ring of four stages, three in flight; the next stage's
 //   operands are read into a second register set while the current stage's
-//   MFMAs run.  Products run on v_mfma_f32_32x32x16_bf16 (split / plain
-//   BF16) or v_mfma_f32_32x32x2f32 (FP32) with two-level FP32 accumulation.
+//   MFMAs run, in a fixed interleaving of LDS reads and MFMAs.  Products run
+//   on v_mfma_f32_32x32x16_f16 (FP16 split), v_mfma_f32_32x32x16_bf16 (BF16
+//   splits / plain BF16) or v_mfma_f32_32x32x2f32 (FP32) with two-level FP32
+//   accumulation.
 //   Epilogue: X_{n+1} = P (sigma=+1) or 2 X_n - P (sigma=-1), likewise Y;
 //   the tile and its mirror are stored (exact symmetry), the operand copy is
 //   re-split, and P-jobs emit FP64 partials of Tr X_{n+1}, ||X_{n+1}||_F^2
