@@ -1175,10 +1175,22 @@ __global__ __launch_bounds__(256) void k_gersh_rows(const float* h, int n, doubl
     if (i >= n) break;
     const float* row = h + (size_t)i * n;
     double rs = 0.0;
-    for (int j = lane; j < n; j += 64) {
-      const float x = row[j];
-      if (!isfinite(x)) bad = 1;
-      if (j != i) rs += fabs((double)x);
+    if ((n & 3) == 0 && ((uintptr_t)h & 15) == 0) {   // 16-byte loads, 4 consecutive columns per lane
+      const f32x4* row4 = (const f32x4*)row;
+      for (int q = lane; q < (n >> 2); q += 64) {
+        const f32x4 x = row4[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (!isfinite(x[e])) bad = 1;
+          if (4 * q + e != i) rs += fabs((double)x[e]);
+        }
+      }
+    } else {
+      for (int j = lane; j < n; j += 64) {
+        const float x = row[j];
+        if (!isfinite(x)) bad = 1;
+        if (j != i) rs += fabs((double)x);
+      }
     }
     rs = wave_sum(rs);
     const double c = row[i];
@@ -1267,14 +1279,38 @@ __global__ __launch_bounds__(1024) void k_lanczos_start(double* v, double* vprev
 }
 
 // w = H v, one wave per row, FP64 accumulation.
+// One wave per row.  When rows are 16-byte aligned (n % 4 == 0, aligned H) each lane
+// takes 4 consecutive columns per load, two loads in flight on separate
+// accumulators; otherwise one column per lane.  The summation order is fixed.
 __global__ __launch_bounds__(256) void k_gemv(const float* h, const double* v, double* w, int n) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   const float* row = h + (size_t)i * n;
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc += (double)row[j] * v[j];
-  acc = wave_sum(acc);
+  double acc0 = 0.0, acc1 = 0.0;
+  if ((n & 3) == 0 && ((uintptr_t)h & 15) == 0) {
+    const int n4 = n >> 2;
+    const f32x4* row4 = (const f32x4*)row;
+    int q = lane;
+    for (; q + 64 < n4; q += 128) {
+      const f32x4 x0 = row4[q], x1 = row4[q + 64];
+      const double* v0 = v + 4 * (size_t)q;
+      const double* v1 = v0 + 256;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc0 += (double)x0[e] * v0[e];
+        acc1 += (double)x1[e] * v1[e];
+      }
+    }
+    if (q < n4) {
+      const f32x4 x0 = row4[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc0 += (double)x0[e] * v[4 * (size_t)q + e];
+    }
+  } else {
+    for (int j = lane; j < n; j += 64) acc0 += (double)row[j] * v[j];
+  }
+  const double acc = wave_sum(acc0 + acc1);
   if (lane == 0) w[i] = acc;
 }
 
