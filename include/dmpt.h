@@ -106,7 +106,10 @@ typedef struct dmpt_opts {
   double idem_tol;        /* also stop when ||X_n - X_n^2||_F^2 <= idem_tol; 0 -> parameter-free test only */
   int32_t project;        /* susceptibility only: 1 -> finish with the occupied-virtual projection
                              (two sweep steps with X frozen at D: sigma = +1 then -1, in the
-                             precision of the recursion; FP32 when it is plain BF16) */
+                             precision of the recursion; FP32 when it is plain BF16).  When the
+                             launch after the last step took sigma = +1 (forward sweep, one
+                             precision for all products), its Y is the first of the two and
+                             is used as it is. */
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
   int32_t ckpt_interval;  /* ADJOINT sweep only: keep X_n every ckpt_interval steps and recompute
                              the steps in between during the backward sweep; 0 -> keep every X_n */
@@ -125,7 +128,8 @@ typedef struct dmpt_info {
   double trace_d;                       /* Tr D (FP64) */
   double idem_err;                      /* ||D - D^2||_F^2 (FP64 sum of the step kernel's FP32 values) */
   double elapsed_ms;                    /* device time of the call (events on opts.stream) */
-  int8_t sigma[DMPT_MAX_STEPS + 1];     /* sigma_n, n = 1..m */
+  int8_t sigma[DMPT_MAX_STEPS + 1];     /* sigma_n, n = 1..m, and at n = m + 1 the sigma of the launch after the
+                                           last step (it runs before the stop is seen; 0 if it did not run) */
   double trace_x[DMPT_MAX_STEPS + 1];   /* Tr X_n, n = 1..m+1 */
   double sqnorm_x[DMPT_MAX_STEPS + 1];  /* ||X_n||_F^2, n = 1..m+1 */
   double idem_x[DMPT_MAX_STEPS + 1];    /* eps_n = ||X_n - X_n^2||_F^2, n = 1..m+1 (0 if not formed) */

@@ -72,7 +72,8 @@ class Info(C.Structure):
             "m": m, "status": STATUS.get(self.status, self.status), "emin": self.emin,
             "emax": self.emax, "beta": self.beta, "trace_d": self.trace_d,
             "idem_err": self.idem_err, "elapsed_ms": self.elapsed_ms,
-            "sigma": list(self.sigma[:m]), "trace_x": list(self.trace_x[:m + 1]),
+            "sigma": list(self.sigma[:m]), "sigma_next": int(self.sigma[m]) if m < len(self.sigma) else 0,
+            "trace_x": list(self.trace_x[:m + 1]),
             "sqnorm_x": list(self.sqnorm_x[:m + 1]),
             "idem_x": list(self.idem_x[:m + 1]),
             "bounds_ms": self.bounds_ms, "step_ms": self.step_ms, "project_ms": self.project_ms,

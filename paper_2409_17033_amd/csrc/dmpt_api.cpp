@@ -675,7 +675,27 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.ctl = ctl;
     auto view = [&](MatRef m) { return pprec == kFP32 ? as_fp32(m) : m; };
     b.x_in = view(x_ref(p, ws, xfin));
-    for (int q = 0; q < 2; ++q) {
+    // The launch after the last step (it ran before the stop was seen, since
+    // the stopping test needs its idempotency error) formed Z = D Y + Y D from
+    // D = X_{m+1} and Y_{m+1}, the product of the first projection step.
+    // When every product runs in one precision that launch replaces the first
+    // projection step: with sigma = +1 its Y_{m+2} = Z is bit for bit what the
+    // step would write (same kernel, inputs, tile products and accumulation
+    // order); with sigma = -1, Y_{m+2} = 2 Y_{m+1} - Z and one elementwise pass
+    // recovers Z = 2 Y_{m+1} - Y_{m+2} (one more FP32 rounding), with its
+    // operand copy at the scale the step would use (Y_{m+2}'s own: both come
+    // from Y_{m+1}) and fresh norm partials for the second step.
+    const int sig_next = hctl.rec[m + 1].sigma;
+    const bool reuse_first = !adjoint && !split_launch && pprec == xprec && hctl.code == kDecideStop &&
+                             (sig_next == 1 || sig_next == -1);
+    int q0 = 0;
+    if (reuse_first) {
+      if (sig_next == -1)
+        DMPT_HIP(launch_reflect(pprec, y_ref(p, ws, yfin), y_ref(p, ws, yfin ^ 1), p.n_pad, nobs, s));
+      yfin ^= 1;
+      q0 = 1;
+    }
+    for (int q = q0; q < 2; ++q) {
       b.fixed_sigma = q == 0 ? 1 : -1;
       b.write_split = q == 0 && pprec != kFP32;   // the second step reads it
       b.y_in = view(y_ref(p, ws, yfin));
@@ -712,7 +732,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       info->trace_x[q - 1] = hctl.rec[q].tr;
       info->sqnorm_x[q - 1] = hctl.rec[q].sq;
       info->idem_x[q - 1] = hctl.rec[q].eps;
-      if (q <= m) info->sigma[q - 1] = (int8_t)hctl.rec[q].sigma;
+      info->sigma[q - 1] = (int8_t)hctl.rec[q].sigma;   // q = m + 1: the launch after the last step (0 if it did not run)
     }
     info->trace_d = hctl.rec[m + 1].tr;
     info->idem_err = hctl.rec[m + 1].eps;

@@ -178,6 +178,9 @@ hipError_t launch_gemm_op(int prec, const void* A, const void* B, float* C, int 
 hipError_t launch_split_copy(const float* src, void* dst, int n_pad, int e, hipStream_t s);
 hipError_t launch_pad(const float* src, int n, int n_pad, float* dst, int transpose, hipStream_t s);
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);
+// b <- 2 a - b for nmat matrices (FP32 masters), rewriting b's operand copy at
+// the scale b's metadata holds and b's norm partials.
+hipError_t launch_reflect(int prec, MatRef a, MatRef b, int n_pad, int nmat, hipStream_t s);
 int stage_k(int prec);   // k values per pipeline stage of the step kernel
 
 }  // namespace dmpt

@@ -1423,6 +1423,52 @@ hipError_t launch_split_copy(const float* src, void* dst, int n_pad, int e, hipS
   return hipGetLastError();
 }
 
+// b <- 2 a - b for every observable (FP32 masters, n_pad x n_pad, one
+// rounding as in the step epilogue), with b's operand copy rewritten at the
+// scale b's metadata records (kSplitH) and b's norm partials replaced by one
+// FP64 partial of ||b||_F^2 per 64 x 64 block.  Grid (n_pad / 64,
+// n_pad / 64, observables).
+__global__ __launch_bounds__(256) void k_reflect(int prec, MatRef a, MatRef b, int n_pad) {
+  __shared__ double s_red[4];
+  const int z = blockIdx.z, bi = blockIdx.y, bj = blockIdx.x, nb = gridDim.x;
+  const float* ya = a.f32 + (size_t)z * a.stride_f32;
+  float* yb = b.f32 + (size_t)z * b.stride_f32;
+  char* op = (char*)b.op + (size_t)z * b.stride_op;
+  MatMeta* mm = (MatMeta*)(b.meta + (size_t)z * b.stride_op);
+  const float sc = prec == kSplitH ? ldexpf(1.0f, mm->scale) : 1.0f;
+  double sq = 0.0;
+  for (int g = threadIdx.x; g < 64 * 8; g += 256) {
+    const int r = bi * 64 + (g >> 3), c0 = bj * 64 + (g & 7) * 8;
+    const size_t o = (size_t)r * n_pad + c0;
+    const f32x4 a0 = *(const f32x4*)(ya + o), a1 = *(const f32x4*)(ya + o + 4);
+    const f32x4 b0 = *(const f32x4*)(yb + o), b1 = *(const f32x4*)(yb + o + 4);
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = 2.0f * a0[e] - b0[e];
+      v[4 + e] = 2.0f * a1[e] - b1[e];
+    }
+    *(f32x4*)(yb + o) = f32x4{v[0], v[1], v[2], v[3]};
+    *(f32x4*)(yb + o + 4) = f32x4{v[4], v[5], v[6], v[7]};
+    if (prec != kFP32) store_group8(prec, op, n_pad, r, c0, v, sc);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sq += (double)v[e] * (double)v[e];
+  }
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mm->nrm[bi * nb + bj] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (bi == 0 && bj == 0) mm->count = nb * nb;
+  }
+}
+
+hipError_t launch_reflect(int prec, MatRef a, MatRef b, int n_pad, int nmat, hipStream_t s) {
+  if (nmat <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reflect, dim3(n_pad / 64, n_pad / 64, nmat), dim3(256), 0, s, prec, a, b, n_pad);
+  return hipGetLastError();
+}
+
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s) {
   if (prec == kFP32 || nmat <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_resplit, dim3(1024, nmat), dim3(256), 0, s, prec, m, n_pad);

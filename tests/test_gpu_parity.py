@@ -143,6 +143,28 @@ def test_response_kernel(gpu):
         assert np.allclose(out, ref, rtol=1e-12, atol=1e-9 * n)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16", "split3_bf16"])
+def test_projection_after_either_last_sigma(gpu, prec):
+    """The launch after the last step runs before the stop is seen; when it
+    took sigma = +1 its Y is the first projection step, which is then not
+    launched again.  Seeded systems with both values of that sigma must match
+    the closed form (info["sigma_next"] reports it)."""
+    dm = _dm()
+    seen = set()
+    for seed in range(12):
+        n, nocc = 200, 60 + 7 * seed
+        h, _, _ = W.known_spectrum(n, nocc, gap=0.3, seed=seed)
+        a = W.random_perturbations(n, 1, seed=100 + seed)[0]
+        h32, a32 = h.astype(np.float32), a.astype(np.float32)
+        chi, D, a0, info = dm.susceptibility(_dev(h32, gpu), _dev(a32, gpu), nocc, precision=prec)
+        seen.add(info["sigma_next"])
+        ref = cf.susceptibility(h32.astype(np.float64), a32.astype(np.float64), nocc, spin=2.0)
+        err = cf.rel_frobenius(_np(chi), ref)
+        print(f"seed {seed} nocc {nocc} {prec}: M={info['m']} sigma_next={info['sigma_next']} errchi={err:.2e}")
+        assert err <= TOL[prec], seed
+    assert seen == {1, -1}, seen
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_adjoint_sweep_matches_forward(gpu, prec):
     dm = _dm()
