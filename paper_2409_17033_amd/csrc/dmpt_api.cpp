@@ -195,12 +195,12 @@ MatRef as_fp32(MatRef m) {
 // groups of kGroupI x kGroupJ neighbouring tiles (a group shares kGroupI
 // 256-row A panels and kGroupJ 128-row B panels; groups on the diagonal are
 // the upper-triangle part of their square, 20 tiles), and whole groups are
-// dealt to the eight XCDs: workgroups are dispatched round-robin over the
-// XCDs in grid order (block b runs on XCD b % 8), so position p of the list
-// is given the next tile of the queue of XCD p % 8.  One XCD holds 32
-// resident workgroups, so a full group keeps them streaming the same panels
-// through its L2.  Full groups go first in every queue and are dealt to the
-// queue with the fewest tiles; the partial diagonal groups close the queues.
+// dealt to the eight XCDs: position p of the list belongs to the queue of XCD
+// p % 8, from which the step kernel's workgroups on that XCD take their tiles
+// in order.  One XCD holds 32 resident workgroups, so a full group keeps them
+// streaming the same panels through its L2.  Full groups go first in every
+// queue and are dealt to the queue with the fewest tiles; the partial diagonal
+// groups close the queues.
 constexpr int kXcds = 8, kGroupI = 4, kGroupJ = 8;
 
 std::vector<std::vector<std::pair<int, int>>> tile_groups(int n_pad) {
