@@ -154,14 +154,16 @@ def test_projection_after_either_last_sigma(gpu, prec):
     for seed in range(12):
         n, nocc = 200, 60 + 7 * seed
         h, _, _ = W.known_spectrum(n, nocc, gap=0.3, seed=seed)
-        a = W.random_perturbations(n, 1, seed=100 + seed)[0]
+        a = W.random_perturbations(n, 2, seed=100 + seed)      # two observables: one pass each
         h32, a32 = h.astype(np.float32), a.astype(np.float32)
         chi, D, a0, info = dm.susceptibility(_dev(h32, gpu), _dev(a32, gpu), nocc, precision=prec)
         seen.add(info["sigma_next"])
-        ref = cf.susceptibility(h32.astype(np.float64), a32.astype(np.float64), nocc, spin=2.0)
-        err = cf.rel_frobenius(_np(chi), ref)
-        print(f"seed {seed} nocc {nocc} {prec}: M={info['m']} sigma_next={info['sigma_next']} errchi={err:.2e}")
-        assert err <= TOL[prec], seed
+        for k in range(2):
+            ref = cf.susceptibility(h32.astype(np.float64), a32[k].astype(np.float64), nocc, spin=2.0)
+            err = cf.rel_frobenius(_np(chi[k]), ref)
+            print(f"seed {seed} nocc {nocc} obs {k} {prec}: M={info['m']} sigma_next={info['sigma_next']} "
+                  f"errchi={err:.2e}")
+            assert err <= TOL[prec], (seed, k)
     assert seen == {1, -1}, seen
 
 
