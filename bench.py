@@ -44,7 +44,51 @@ def parse():
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5, help="FP64 oracle SP2+chi steps in the CPU sample")
+    ap.add_argument("--extra", choices=["fermi", "nonorth"], default=None,
+                    help="instead of the headline metric, time the finite-temperature path (Sec. V.B: "
+                         "gapless banded H, kT = 0.01, one random observable) or the non-orthonormal one "
+                         "(Sec. V.A: the headline workload with Z = I + 1e-3 G) and print their own JSON line")
     return ap.parse_args()
+
+
+def run_extra(args, dm, torch, W, dev):
+    """Time one of the Sec. V paths in args.precision and FP32 (steps timed
+    calls after warmup ones, inputs resident); prints one JSON line."""
+    t = time.perf_counter()
+    if args.extra == "fermi":
+        wl = W.banded_gapless(args.n, half_bandwidth=256, nobs=1)
+        H, A = torch.from_numpy(wl.H).to(dev), torch.from_numpy(wl.A[0]).to(dev)
+        call = lambda prec: dm.susceptibility_fermi(H, A, wl.nocc, 0.01, precision=prec)
+        workload = f"gapless banded H (half-bandwidth 256), N={wl.n}, N_occ={wl.nocc}, kT=0.01, one random observable"
+    else:
+        wl = W.banded_gapped(args.n, cfg=2)
+        H, A = torch.from_numpy(wl.H).to(dev), torch.from_numpy(wl.A[0]).to(dev)
+        g = torch.Generator(device=dev).manual_seed(0)
+        Z = torch.eye(wl.n, device=dev) + 1e-3 * torch.randn(wl.n, wl.n, device=dev, generator=g)
+        call = lambda prec: dm.susceptibility_nonorth(H, Z, A, wl.nocc, precision=prec)
+        workload = f"headline workload N={wl.n} in a basis with inverse factor Z = I + 1e-3 G"
+    log(f"{args.extra} workload N={wl.n} generated in {time.perf_counter() - t:.1f} s")
+    torch.cuda.synchronize()
+    paths = {}
+    for prec in dict.fromkeys([args.precision, "fp32"]):
+        for _ in range(args.warmup):
+            call(prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            out = call(prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / max(args.steps, 1)
+        info = out[-1]
+        paths[prec] = {"ms": round(ms, 3), "device_ms": round(info["elapsed_ms"], 3)}
+        if args.extra == "fermi":
+            paths[prec].update({"mu": info["mu"], "doublings": info["doublings"], "newton": info["newton"],
+                                "products": info["products"]})
+        else:
+            paths[prec]["m"] = info["m"]
+        log(f"{args.extra} {prec}: {ms:.1f} ms  {paths[prec]}")
+    print(json.dumps({"extra": args.extra, "unit": "ms", "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic", "config": {"workload": workload, "n": wl.n}, "paths": paths}), flush=True)
 
 
 def property_errors(torch, H, A, D, chi, nocc, spin):
@@ -148,6 +192,9 @@ def main():
 
     dm.load()
     dev = torch.device("cuda:0")
+    if args.extra:
+        run_extra(args, dm, torch, W, dev)
+        return
     t = time.perf_counter()
     wl = W.banded_gapped(args.n, cfg=2)
     log(f"workload N={wl.n} generated in {time.perf_counter() - t:.1f} s")
