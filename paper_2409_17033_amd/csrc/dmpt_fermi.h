@@ -17,7 +17,7 @@ hipError_t launch_axpby(float* z, const float* x, float a, const float* y, float
 hipError_t launch_symm(const float* in, float alpha, const float* x, float beta, float* out, int n_pad,
                        hipStream_t s);
 // FP64 per-row-block partials over the leading n x n block: part[2b] = trace,
-// part[2b + 1] = sum of squares, b = 0 .. n_pad / 64 - 1.
+// part[2b + 1] = sum of squares, b = 0 .. n_pad / 4 - 1 (four rows per block).
 hipError_t launch_trace_sq(const float* m, int n, int n_pad, double* part, hipStream_t s);
 int trace_sq_blocks(int n_pad);
 

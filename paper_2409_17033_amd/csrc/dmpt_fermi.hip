@@ -75,22 +75,44 @@ __global__ __launch_bounds__(256) void k_symm(const float* in, float alpha, cons
 
 // Block b sums rows 64b .. 64b + 63 of the leading n x n block, one wave per
 // 16 rows, in a fixed order.
+// (Tr M, ||M||_F^2) over the leading n x n block of an n_pad-strided matrix:
+// one wave per row, 16-byte loads when the rows allow it (n % 4 == 0 and M
+// 16-byte aligned), two accumulators per lane; block b adds its four rows in
+// order into part[2b], part[2b + 1] (the host sums the blocks in order).
 __global__ __launch_bounds__(256) void k_trace_sq(const float* m, int n, int n_pad, double* part) {
   __shared__ double s_tr[4], s_sq[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double tr = 0.0, sq = 0.0;
-  for (int k = 0; k < 16; ++k) {
-    const int i = blockIdx.x * 64 + wave * 16 + k;
-    if (i >= n) break;
+  const int i = blockIdx.x * 4 + wave;
+  double tr = 0.0, sq0 = 0.0, sq1 = 0.0;
+  if (i < n) {
     const float* row = m + (size_t)i * n_pad;
-    for (int j = lane; j < n; j += 64) {
-      const double v = row[j];
-      sq += v * v;
-      if (j == i) tr += v;
+    if ((n & 3) == 0 && ((uintptr_t)m & 15) == 0) {
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const f4* row4 = (const f4*)row;
+      const int n4 = n >> 2;
+      int q = lane;
+      for (; q + 64 < n4; q += 128) {
+        const f4 x0 = row4[q], x1 = row4[q + 64];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          sq0 += (double)x0[e] * (double)x0[e];
+          sq1 += (double)x1[e] * (double)x1[e];
+        }
+      }
+      if (q < n4) {
+        const f4 x0 = row4[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sq0 += (double)x0[e] * (double)x0[e];
+      }
+    } else {
+      for (int j = lane; j < n; j += 64) {
+        const double v = row[j];
+        sq0 += v * v;
+      }
     }
+    if (lane == 0) tr = row[i];
   }
-  tr = wave_sum64(tr);
-  sq = wave_sum64(sq);
+  const double sq = wave_sum64(sq0 + sq1);
   if (lane == 0) {
     s_tr[wave] = tr;
     s_sq[wave] = sq;
@@ -124,7 +146,7 @@ hipError_t launch_symm(const float* in, float alpha, const float* x, float beta,
   return hipGetLastError();
 }
 
-int trace_sq_blocks(int n_pad) { return n_pad / 64; }
+int trace_sq_blocks(int n_pad) { return n_pad / 4; }   // one row per wave, four per block
 
 hipError_t launch_trace_sq(const float* m, int n, int n_pad, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_trace_sq, dim3(trace_sq_blocks(n_pad)), dim3(256), 0, s, m, n, n_pad, part);
