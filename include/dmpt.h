@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 3
+#define DMPT_ABI_VERSION 4
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -384,18 +384,21 @@ dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, flo
 
 /* Host mirror of the device-side step controller (pure function, no device).
  * Decision for iterate X_n (Sec. II) from FP64 Tr X_n, ||X_n||_F^2, its
- * idempotency error eps = ||X_n - X_n^2||_F^2, eps_prev2 = eps_{n-2} and the
- * number of steps taken (steps = n - 1), tested in this order:
+ * idempotency error eps = ||X_n - X_n^2||_F^2, the earlier errors
+ * eps_prevK = eps_{n-K} (K = 1, 2, 3; eps_prev3 is read only when steps >= 3)
+ * and the number of steps taken (steps = n - 1), tested in this order:
  *   -3       : bounds violation (X_n left the [0,1] spectrum envelope)
  *    0       : stop, X_n is the result: steps >= min_iter and either
  *              eps <= idem_tol, or eps >= eps_prev2 with eps < 1/64
- *              (rounding floor reached; needs steps >= 2)
+ *              (needs steps >= 2) and the rise is at the rounding floor:
+ *              eps <= 128 n 2^-48 (FP32 storage of X_n), or the previous
+ *              test rose too (eps_prev1 >= eps_prev3, steps >= 3)
  *   +1 / -1  : sigma_n for the next step (Tr X_{n+1} closest to N_occ).
  * The step limit (max_iter, status NOT_CONVERGED) is applied by the caller.
  * The device makes the same decisions, the stopping test one launch later
  * (eps_n is a by-product of the launch that forms X_n^2). */
-int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev2, int32_t steps,
-                        int32_t n, double nocc, int32_t min_iter, double idem_tol);
+int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev1, double eps_prev2, double eps_prev3,
+                        int32_t steps, int32_t n, double nocc, int32_t min_iter, double idem_tol);
 
 const char* dmpt_status_string(dmpt_status status);
 const char* dmpt_last_error(void);

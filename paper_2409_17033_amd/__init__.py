@@ -231,10 +231,12 @@ def response(chi, H1, *, stream=None):
     return np.array(out[:], dtype=np.float64).reshape(k, p)
 
 
-def sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter=10, idem_tol=0.0) -> int:
+def sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc, min_iter=10, idem_tol=0.0) -> int:
     """Host mirror of the device step controller (dmpt_sp2_decide in include/dmpt.h):
-    -3 bounds violation, 0 stop, else sigma_n (+1 / -1) for iterate X_n."""
-    return int(load().dmpt_sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter, idem_tol))
+    -3 bounds violation, 0 stop, else sigma_n (+1 / -1) for iterate X_n, from
+    eps_n and eps_{n-1}, eps_{n-2}, eps_{n-3}."""
+    return int(load().dmpt_sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc,
+                                      min_iter, idem_tol))
 
 
 def scf_response(H0, U, A, nocc: int, *, mixer: str = "linear", max_iter: int = 200, mix: float = 0.3,

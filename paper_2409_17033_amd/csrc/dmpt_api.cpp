@@ -110,11 +110,14 @@ struct Plan {
 // Two-level accumulation: the MFMA accumulator is added into the running tile
 // sum every `flush` groups of 4 pipeline stages.  Balancing the inner chain
 // (F stages x MFMAs per stage per block) against the outer one (stages / F)
-// gives F ~ sqrt(stages / chain).
+// gives F ~ sqrt(stages / chain); the constant is measured: the chi error
+// against the closed form is U-shaped in F, with its minimum at about 3/8 of
+// sqrt(stages / chain) for FP32, the FP16 split and the three-term BF16 split
+// at N = 4096 and 8192 (outer FP32 sums cost more than inner MFMA ones).
 int flush_interval(int prec, int n_pad) {
   const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : (prec == kSplit2 || prec == kSplit32 || prec == kSplitH) ? 3 : 2;
   const int stages = n_pad / stage_k(prec);
-  const double f = std::sqrt((double)stages / chain) / 4.0;
+  const double f = std::sqrt((double)stages / chain) * 0.375;
   return std::max(1, (int)std::lround(f));
 }
 
@@ -1740,9 +1743,9 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
   return DMPT_OK;
 }
 
-int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev2, int32_t steps, int32_t n,
-                        double nocc, int32_t min_iter, double idem_tol) {
-  return sp2_decide(tr, sq, eps, eps_prev2, steps, n, nocc, min_iter, idem_tol);
+int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev1, double eps_prev2, double eps_prev3,
+                        int32_t steps, int32_t n, double nocc, int32_t min_iter, double idem_tol) {
+  return sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc, min_iter, idem_tol);
 }
 
 const char* dmpt_status_string(dmpt_status st) {

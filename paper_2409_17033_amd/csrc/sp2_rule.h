@@ -11,10 +11,17 @@
 // stop: with the idempotency error eps_n = ||X_n - X_n^2||_F^2 (the sum of
 //   (x - x^2)^2 over the spectrum of X_n, >= 0), stop at X_n once at least
 //   min_iter steps were taken and either eps_n <= idem_tol, or
-//   eps_n >= eps_{n-2} while eps_n < 1/64: every state is resolved
-//   (|x - x^2| < 1/8) and two more steps did not reduce the error, so the
-//   rounding floor of the arithmetic is reached.  Without a gap at N_occ a
-//   state stays near x = 1/2 and only the step limit ends the recursion.
+//   eps_n >= eps_{n-2} while eps_n < 1/64 (every state is resolved,
+//   |x - x^2| < 1/8, and two more steps did not reduce the error) and the
+//   rise is at the rounding floor: eps_n <= 128 n u^2 with u = 2^-24 (the
+//   iterate is stored in FP32, so each eigenvalue carries noise of order u
+//   and eps cannot fall much below n u^2), or the previous test rose too,
+//   eps_{n-1} >= eps_{n-3}.  One rise far above the floor is not enough:
+//   once rounding has put eigenvalues on both sides of 0 (or of 1), the
+//   trace no longer shows which side dominates eps, and a sigma that doubles
+//   the larger side's deviations raises eps before the floor is reached;
+//   the next steps bring it down again.  Without a gap at N_occ a state
+//   stays near x = 1/2 and only the step limit ends the recursion.
 // bounds: a spectrum inside [0, 1] keeps 0 <= ||X||_F^2 <= n and
 //   0 <= Tr X <= n; leaving that envelope (or non-finite traces) means the
 //   spectral bounds did not enclose H and the recursion diverges.
@@ -38,18 +45,23 @@ enum DecideCode : int {
 };
 
 constexpr double kUnresolved = 1.0 / 64.0;
+constexpr double kFloorFactor = 128.0;
+constexpr double kUnitFP32 = 5.9604644775390625e-08;   // 2^-24
 
 DMPT_HD inline bool sp2_bounds_ok(double tr, double sq, int n) {
   if (!(isfinite(tr) && isfinite(sq))) return false;
   return !(sq > n + 1.0 || tr < -1.0 || tr > n + 1.0);
 }
 
-// Stopping test for X_n: steps = n - 1, eps = eps_n, eps_prev2 = eps_{n-2}.
-DMPT_HD inline bool sp2_should_stop(double eps, double eps_prev2, int steps, int min_iter,
-                                    double idem_tol) {
+// Stopping test for X_n: steps = n - 1, eps = eps_n, eps_prevK = eps_{n-K}
+// (eps_prev3 is read only when steps >= 3).
+DMPT_HD inline bool sp2_should_stop(double eps, double eps_prev1, double eps_prev2, double eps_prev3,
+                                    int steps, int n, int min_iter, double idem_tol) {
   if (steps < min_iter) return false;
   if (eps <= idem_tol) return true;
-  return steps >= 2 && eps >= eps_prev2 && eps < kUnresolved;
+  if (!(steps >= 2 && eps >= eps_prev2 && eps < kUnresolved)) return false;
+  if (eps <= kFloorFactor * n * kUnitFP32 * kUnitFP32) return true;
+  return steps >= 3 && eps_prev1 >= eps_prev3;
 }
 
 DMPT_HD inline int sp2_sigma(double tr, double sq, double nocc) {
@@ -60,10 +72,10 @@ DMPT_HD inline int sp2_sigma(double tr, double sq, double nocc) {
 
 // Decision for iterate X_n given its traces and idempotency errors (the
 // oracle's order: bounds, stop, sigma).
-DMPT_HD inline int sp2_decide(double tr, double sq, double eps, double eps_prev2, int steps, int n,
-                              double nocc, int min_iter, double idem_tol) {
+DMPT_HD inline int sp2_decide(double tr, double sq, double eps, double eps_prev1, double eps_prev2,
+                              double eps_prev3, int steps, int n, double nocc, int min_iter, double idem_tol) {
   if (!sp2_bounds_ok(tr, sq, n)) return kDecideBounds;
-  if (sp2_should_stop(eps, eps_prev2, steps, min_iter, idem_tol)) return kDecideStop;
+  if (sp2_should_stop(eps, eps_prev1, eps_prev2, eps_prev3, steps, n, min_iter, idem_tol)) return kDecideStop;
   return sp2_sigma(tr, sq, nocc);
 }
 

@@ -36,7 +36,7 @@ def test_exports_every_declared_function(lib):
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 3
+    assert lib.dmpt_abi_version() == 4
 
 
 def test_struct_layouts():
@@ -228,7 +228,7 @@ def test_controller_sigma_matches_oracle_rule():
         nocc = float(rng.integers(1, n))
         tr = rng.uniform(0, n)
         sq = tr * rng.uniform(0.0, 1.0)
-        got = dm.sp2_decide(tr, sq, 0.5, 0.0, 0, n, nocc, min_iter=10)
+        got = dm.sp2_decide(tr, sq, 0.5, 0.0, 0.0, 0.0, 0, n, nocc, min_iter=10)
         assert got == sp2.choose_sigma(tr, sq, nocc)
 
 
@@ -244,8 +244,10 @@ def test_controller_replays_oracle_run():
         _, tr = sp2.sp2_density(h, wl.nocc)
         for n in range(1, tr.m + 2):
             t, q, e = tr.traces[n - 1], tr.sqnorms[n - 1], tr.errors[n - 1]
+            e1 = tr.errors[n - 2] if n >= 2 else 0.0
             e2 = tr.errors[n - 3] if n >= 3 else 0.0
-            code = dm.sp2_decide(t, q, e, e2, n - 1, wl.n, wl.nocc, 10, 0.0)
+            e3 = tr.errors[n - 4] if n >= 4 else 0.0
+            code = dm.sp2_decide(t, q, e, e1, e2, e3, n - 1, wl.n, wl.nocc, 10, 0.0)
             if n <= tr.m:
                 assert code == tr.sigmas[n - 1], n
             else:
@@ -254,23 +256,32 @@ def test_controller_replays_oracle_run():
 
 def test_controller_error_codes():
     import paper_2409_17033_amd as dm
+    d = dm.sp2_decide     # (tr, sq, eps, eps_{n-1}, eps_{n-2}, eps_{n-3}, steps, n, nocc, ...)
     # bounds violations come first
-    assert dm.sp2_decide(float("nan"), 1.0, 0.0, 0.0, 0, 10, 5) == -3
-    assert dm.sp2_decide(5.0, 12.0, 0.0, 0.0, 0, 10, 5) == -3        # ||X||^2 > n + 1
-    assert dm.sp2_decide(-2.0, 1.0, 0.0, 0.0, 0, 10, 5) == -3
-    assert dm.sp2_decide(5.0, float("inf"), 0.0, 0.0, 20, 10, 5) == -3
+    assert d(float("nan"), 1.0, 0.0, 0.0, 0.0, 0.0, 0, 10, 5) == -3
+    assert d(5.0, 12.0, 0.0, 0.0, 0.0, 0.0, 0, 10, 5) == -3        # ||X||^2 > n + 1
+    assert d(-2.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0, 10, 5) == -3
+    assert d(5.0, float("inf"), 0.0, 0.0, 0.0, 0.0, 20, 10, 5) == -3
     # a state at x = 1/2 ((x - x^2)^2 = 1/16 >= 1/64) never stops, even stalled
-    assert dm.sp2_decide(5.0, 4.75, 1 / 16, 1 / 16, 20, 10, 5) in (1, -1)
-    # floor reached: eps stopped falling over two steps and is resolved
-    assert dm.sp2_decide(5.0, 5.0, 1e-12, 1e-12, 20, 10, 5) == 0
-    assert dm.sp2_decide(5.0, 5.0, 2e-12, 1e-12, 20, 10, 5) == 0
+    assert d(5.0, 4.75, 1 / 16, 1 / 16, 1 / 16, 1 / 16, 20, 10, 5) in (1, -1)
+    # floor reached: eps stopped falling over two steps and is within 128 n u^2
+    # (u = 2^-24; 128 * 10 * 2^-48 = 4.5e-12)
+    assert d(5.0, 5.0, 1e-12, 1e-9, 1e-12, 1e-6, 20, 10, 5) == 0
+    assert d(5.0, 5.0, 2e-12, 1e-9, 1e-12, 1e-6, 20, 10, 5) == 0
     # still falling: continue
-    assert dm.sp2_decide(5.0, 5.0, 1e-12, 1e-9, 20, 10, 5) in (1, -1)
+    assert d(5.0, 5.0, 1e-12, 1e-6, 1e-9, 1e-3, 20, 10, 5) in (1, -1)
+    # a single rise far above the floor does not stop (the previous test fell) ...
+    assert d(5.0, 5.0, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10, 5) in (1, -1)
+    # ... a second rise in a row does, at any level below 1/64
+    assert d(5.0, 5.0, 1.2e-8, 3.1e-9, 3.5e-9, 3.0e-9, 20, 10, 5) == 0
+    assert d(5.0, 5.0, 1e-3, 1e-4, 1e-4, 1e-5, 20, 10, 5) == 0
+    # the floor scales with n: the same single rise stops for n = 10^6 (5.8e-7)
+    assert d(5e5, 5e5, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10 ** 6, 5e5) == 0
     # before min_iter no stop even at the floor
-    assert dm.sp2_decide(5.0, 5.0, 1e-12, 1e-12, 3, 10, 5) in (1, -1)
+    assert d(5.0, 5.0, 1e-12, 1e-12, 1e-12, 1e-12, 3, 10, 5) in (1, -1)
     # exactly idempotent / idem_tol
-    assert dm.sp2_decide(5.0, 5.0, 0.0, 0.0, 10, 10, 5) == 0
-    assert dm.sp2_decide(5.0, 5.0, 5e-7, 1e-9, 20, 10, 5, 10, 1e-6) == 0
+    assert d(5.0, 5.0, 0.0, 0.0, 0.0, 0.0, 10, 10, 5) == 0
+    assert d(5.0, 5.0, 5e-7, 1e-9, 1e-9, 1e-9, 20, 10, 5, 10, 1e-6) == 0
 
 
 def test_nonorth_sizes_and_validation(lib):
