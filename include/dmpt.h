@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 4
+#define DMPT_ABI_VERSION 5
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -391,14 +391,17 @@ dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, flo
  *    0       : stop, X_n is the result: steps >= min_iter and either
  *              eps <= idem_tol, or eps >= eps_prev2 with eps < 1/64
  *              (needs steps >= 2) and the rise is at the rounding floor:
- *              eps <= 128 n 2^-48 (FP32 storage of X_n), or the previous
- *              test rose too (eps_prev1 >= eps_prev3, steps >= 3)
+ *              eps <= 128 n u^2, u the unit roundoff of X_n^2 in the given
+ *              dmpt_precision (2^-16 for DMPT_SPLIT_BF16, 2^-8 for DMPT_BF16,
+ *              2^-24 otherwise), or the previous test rose too
+ *              (eps_prev1 >= eps_prev3, steps >= 3)
  *   +1 / -1  : sigma_n for the next step (Tr X_{n+1} closest to N_occ).
  * The step limit (max_iter, status NOT_CONVERGED) is applied by the caller.
  * The device makes the same decisions, the stopping test one launch later
  * (eps_n is a by-product of the launch that forms X_n^2). */
 int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev1, double eps_prev2, double eps_prev3,
-                        int32_t steps, int32_t n, double nocc, int32_t min_iter, double idem_tol);
+                        int32_t steps, int32_t n, double nocc, int32_t min_iter, double idem_tol,
+                        int32_t precision);
 
 const char* dmpt_status_string(dmpt_status status);
 const char* dmpt_last_error(void);

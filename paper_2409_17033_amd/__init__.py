@@ -231,12 +231,13 @@ def response(chi, H1, *, stream=None):
     return np.array(out[:], dtype=np.float64).reshape(k, p)
 
 
-def sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc, min_iter=10, idem_tol=0.0) -> int:
+def sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc, min_iter=10, idem_tol=0.0,
+               precision: str = "fp32") -> int:
     """Host mirror of the device step controller (dmpt_sp2_decide in include/dmpt.h):
     -3 bounds violation, 0 stop, else sigma_n (+1 / -1) for iterate X_n, from
-    eps_n and eps_{n-1}, eps_{n-2}, eps_{n-3}."""
+    eps_n and eps_{n-1}, eps_{n-2}, eps_{n-3}, for the product precision."""
     return int(load().dmpt_sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc,
-                                      min_iter, idem_tol))
+                                      min_iter, idem_tol, PRECISION[precision]))
 
 
 def scf_response(H0, U, A, nocc: int, *, mixer: str = "linear", max_iter: int = 200, mix: float = 0.3,

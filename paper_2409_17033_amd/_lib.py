@@ -23,7 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
-ABI_VERSION = 4   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
+ABI_VERSION = 5   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
 PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4, "split_fp16": 5}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
@@ -181,7 +181,7 @@ def load() -> C.CDLL:
     lib.dmpt_mixer_train.argtypes = [P, P, P, P, I32, I32, P, P, I32, P, P, I32, I32, I32, D, C.POINTER(D), P, P,
                                      SZ]
     lib.dmpt_mixer_train.restype = C.c_int
-    lib.dmpt_sp2_decide.argtypes = [D, D, D, D, D, D, I32, I32, D, I32, D]
+    lib.dmpt_sp2_decide.argtypes = [D, D, D, D, D, D, I32, I32, D, I32, D, I32]
     lib.dmpt_sp2_decide.restype = I32
     lib.dmpt_status_string.argtypes = [C.c_int]
     lib.dmpt_status_string.restype = C.c_char_p

@@ -565,6 +565,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.nocc = o.nocc;
   a.idem_tol = o.idem_tol;
   a.decide = 1;
+  a.unit = sp2_unit(xprec);   // both launches of a split step take the same decision
   a.write_split = 1;
   a.flush = flush_interval(xprec, p.n_pad);
   a.jobs = d_jobs;
@@ -1744,8 +1745,9 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
 }
 
 int32_t dmpt_sp2_decide(double tr, double sq, double eps, double eps_prev1, double eps_prev2, double eps_prev3,
-                        int32_t steps, int32_t n, double nocc, int32_t min_iter, double idem_tol) {
-  return sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc, min_iter, idem_tol);
+                        int32_t steps, int32_t n, double nocc, int32_t min_iter, double idem_tol,
+                        int32_t precision) {
+  return sp2_decide(tr, sq, eps, eps_prev1, eps_prev2, eps_prev3, steps, n, nocc, min_iter, idem_tol, precision);
 }
 
 const char* dmpt_status_string(dmpt_status st) {

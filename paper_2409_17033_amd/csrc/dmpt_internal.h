@@ -110,6 +110,7 @@ struct StepArgs {
   int step;                  // n: computes X_{n+1}, Y_{n+1} from X_n, Y_n
   int max_iter, min_iter;
   double nocc, idem_tol;
+  double unit;               // unit roundoff of X_n^2 for the stopping test (the X product precision)
   int decide;                // 1: evaluate the controller on the partials of X_n
   int fixed_sigma;           // used when decide == 0 and sigma_src == nullptr
   const StepRec* sigma_src;  // decide == 0: sigma_n read from sigma_src[step].sigma

@@ -450,7 +450,7 @@ __device__ int step_controller(const StepArgs& a, int* s_code) {
           const double e1 = k >= 3 ? c->rec[k - 2].eps : 0.0;
           const double e2 = k >= 4 ? c->rec[k - 3].eps : 0.0;
           const double e3 = k >= 5 ? c->rec[k - 4].eps : 0.0;
-          if (sp2_should_stop(eps, e1, e2, e3, k - 2, a.n, a.min_iter, a.idem_tol)) {
+          if (sp2_should_stop(eps, e1, e2, e3, k - 2, a.n, a.min_iter, a.idem_tol, a.unit)) {
             code = kDecideStop;
             m = k - 2;
           } else if (k - 2 >= a.max_iter) {

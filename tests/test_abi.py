@@ -36,7 +36,7 @@ def test_exports_every_declared_function(lib):
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 4
+    assert lib.dmpt_abi_version() == 5
 
 
 def test_struct_layouts():
@@ -277,6 +277,10 @@ def test_controller_error_codes():
     assert d(5.0, 5.0, 1e-3, 1e-4, 1e-4, 1e-5, 20, 10, 5) == 0
     # the floor scales with n: the same single rise stops for n = 10^6 (5.8e-7)
     assert d(5e5, 5e5, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10 ** 6, 5e5) == 0
+    # the floor follows the product precision: two BF16 terms keep 16 bits
+    # (128 * 10 * 2^-32 = 3.0e-7), so a single rise at 1.2e-8 is at their floor
+    assert d(5.0, 5.0, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10, 5, precision="split_bf16") == 0
+    assert d(5.0, 5.0, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10, 5, precision="split_fp16") in (1, -1)
     # before min_iter no stop even at the floor
     assert d(5.0, 5.0, 1e-12, 1e-12, 1e-12, 1e-12, 3, 10, 5) in (1, -1)
     # exactly idempotent / idem_tol
