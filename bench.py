@@ -44,11 +44,56 @@ def parse():
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5, help="FP64 oracle SP2+chi steps in the CPU sample")
-    ap.add_argument("--extra", choices=["fermi", "nonorth"], default=None,
+    ap.add_argument("--extra", choices=["fermi", "nonorth", "shapes"], default=None,
                     help="instead of the headline metric, time the finite-temperature path (Sec. V.B: "
-                         "gapless banded H, kT = 0.01, one random observable) or the non-orthonormal one "
-                         "(Sec. V.A: the headline workload with Z = I + 1e-3 G) and print their own JSON line")
+                         "gapless banded H, kT = 0.01, one random observable), the non-orthonormal one "
+                         "(Sec. V.A: the headline workload with Z = I + 1e-3 G), or the water-cluster "
+                         "shapes of Sec. VI (N = 2400, 4560, 7224; both duality routes) and print their "
+                         "own JSON line")
     return ap.parse_args()
+
+
+def run_shapes(args, dm, torch, W, dev):
+    """The matrix shapes of Sec. VI's water clusters (Table 2): for 100, 190 and
+    301 molecules, time-to-chi and the step kernel's rate in args.precision and
+    FP32, and the first-order response by both routes of the duality:
+    Tr[chi^A H1] (timed) and s Tr[A D1] (D1 from the same recursion with H1 in
+    place of A).  Prints one JSON line."""
+    shapes = []
+    for mol in (100, 190, 301):
+        t = time.perf_counter()
+        wl = W.water_shaped(mol)
+        log(f"water-shaped N={wl.n} generated in {time.perf_counter() - t:.1f} s")
+        H, A, H1 = (torch.from_numpy(x).to(dev) for x in (wl.H, wl.A[0], wl.H1[0]))
+        n_pad = -(-wl.n // 256) * 256
+        row = {"molecules": mol, "n": wl.n, "nocc": wl.nocc, "n_pad": n_pad, "paths": {}}
+        for prec in dict.fromkeys([args.precision, "fp32"]):
+            ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, prec, args.steps, args.warmup)
+            info = infos[-1]
+            m = info["m"]
+            step_avg = info["step_ms"] / max(m, 1)
+            executed = 3.0 * float(n_pad) ** 3 * PRODUCTS[prec] / (step_avg * 1e-3) / 1e12
+            d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, precision=prec, spin=1.0, want_density=False)
+            r_d1 = 2.0 * float(dm.response(d1, A)[0, 0])
+            row["paths"][prec] = {
+                "ms": round(ms, 3), "m": m, "step_avg_ms": round(step_avg, 4),
+                "mfma_tflops": round(executed, 1), "mfma_tflops_fma1": round(executed / 2, 1),
+                "algorithmic_tflops": round(3.0 * float(wl.n) ** 3 * m / (ms * 1e-3) / 1e12, 1),
+                "tr_chi_h1": float(resp[0, 0]), "s_tr_a_d1": r_d1, "m_d1": info1["m"],
+                "props": property_errors(torch, H, A, D, chi, wl.nocc, 2.0),
+            }
+            log(f"N={wl.n} {prec}: {ms:.1f} ms  M={m}  step {step_avg:.3f} ms  MFMA {executed:.1f} TF/s  "
+                f"Tr[chi H1]={resp[0, 0]:.8f}  2Tr[A D1]={r_d1:.8f}")
+            del chi, D, d1
+            torch.cuda.empty_cache()
+        shapes.append(row)
+        del H, A, H1
+    print(json.dumps({"extra": "shapes", "unit": "ms", "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic",
+                      "config": {"workload": "water-cluster shapes of Sec. VI: N = 24 and N_occ = 5 per "
+                                             "molecule, config-2 banded H with the gap at 2 % of the width, "
+                                             "A = site position, H1 = one potential shift per atom"},
+                      "shapes": shapes}), flush=True)
 
 
 def run_extra(args, dm, torch, W, dev):
@@ -192,6 +237,9 @@ def main():
 
     dm.load()
     dev = torch.device("cuda:0")
+    if args.extra == "shapes":
+        run_shapes(args, dm, torch, W, dev)
+        return
     if args.extra:
         run_extra(args, dm, torch, W, dev)
         return

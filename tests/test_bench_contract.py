@@ -32,3 +32,27 @@ def test_traffic_figure_follows_the_kernel_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("split_fp16", 8192) is None
     assert bench.measured_traffic("no_such_precision", 8192) is None
+
+
+def test_water_shaped_workload():
+    """The Sec. VI water-cluster stand-in: 24 basis functions and 5 occupied
+    orbitals per molecule, the gap opened to 2 % of the unshifted spectral
+    width, one potential shift per atom (8 basis functions)."""
+    import numpy as np
+
+    import workloads as W
+    wl = W.water_shaped(6, cache=False)
+    assert (wl.n, wl.nocc) == (144, 30)
+    h = wl.H.astype(np.float64)
+    assert np.array_equal(wl.H, wl.H.T)
+    w = np.linalg.eigvalsh(h)
+    gap = w[wl.nocc] - w[wl.nocc - 1]
+    # the shift moves only the virtual eigenvalues up by delta, so the width
+    # before it is width - delta = width - (gap - gap_before) >= width - gap
+    assert gap >= 0.02 * (w[-1] - w[0] - gap) - 1e-6
+    d = np.diag(wl.H1[0])
+    assert np.count_nonzero(wl.H1[0] - np.diag(d)) == 0
+    blocks = d.reshape(-1, 8)
+    assert (blocks == blocks[:, :1]).all() and len(np.unique(blocks[:, 0])) == 18
+    assert np.abs(d).max() <= 1.0
+    assert np.array_equal(np.diag(wl.A[0]), np.arange(144, dtype=np.float32) - 71.5)
