@@ -11,7 +11,7 @@ A = centred site-position operator, 8 Frobenius-normalised random H1
 (synthetic stand-in for the paper's water-cluster Fockians, which are not
 available).  Inputs are resident in HBM before the timed region.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -226,8 +226,7 @@ def measured_traffic(prec, n):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -54,7 +54,7 @@ typedef enum dmpt_status {
   DMPT_ERR_BOUNDS = 4,         /* [emin, emax] did not enclose the spectrum: the recursion left [0,1] */
   DMPT_ERR_DEVICE = 5,         /* a HIP runtime call failed */
   DMPT_ERR_WORKSPACE = 6,      /* workspace missing or smaller than required */
-  DMPT_ERR_UNSUPPORTED = 7     /* valid request this build does not implement */
+  DMPT_ERR_UNSUPPORTED = 7     /* valid request this library does not implement */
 } dmpt_status;
 
 /* Arithmetic of the dense products on the matrix cores (Sec. VI.B).
@@ -289,7 +289,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
  *   LEARNED   v <- v + mix r + (||r|| / sqrt(n)) net(sqrt(n) r / ||r||), net
  *             the BF16 site-local network of dmpt_mixer_*; a step whose
  *             residual does not decrease is rejected and replaced by the
- *             linear step (linear mixing is the fallback and the judge).
+ *             linear step (linear mixing is the fallback and the reference).
  * Inputs: H0, A device n x n; U device n floats; chi device n x n (written).
  * opts: as for dmpt_susceptibility (sweep, spin, workspace are taken from it;
  * the sweep is forced to ADJOINT); workspace >= dmpt_scf_workspace_bytes.
@@ -302,7 +302,7 @@ typedef enum dmpt_mixer {
   DMPT_MIX_LEARNED = 2,
   DMPT_MIX_LEARNED_ANDERSON = 3   /* Anderson extrapolation with the network as its preconditioner:
                                      vb = v - sum_j gamma_j dV_j, rb = r - sum_j gamma_j dR_j, then the
-                                     LEARNED step from (vb, rb); judged like LEARNED */
+                                     LEARNED step from (vb, rb); rejected like LEARNED */
 } dmpt_mixer;
 
 #define DMPT_MAX_SCF 1024

@@ -1690,7 +1690,7 @@ dmpt_status dmpt_scf_response(const float* H0, const float* U, const float* A, f
     st = norms(rt, ft, &rn2, &fn2);
     if (st != DMPT_OK) return st;
     if (special && rn2 > rn && evals < scf->max_iter) {
-      // the judge: fall back to the linear step from the current state
+      // rejected: fall back to the linear step from the current state
       ++rejected;
       DMPT_HIP(scf_step(vt, v, r, scf->mix, nullptr, 0.0, n, s));
       st = evaluate(vt, ft, cw[cur ^ 1]);

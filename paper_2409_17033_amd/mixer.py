@@ -129,21 +129,21 @@ def training_pairs(H0, U, observables, nocc: int, *, mix: float = 0.3, tol: floa
     return out + (vstars,) if return_fixed_points else out
 
 
-def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int = 256, rounds: int = 2,
+def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int = 256, passes: int = 2,
                 steps: int = 6000, batch: int = 64, lr: float = 1e-3, mix: float = 0.3, tol: float = 1e-6,
                 max_iter: int = 400, collect_iter: int = 100, min_residual: float = 1e-5, seed: int = 11, **kw):
     """Train a mixer for the loop of (H0, U) on the method's own pairs.
 
-    Round 0 trains on the states of linear-mixing runs (training_pairs).  A
+    Pass 0 trains on the states of linear-mixing runs (training_pairs).  A
     network trained only there meets, once it is used, residuals that its own
     earlier steps left behind, which linear mixing never produces; so each
-    further round runs the learned loop on the training observables, labels
+    further pass runs the learned loop on the training observables, labels
     every state it visits with the exact correction toward that observable's
     fixed point v* (from the linear run), adds those pairs to the set and
     trains a fresh network on the union (data aggregation; Ross, Gordon &
     Bagnell, 2011).  Every network is scored by its mean number of loop
     evaluations over the training observables and the best one is returned,
-    with a report {rounds: [(pairs, loss, mean evaluations)], chosen: index}.
+    with a report {passes: [(pairs, loss, mean evaluations)], chosen: index}.
     The learned runs stop after collect_iter evaluations (a poor early network
     would otherwise spend max_iter on each observable).
     """
@@ -151,9 +151,9 @@ def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int 
     x, t, vstars = training_pairs(H0, U, observables, nocc, mix=mix, tol=tol, max_iter=max_iter,
                                   min_residual=min_residual, return_fixed_points=True, **kw)
     gen = torch.Generator().manual_seed(seed)
-    report, best = {"rounds": []}, None
+    report, best = {"passes": []}, None
     E = H0.diagonal().contiguous().float()      # on-site energies (a network input)
-    for rnd in range(rounds + 1):
+    for rnd in range(passes + 1):
         net = Mixer(U, E, window=window, hidden=hidden, seed=seed + rnd)
         hist = net.train(x, t, steps=steps, batch=batch, lr=lr)
         loss = sum(hist[-100:]) / len(hist[-100:])
@@ -162,15 +162,15 @@ def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int 
             _, sinfo, _, v, r = scf_response(H0, U, a, nocc, mixer="learned", net=net, mix=mix, tol=tol,
                                              max_iter=collect_iter, record=True, raise_on_error=False, **kw)
             evals.append(sinfo["iters"])
-            if rnd < rounds:
+            if rnd < passes:
                 xn, tn = _pairs(v, r, sinfo["residual"], vstar, mix, min_residual, drop_last=False)
                 xs.append(xn)
                 ts.append(tn)
         score = sum(evals) / len(evals)
-        report["rounds"].append((int(x.shape[0]), loss, score))
+        report["passes"].append((int(x.shape[0]), loss, score))
         if best is None or score < best[1]:
             best = (net, score, rnd)
-        if rnd < rounds:
+        if rnd < passes:
             x, t = torch.cat(xs), torch.cat(ts)
             perm = torch.randperm(x.shape[0], generator=gen).to(x.device)
             x, t = x[perm].contiguous(), t[perm].contiguous()

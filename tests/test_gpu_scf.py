@@ -152,7 +152,7 @@ def test_scf_duality_config4(gpu, c4):
 @pytest.mark.timeout(600)
 def test_learned_mixer_gain_config4(gpu, c4):
     """Train the mixer on the method's own pairs from 72 training observables
-    (linear-mixing states, then two rounds of states the learned loop visits;
+    (linear-mixing states, then two passes of states the learned loop visits;
     over 2000 pairs), then solve for held-out observables (A and 8 more) with
     linear, Anderson and learned mixing to residual 1e-6: the learned loop
     must reach the same chi as linear mixing in fewer evaluations."""
@@ -163,8 +163,8 @@ def test_learned_mixer_gain_config4(gpu, c4):
     wl, u, train = c4
     H, U = torch.from_numpy(wl.H).to(gpu), torch.from_numpy(u).to(gpu)
     obs = [torch.from_numpy(a).to(gpu) for a in train]
-    net, report = train_mixer(H, U, obs[:72], wl.nocc, window=32, hidden=256, rounds=2)
-    print(f"\ntraining rounds (pairs, loss, mean evaluations): {report['rounds']}, chosen {report['chosen']}")
+    net, report = train_mixer(H, U, obs[:72], wl.nocc, window=32, hidden=256, passes=2)
+    print(f"\ntraining passes (pairs, loss, mean evaluations): {report['passes']}, chosen {report['chosen']}")
     held = [torch.from_numpy(wl.A[0]).to(gpu)] + obs[72:80]
     ev = {"linear": [], "anderson": [], "learned": [], "learned_anderson": []}
     for j, a in enumerate(held):
@@ -177,7 +177,7 @@ def test_learned_mixer_gain_config4(gpu, c4):
         for k in ("anderson", "learned", "learned_anderson"):
             assert cf.rel_frobenius(chis[k], chis["linear"]) <= 1e-5
     print("evaluations to 1e-6 on held-out observables: " + "; ".join(f"{k} {v}" for k, v in ev.items()))
-    assert report["rounds"][-1][0] >= 2000
+    assert report["passes"][-1][0] >= 2000
     assert sum(ev["learned"]) < 0.75 * sum(ev["linear"])
     # the network as Anderson's preconditioner beats Anderson itself
     assert sum(ev["learned_anderson"]) < 0.85 * sum(ev["anderson"])
