@@ -281,6 +281,11 @@ def test_controller_error_codes():
     # (128 * 10 * 2^-32 = 3.0e-7), so a single rise at 1.2e-8 is at their floor
     assert d(5.0, 5.0, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10, 5, precision="split_bf16") == 0
     assert d(5.0, 5.0, 1.2e-8, 3.1e-9, 3.5e-9, 1.4e-4, 20, 10, 5, precision="split_fp16") in (1, -1)
+    # one BF16 term keeps 8 bits: 128 * 10 * 2^-16 = 2.0e-2 reaches past 1/64,
+    # so there the 1/64 resolution test is the only bound on a single rise
+    assert d(5.0, 5.0, 1e-2, 1e-3, 5e-3, 1e-1, 20, 10, 5, precision="bf16") == 0
+    assert d(5.0, 5.0, 1e-2, 1e-3, 5e-3, 1e-1, 20, 10, 5, precision="split_bf16") in (1, -1)
+    assert d(5.0, 5.0, 2e-2, 1e-3, 5e-3, 1e-1, 20, 10, 5, precision="bf16") in (1, -1)
     # before min_iter no stop even at the floor
     assert d(5.0, 5.0, 1e-12, 1e-12, 1e-12, 1e-12, 3, 10, 5) in (1, -1)
     # exactly idempotent / idem_tol
