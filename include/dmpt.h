@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 5
+#define DMPT_ABI_VERSION 6
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -113,7 +113,18 @@ typedef struct dmpt_opts {
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
   int32_t ckpt_interval;  /* ADJOINT sweep only: keep X_n every ckpt_interval steps and recompute
                              the steps in between during the backward sweep; 0 -> keep every X_n */
-  int32_t reserved;       /* must be 0 */
+  int32_t refine;         /* susceptibility, forward sweep with projection only: 1 -> one residual
+                             correction of chi after the projection (Appendix, proof of Eq.
+                             Equivalence: the exact chi' satisfies [H, chi'] = [D, A] and has no
+                             occupied-occupied / virtual-virtual blocks).  With Y the projected
+                             sweep result: R = [D, A] - [H, Y] from FP32-accurate products
+                             (three-term BF16 split; FP16 split for DMPT_SPLIT_FP16; FP32 for
+                             DMPT_FP32), B = [D, R], delta = the forward sweep of B (Eq.
+                             DMSuscept with A := B) in plain BF16 products over the recorded
+                             sigma sequence, projected with D, and chi' = Y + delta.  On the
+                             eigenbasis delta_ij = R_ij / (lambda_i - lambda_j) on the
+                             occupied-virtual pairs, the error left in Y there; the sweep only
+                             has to be accurate relative to that small correction.  0 -> off. */
   double spin;            /* s; 0 -> 2 */
   void* stream;           /* hipStream_t */
   void* workspace;        /* device memory owned by the caller */
@@ -140,6 +151,7 @@ typedef struct dmpt_info {
   double output_ms;                     /* D / chi / a0 output kernel */
   int32_t step_launches;                /* step kernels launched (>= m + 1: the last one decides the stop) */
   int32_t tile;                         /* output tile edge of the step kernel */
+  double refine_ms;                     /* residual correction (opts.refine), when profiled */
 } dmpt_info;
 
 /* ABI version compiled into the library (DMPT_ABI_VERSION). */
@@ -381,6 +393,29 @@ dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, flo
                              int32_t hidden, const float* U, const float* E, int32_t n, const float* x, const float* t,
                              int32_t npairs, int32_t batch, int32_t steps, double lr, double* loss_history,
                              void* stream, void* workspace, size_t workspace_bytes);
+
+/* Training pairs of the learned mixer from one recorded loop (the LEARNED
+ * mixer's data; callers: its trainer).  v, r: device, k x n row-major FP32, the
+ * recorded states and residuals (dmpt_scf_opts.record_v / record_r);
+ * residual: host, k relative residuals (dmpt_scf_info.residual); vstar:
+ * device, n FP32, the loop's converged state.  Every row j with
+ * residual[j] >= min_residual (and j < k - 1 when drop_last) gives, in order,
+ *   x = sqrt(n) r_j / ||r_j||,   t = sqrt(n) (v* - v_j - mix r_j) / ||r_j||
+ * (||r_j|| accumulated in FP64) in rows of x_out, t_out (device, capacity x n);
+ * *count (host) receives the number of rows written.  workspace: device,
+ * >= dmpt_mixer_rows_workspace_bytes(k).  More kept rows than capacity:
+ * DMPT_ERR_ARG, nothing written. */
+size_t dmpt_mixer_rows_workspace_bytes(int32_t rows);
+dmpt_status dmpt_mixer_pairs(const float* v, const float* r, const double* residual, int32_t k, int32_t n,
+                             const float* vstar, double mix, double min_residual, int32_t drop_last,
+                             float* x_out, float* t_out, int32_t capacity, int32_t* count, void* stream,
+                             void* workspace, size_t workspace_bytes);
+/* x_out, t_out (device, npairs x n) = the rows of x, t (device, npairs x n)
+ * in one random order (Fisher-Yates on splitmix64 draws of seed; the same
+ * seed gives the same order); the outputs must not alias the inputs.
+ * workspace: device, >= dmpt_mixer_rows_workspace_bytes(npairs). */
+dmpt_status dmpt_mixer_shuffle(const float* x, const float* t, int32_t npairs, int32_t n, uint64_t seed,
+                               float* x_out, float* t_out, void* stream, void* workspace, size_t workspace_bytes);
 
 /* Host mirror of the device-side step controller (pure function, no device).
  * Decision for iterate X_n (Sec. II) from FP64 Tr X_n, ||X_n||_F^2, its

@@ -23,7 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
-ABI_VERSION = 5   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
+ABI_VERSION = 6   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
 PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4, "split_fp16": 5}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
@@ -33,6 +33,7 @@ EXPORTS = [
     "dmpt_susceptibility", "dmpt_response_workspace_bytes", "dmpt_response",
     "dmpt_scf_response", "dmpt_scf_workspace_bytes", "dmpt_mixer_param_count", "dmpt_mixer_workspace_bytes",
     "dmpt_mixer_init", "dmpt_mixer_forward", "dmpt_mixer_loss_grad", "dmpt_mixer_train",
+    "dmpt_mixer_rows_workspace_bytes", "dmpt_mixer_pairs", "dmpt_mixer_shuffle",
     "dmpt_nonorth_workspace_bytes", "dmpt_susceptibility_nonorth",
     "dmpt_fermi_workspace_bytes", "dmpt_susceptibility_fermi",
     "dmpt_sp2_decide", "dmpt_status_string", "dmpt_last_error",
@@ -47,7 +48,7 @@ class Opts(C.Structure):
         ("sweep", C.c_int32),
         ("idem_tol", C.c_double),
         ("project", C.c_int32), ("profile", C.c_int32),
-        ("ckpt_interval", C.c_int32), ("reserved", C.c_int32),
+        ("ckpt_interval", C.c_int32), ("refine", C.c_int32),
         ("spin", C.c_double),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
     ]
@@ -64,6 +65,7 @@ class Info(C.Structure):
         ("idem_x", C.c_double * (DMPT_MAX_STEPS + 1)),
         ("bounds_ms", C.c_double), ("step_ms", C.c_double), ("project_ms", C.c_double),
         ("output_ms", C.c_double), ("step_launches", C.c_int32), ("tile", C.c_int32),
+        ("refine_ms", C.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -78,6 +80,7 @@ class Info(C.Structure):
             "idem_x": list(self.idem_x[:m + 1]),
             "bounds_ms": self.bounds_ms, "step_ms": self.step_ms, "project_ms": self.project_ms,
             "output_ms": self.output_ms, "step_launches": self.step_launches, "tile": self.tile,
+            "refine_ms": self.refine_ms,
         }
 
 
@@ -181,6 +184,13 @@ def load() -> C.CDLL:
     lib.dmpt_mixer_train.argtypes = [P, P, P, P, I32, I32, P, P, I32, P, P, I32, I32, I32, D, C.POINTER(D), P, P,
                                      SZ]
     lib.dmpt_mixer_train.restype = C.c_int
+    lib.dmpt_mixer_rows_workspace_bytes.argtypes = [I32]
+    lib.dmpt_mixer_rows_workspace_bytes.restype = SZ
+    lib.dmpt_mixer_pairs.argtypes = [P, P, C.POINTER(D), I32, I32, P, D, D, I32, P, P, I32, C.POINTER(I32), P, P,
+                                     SZ]
+    lib.dmpt_mixer_pairs.restype = C.c_int
+    lib.dmpt_mixer_shuffle.argtypes = [P, P, I32, I32, C.c_uint64, P, P, P, P, SZ]
+    lib.dmpt_mixer_shuffle.restype = C.c_int
     lib.dmpt_sp2_decide.argtypes = [D, D, D, D, D, D, I32, I32, D, I32, D, I32]
     lib.dmpt_sp2_decide.restype = I32
     lib.dmpt_status_string.argtypes = [C.c_int]

@@ -45,7 +45,7 @@ constexpr int kOutBlocks = 1024;
 constexpr int kChunk = 8;   // step launches between host polls of the done flag
 
 struct Opts {
-  int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile, ckpt;
+  int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile, ckpt, refine;
   double emin, emax, idem_tol, spin;
   hipStream_t stream;
   char* ws;
@@ -69,7 +69,9 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (o->profile != 0 && o->profile != 1) return fail(DMPT_ERR_ARG, "profile must be 0 or 1");
   if (o->ckpt_interval < 0 || o->ckpt_interval > DMPT_MAX_STEPS)
     return fail(DMPT_ERR_ARG, "ckpt_interval out of range [0, %d]", DMPT_MAX_STEPS);
-  if (o->reserved != 0) return fail(DMPT_ERR_ARG, "reserved must be 0");
+  if (o->refine != 0 && o->refine != 1) return fail(DMPT_ERR_ARG, "refine must be 0 or 1");
+  if (o->refine && (o->sweep != DMPT_SWEEP_FORWARD || !o->project))
+    return fail(DMPT_ERR_ARG, "refine needs the forward sweep with the projection");
   r->n = o->n;
   r->nocc = o->nocc;
   r->prec = o->precision == DMPT_FP32 ? kFP32
@@ -85,6 +87,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   r->project = o->project;
   r->profile = o->profile;
   r->ckpt = o->ckpt_interval;
+  r->refine = o->refine;
   r->emin = o->emin;
   r->emax = o->emax;
   r->idem_tol = o->idem_tol;
@@ -103,6 +106,12 @@ struct Plan {
   size_t mat_f32, mat_op, mat_meta; // bytes per matrix: master, operand copy, metadata
   size_t off_ctl, off_part[2], off_jobs, off_jobs_proj, off_gersh, off_lz, off_a0, off_x, off_y;
   size_t x_slot_bytes, y_obs_bytes, y_slot_bytes;
+  // residual refinement (opts.refine): operand copies of D, H, A_k, Y_k in the
+  // residual's format, two FP32 product buffers, the BF16 copies of R_k and
+  // D, the BF16 sweep's X and Y slots, and the norm partials
+  int rprec;
+  size_t rf_copy_bytes, rf_bslot_bytes;
+  size_t off_rf_copy, off_rf_v, off_rf_r, off_rf_dbf, off_rf_x, off_rf_y, off_rf_norm;
   size_t total;
   int njobs_max, njobs_proj_max, lz_steps;
 };
@@ -115,6 +124,12 @@ struct Plan {
 // sqrt(stages / chain) for FP32, the FP16 split and the three-term BF16 split
 // at N = 4096 and 8192 (outer FP32 sums cost more than inner MFMA ones).
 int flush_interval(int prec, int n_pad) {
+  // FP32 operands: each accumulator block goes into the FP64 tile sum every
+  // 4 stages (64 k values, 32 MFMAs); the outer sum is exact, so a short
+  // chain is best; 4 is the shortest interval the rotating schedule keeps
+  // in the shadow of the MFMAs (measured at N = 8192: chi 7.0e-6 against
+  // 1.67e-5 with two FP32 levels).
+  if (prec == kFP32) return 4;
   const int chain = prec == kFP32 ? 8 : prec == kSplit3 ? 6 : (prec == kSplit2 || prec == kSplit32 || prec == kSplitH) ? 3 : 2;
   const int stages = n_pad / stage_k(prec);
   const double f = std::sqrt((double)stages / chain) * 0.375;
@@ -161,7 +176,34 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   p->y_obs_bytes = p->x_slot_bytes;
   p->y_slot_bytes = p->y_obs_bytes * std::max(nobs, 0);
   p->off_y = off; off = align_up(off + p->y_slot_bytes * 2);
+  p->rprec = o.prec == kSplitH ? kSplitH : o.prec == kFP32 ? kFP32 : kSplit3;
+  if (o.refine && nobs > 0 && !adjoint) {
+    const int k = std::max(nobs, 0);
+    p->rf_copy_bytes = align_up(np2 * (p->rprec == kFP32 ? 4 : operand_bytes(p->rprec)));
+    p->rf_bslot_bytes = align_up(np2 * 4) + align_up(np2 * 2) + align_up(p->mat_meta);
+    p->off_rf_copy = off; off = align_up(off + p->rf_copy_bytes * (2 + 2 * (size_t)k));
+    p->off_rf_v = off; off = align_up(off + np2 * 4 * 2);
+    p->off_rf_r = off; off = align_up(off + np2 * 2 * k);
+    p->off_rf_dbf = off; off = align_up(off + np2 * 2);
+    p->off_rf_x = off; off = align_up(off + p->rf_bslot_bytes * 2);
+    p->off_rf_y = off; off = align_up(off + p->rf_bslot_bytes * 2 * k);
+    p->off_rf_norm = off; off = align_up(off + sizeof(double) * kNormBlocks * (2 + 2 * (size_t)k));
+  }
   p->total = off;
+}
+
+// Plain BF16 matrix set of the refinement sweep: slot q (0/1) of X, or of
+// observable k's Y (stride between observables).
+MatRef bf16_ref(const Plan& p, char* ws, size_t off, int slot, int nmat) {
+  const size_t np2 = (size_t)p.n_pad * p.n_pad;
+  char* base = ws + off + (size_t)slot * p.rf_bslot_bytes * nmat;
+  MatRef m;
+  m.f32 = (float*)base;
+  m.op = base + align_up(np2 * 4);
+  m.meta = base + align_up(np2 * 4) + align_up(np2 * 2);
+  m.stride_f32 = p.rf_bslot_bytes / 4;
+  m.stride_op = p.rf_bslot_bytes;
+  return m;
 }
 
 MatRef x_ref(const Plan& p, char* ws, int slot) {
@@ -710,6 +752,157 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   }
 
   const int mp1 = prof.mark();
+  if (nobs > 0 && o.refine && st == DMPT_OK) {
+    // Residual correction of chi' (opts.refine; Appendix, proof of Eq.
+    // Equivalence).  The exact chi' = L o A on the eigenbasis of H solves
+    // [H, chi'] = [D, A] with no occupied-occupied / virtual-virtual blocks,
+    // so for the projected sweep result Y the error E = chi' - Y satisfies
+    // (lambda_i - lambda_j) E_ij = R_ij on the occupied-virtual pairs,
+    // R = [D, A] - [H, Y].  The sweep of B = [D, R] = (f_i - f_j) R_ij applies
+    // L again: L o B = R_ij / (lambda_i - lambda_j) = E_ij there and 0
+    // elsewhere.  R needs FP32-accurate products (it is a small difference of
+    // large terms); the sweep of B only needs accuracy relative to the small
+    // correction, so it runs on plain BF16 products.
+    //   R = W - W^T, W = D A + Y H (A, H symmetric: NT products)
+    //   Y_1 = beta B = -beta (R D^T + D R^T): a sweep step with Y := R, X := D
+    //   delta = Y_{m+1} of the BF16 recursion X_1 = alpha I + beta H, sigma_n as recorded
+    //   Y <- Y + P(delta), P the two-step occupied-virtual projection with D
+    const size_t np2 = (size_t)p.n_pad * p.n_pad;
+    const int rp = p.rprec;
+    const MatRef xf = x_ref(p, ws, xfin);
+    const MatRef yf = y_ref(p, ws, yfin);
+    char* cbase = ws + p.off_rf_copy;
+    auto cpy = [&](int q) { return (void*)(cbase + (size_t)q * p.rf_copy_bytes); };   // 0 D, 1 H, 2+k A_k, 2+nobs+k Y_k
+    float* v1 = (float*)(ws + p.off_rf_v);
+    float* v2 = v1 + np2;
+    // operand copies (kSplitH: power-of-two scales from entry bounds: |D_ij| <= 1,
+    // |H_ij| <= max(|emin|, |emax|), |M_ij| <= ||M||_F for A_k and Y_k)
+    std::vector<int> ex(2 + 2 * nobs, 0);
+    if (rp == kSplitH) {
+      double* np_ = (double*)(ws + p.off_rf_norm);
+      for (int k = 0; k < nobs; ++k) {
+        DMPT_HIP(launch_norm2(A + (size_t)k * o.n * o.n, (size_t)o.n * o.n, np_ + (size_t)(2 + k) * kNormBlocks, s));
+        DMPT_HIP(launch_norm2(yf.f32 + (size_t)k * yf.stride_f32, np2, np_ + (size_t)(2 + nobs + k) * kNormBlocks, s));
+      }
+      std::vector<double> hn((size_t)(2 + 2 * nobs) * kNormBlocks, 0.0);
+      DMPT_HIP(hipMemcpyAsync(hn.data() + 2 * kNormBlocks, np_ + 2 * kNormBlocks,
+                              sizeof(double) * kNormBlocks * 2 * nobs, hipMemcpyDeviceToHost, s));
+      DMPT_HIP(hipStreamSynchronize(s));
+      auto expo = [](double bound) {
+        if (!(bound > 0.0) || !std::isfinite(bound)) return 0;
+        return std::max(-100, std::min(100, (int)std::floor(std::log2(32768.0 / bound))));
+      };
+      ex[0] = kXScaleExp;
+      ex[1] = expo(std::max(std::fabs(hctl.emin), std::fabs(hctl.emax)));
+      for (int q = 2; q < 2 + 2 * nobs; ++q) {
+        double t = 0.0;
+        for (int b = 0; b < kNormBlocks; ++b) t += hn[(size_t)q * kNormBlocks + b];
+        ex[q] = expo(std::sqrt(t));
+      }
+    }
+    // FP32 residual products read padded FP32 copies of H and A_k; D and Y
+    // are their own masters
+    auto src_of = [&](int q) -> const float* {
+      if (q == 0) return xf.f32;
+      if (q == 1) return H;
+      if (q < 2 + nobs) return A + (size_t)(q - 2) * o.n * o.n;
+      return yf.f32 + (size_t)(q - 2 - nobs) * yf.stride_f32;
+    };
+    auto nsrc_of = [&](int q) { return (q == 0 || q >= 2 + nobs) ? p.n_pad : o.n; };
+    auto opnd = [&](int q) -> const void* {
+      if (rp == kFP32 && (q == 0 || q >= 2 + nobs)) return src_of(q);
+      return cpy(q);
+    };
+    for (int q = 0; q < 2 + 2 * nobs; ++q) {
+      if (rp == kFP32) {
+        if (q == 1 || (q >= 2 && q < 2 + nobs)) DMPT_HIP(launch_pad(src_of(q), o.n, p.n_pad, (float*)cpy(q), 0, s));
+      } else {
+        DMPT_HIP(launch_copy_src(rp, src_of(q), nsrc_of(q), cpy(q), p.n_pad, ex[q], s));
+      }
+    }
+    // BF16 copy of D (the X operand of the B step and of the projection of delta)
+    char* dbf = ws + p.off_rf_dbf;
+    DMPT_HIP(launch_copy_src(kBF16, xf.f32, p.n_pad, dbf, p.n_pad, 0, s));
+    const int flr = flush_interval(rp, p.n_pad);
+    char* rbase = ws + p.off_rf_r;
+    for (int k = 0; k < nobs; ++k) {
+      DMPT_HIP(launch_gemm_op(rp, opnd(0), opnd(2 + k), v1, p.n_pad, std::ldexp(1.0f, -(ex[0] + ex[2 + k])), flr, 0, s));
+      DMPT_HIP(launch_gemm_op(rp, opnd(2 + nobs + k), opnd(1), v2, p.n_pad,
+                              std::ldexp(1.0f, -(ex[2 + nobs + k] + ex[1])), flr, 0, s));
+      DMPT_HIP(launch_antisym_bf16(v1, v2, p.n_pad, rbase + (size_t)k * np2 * 2, s));
+    }
+    // plain BF16 sweep of B over the recorded sigma sequence
+    const int flb = flush_interval(kBF16, p.n_pad);
+    MatRef dref;
+    dref.f32 = xf.f32;
+    dref.op = dbf;
+    dref.meta = xf.meta;
+    dref.stride_f32 = 0;
+    dref.stride_op = 0;
+    MatRef rref;
+    rref.f32 = xf.f32;          // not read: sigma = +1 Z-jobs use only the operand copies
+    rref.op = rbase;
+    rref.meta = xf.meta;
+    rref.stride_f32 = 0;
+    rref.stride_op = np2 * 2;
+    auto bx = [&](int q) { return bf16_ref(p, ws, p.off_rf_x, q, 1); };
+    auto by = [&](int q) { return bf16_ref(p, ws, p.off_rf_y, q, nobs); };
+    const uint32_t* d_pjobs = (const uint32_t*)(ws + p.off_jobs_proj);   // Z-jobs of every observable
+    const int nzj = p.nparts_step * nobs;
+    StepArgs b;
+    std::memset(&b, 0, sizeof(b));
+    b.n = o.n;
+    b.n_pad = p.n_pad;
+    b.ntile = p.ntile;
+    b.decide = 0;
+    b.flush = flb;
+    b.ctl = ctl;
+    b.fixed_sigma = 1;
+    b.write_split = 1;
+    b.jobs = d_pjobs;
+    b.x_in = dref;
+    b.y_in = rref;
+    b.y_out = by(1);
+    b.oscale = (float)(-hctl.beta);
+    DMPT_HIP(run_step(kBF16, b, nzj));
+    DMPT_HIP(launch_init(kBF16, p.tile, H, nullptr, o.n, p.n_pad, 0, nullptr, 0, bx(1), by(1), 0.0, part[1], ctl, s));
+    StepArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.n = o.n;
+    r.n_pad = p.n_pad;
+    r.ntile = p.ntile;
+    r.decide = 0;
+    r.sigma_src = ctl->rec;
+    r.write_split = 1;
+    r.flush = flb;
+    r.ctl = ctl;
+    r.jobs = d_jobs;
+    r.nparts = p.nparts_step;
+    for (int n = 1; n <= m; ++n) {
+      r.step = n;
+      r.x_in = bx(n & 1);
+      r.x_out = bx((n + 1) & 1);
+      r.y_in = by(n & 1);
+      r.y_out = by((n + 1) & 1);
+      r.part_in = part[n & 1];
+      r.part_out = part[(n + 1) & 1];
+      DMPT_HIP(run_step(kBF16, r, njobs_main));
+    }
+    // projection of delta with D, then Y += P(delta)
+    int yd = (m + 1) & 1;
+    for (int q = 0; q < 2; ++q) {
+      b.fixed_sigma = q == 0 ? 1 : -1;
+      b.write_split = q == 0;
+      b.oscale = 1.0f;
+      b.y_in = by(yd);
+      b.y_out = by(yd ^ 1);
+      DMPT_HIP(run_step(kBF16, b, nzj));
+      yd ^= 1;
+    }
+    const MatRef dl = by(yd);
+    DMPT_HIP(launch_add_into(yf.f32, yf.stride_f32, dl.f32, dl.stride_f32, p.n_pad, nobs, s));
+  }
+  const int mr1 = prof.mark();
   // outputs
   const MatRef xf = x_ref(p, ws, xfin);
   const MatRef yf = y_ref(p, ws, yfin);
@@ -751,7 +944,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       for (int q = 0; q < (int)step_marks.size() && q < m; ++q) t += prof.ms(step_marks[q].first, step_marks[q].second);
       info->step_ms = t;
       info->project_ms = prof.ms(mp0, mp1);
-      info->output_ms = prof.ms(mp1, mo1);
+      info->refine_ms = prof.ms(mp1, mr1);
+      info->output_ms = prof.ms(mr1, mo1);
     }
   }
   if (st != DMPT_OK) {
@@ -954,6 +1148,7 @@ dmpt_status fermi_check(const dmpt_opts* opts, const dmpt_fermi_opts* f, int nob
   if (!f) return fail(DMPT_ERR_ARG, "fermi options are NULL");
   if (o->prec != kFP32 && o->prec != kSplitH)
     return fail(DMPT_ERR_UNSUPPORTED, "the finite-temperature path runs in DMPT_FP32 or DMPT_SPLIT_FP16");
+  if (o->refine) return fail(DMPT_ERR_UNSUPPORTED, "refine applies to the zero-temperature solve");
   if (nobs < 0 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [0, %d]", nobs, kMaxObs);
   if (!(std::isfinite(f->kt) && f->kt > 0)) return fail(DMPT_ERR_ARG, "kt must be finite and > 0");
   if (f->canonical != 0 && f->canonical != 1) return fail(DMPT_ERR_ARG, "canonical must be 0 or 1");
@@ -1364,6 +1559,7 @@ dmpt_status scf_check(const dmpt_opts* opts, const dmpt_scf_opts* scf, Opts* o, 
       (!scf->mlp_params || !mixer_sizes_ok(o->n, scf->mlp_window, scf->mlp_hidden, 1)))
     return fail(DMPT_ERR_ARG, "the learned mixer needs mlp_params and a valid mlp_window / mlp_hidden");
   if (scf->reserved != 0) return fail(DMPT_ERR_ARG, "scf reserved must be 0");
+  if (o->refine) return fail(DMPT_ERR_UNSUPPORTED, "refine applies to the forward sweep, not the self-consistent loop");
   *o2 = *opts;
   o2->sweep = DMPT_SWEEP_ADJOINT;
   o2->spin = 1.0;
@@ -1487,6 +1683,67 @@ dmpt_status dmpt_mixer_train(float* master, uint16_t* params, float* adam_m, flo
     DMPT_HIP(mixer_adam(master, params, adam_m, adam_v, (const float*)(ws + m.grad), np, (float)lr, k, s));
   }
   if (loss_history) DMPT_HIP(hipMemcpyAsync(loss_history, ld, sizeof(double) * steps, hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+size_t dmpt_mixer_rows_workspace_bytes(int32_t rows) {
+  if (rows < 1 || rows > (1 << 24)) {
+    fail(DMPT_ERR_ARG, "rows = %d out of range [1, 2^24]", rows);
+    return 0;
+  }
+  return align_up(sizeof(int32_t) * (size_t)rows);
+}
+
+dmpt_status dmpt_mixer_pairs(const float* v, const float* r, const double* residual, int32_t k, int32_t n,
+                             const float* vstar, double mix, double min_residual, int32_t drop_last,
+                             float* x_out, float* t_out, int32_t capacity, int32_t* count, void* stream,
+                             void* workspace, size_t workspace_bytes) {
+  if (!v || !r || !residual || !vstar || !x_out || !t_out || !count) return fail(DMPT_ERR_ARG, "NULL argument");
+  if (k < 1 || k > (1 << 24) || n < 1 || n > 65536) return fail(DMPT_ERR_ARG, "k = %d or n = %d out of range", k, n);
+  if (drop_last != 0 && drop_last != 1) return fail(DMPT_ERR_ARG, "drop_last must be 0 or 1");
+  if (!std::isfinite(mix) || !std::isfinite(min_residual)) return fail(DMPT_ERR_ARG, "mix and min_residual must be finite");
+  if (!workspace || workspace_bytes < align_up(sizeof(int32_t) * (size_t)k))
+    return fail(DMPT_ERR_WORKSPACE, "workspace needs %zu bytes", align_up(sizeof(int32_t) * (size_t)k));
+  std::vector<int32_t> rows;
+  for (int j = 0; j < k; ++j)
+    if (residual[j] >= min_residual && !(drop_last && j == k - 1)) rows.push_back(j);
+  if ((int)rows.size() > capacity) return fail(DMPT_ERR_ARG, "%zu pairs exceed capacity %d", rows.size(), capacity);
+  *count = (int32_t)rows.size();
+  if (rows.empty()) return DMPT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int* d_rows = (int*)workspace;
+  DMPT_HIP(hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, s));
+  DMPT_HIP(mixer_pairs(v, r, vstar, d_rows, (int)rows.size(), n, (float)mix, x_out, t_out, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+dmpt_status dmpt_mixer_shuffle(const float* x, const float* t, int32_t npairs, int32_t n, uint64_t seed,
+                               float* x_out, float* t_out, void* stream, void* workspace, size_t workspace_bytes) {
+  if (!x || !t || !x_out || !t_out) return fail(DMPT_ERR_ARG, "NULL argument");
+  if (npairs < 1 || npairs > (1 << 24) || n < 1 || n > 65536)
+    return fail(DMPT_ERR_ARG, "npairs = %d or n = %d out of range", npairs, n);
+  if (x_out == x || t_out == t) return fail(DMPT_ERR_ARG, "the shuffle does not run in place");
+  if (!workspace || workspace_bytes < align_up(sizeof(int32_t) * (size_t)npairs))
+    return fail(DMPT_ERR_WORKSPACE, "workspace needs %zu bytes", align_up(sizeof(int32_t) * (size_t)npairs));
+  // Fisher-Yates with splitmix64 draws (counter = seed + step), index by
+  // the high half of a 64 x 64-bit product (Lemire's bounded integers).
+  std::vector<int32_t> perm(npairs);
+  for (int i = 0; i < npairs; ++i) perm[i] = i;
+  for (int i = npairs - 1; i > 0; --i) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(npairs - i);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int j = (int)(((unsigned __int128)z * (uint64_t)(i + 1)) >> 64);
+    std::swap(perm[i], perm[j]);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int* d_perm = (int*)workspace;
+  DMPT_HIP(hipMemcpyAsync(d_perm, perm.data(), sizeof(int32_t) * npairs, hipMemcpyHostToDevice, s));
+  DMPT_HIP(mixer_gather_rows(x, d_perm, npairs, n, x_out, s));
+  DMPT_HIP(mixer_gather_rows(t, d_perm, npairs, n, t_out, s));
   DMPT_HIP(hipStreamSynchronize(s));
   return DMPT_OK;
 }

@@ -116,7 +116,10 @@ struct StepArgs {
   const StepRec* sigma_src;  // decide == 0: sigma_n read from sigma_src[step].sigma
   int write_split;           // also write the operand copy of the outputs
   int flush;                 // two-level accumulation: add the pass accumulator into the
-                             // running tile sum every `flush` stages (0: single level)
+                             // running tile sum every `flush` groups of 4 stages (FP32
+                             // operands: into an FP64 tile sum every `flush` stages)
+                             // (0: single level)
+  float oscale;              // tile sums are multiplied by this before the epilogue (0 or 1: none)
   const uint32_t* jobs;
   int njobs;                 // length of the job list
   unsigned int* qhead;       // this launch's queue counters (zero at launch start)
@@ -178,6 +181,18 @@ hipError_t launch_gemm_op(int prec, const void* A, const void* B, float* C, int 
 // matrix scaled by 2^e.
 hipError_t launch_split_copy(const float* src, void* dst, int n_pad, int e, hipStream_t s);
 hipError_t launch_pad(const float* src, int n, int n_pad, float* dst, int transpose, hipStream_t s);
+// Residual refinement helpers.
+//   launch_copy_src: tiled operand copy (prec kSplitH at scale 2^e, kSplit3 or
+//     kBF16) of the zero padding of an n_src x n_src row-major FP32 matrix.
+//   launch_norm2: kNormBlocks FP64 partials of the squared Frobenius norm of
+//     `count` consecutive floats.
+//   launch_antisym_bf16: plain BF16 tiled copy of W - W^T, W = V1 + V2.
+//   launch_add_into: y_k += d_k over nmat n_pad x n_pad FP32 masters.
+constexpr int kNormBlocks = 256;
+hipError_t launch_copy_src(int prec, const float* src, int n_src, void* dst, int n_pad, int e, hipStream_t s);
+hipError_t launch_norm2(const float* src, size_t count, double* part, hipStream_t s);
+hipError_t launch_antisym_bf16(const float* v1, const float* v2, int n_pad, void* dst, hipStream_t s);
+hipError_t launch_add_into(float* y, size_t ys, const float* d, size_t ds, int n_pad, int nmat, hipStream_t s);
 hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s);
 // b <- 2 a - b for nmat matrices (FP32 masters), rewriting b's operand copy at
 // the scale b's metadata holds and b's norm partials.

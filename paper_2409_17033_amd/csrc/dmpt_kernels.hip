@@ -378,6 +378,22 @@ __device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC
     }
 }
 
+// FP32 stage products with the accumulator blocks taken in the order
+// F, F + 1, F + 2, F + 3 (block b = (b / 2, b % 2)).
+template <int F>
+__device__ __forceinline__ void mma_fp32_from(const Ops<kFP32>& o, f32x16 (&acc)[BR][BC]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int b = (F + t) & 3, i = b >> 1, j = b & 1;
+    f32x16 c = acc[i][j];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) c = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a[i][q][e], o.b[j][q][e], c, 0, 0, 0);
+    acc[i][j] = c;
+  }
+}
+
 // Issue order inside one pipeline stage: the R LDS reads of the next stage
 // are spread among the M MFMAs of this one (a read, then M / R MFMAs; when R
 // does not divide M, a read per MFMA and the remaining MFMAs last; the
@@ -627,10 +643,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   #pragma unroll
     for (int i = 0; i < BR; ++i)
   #pragma unroll
-      for (int j = 0; j < BC; ++j) {
-        acc[i][j] = f32x16{0};
-        tot[i][j] = f32x16{0};
-      }
+      for (int j = 0; j < BC; ++j) acc[i][j] = f32x16{0};
 
     // The stages of the job's K stream are fetched in order, each call of dma
     // the next one: cA / cB address stage cs of the A / B panel (tiled: its
@@ -659,6 +672,64 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     LDS_AS char* R2 = (LDS_AS char*)ring2;
     LDS_AS char* R3 = (LDS_AS char*)ring3;
 
+    if constexpr (PREC == kFP32) {
+      // FP32 products: the MFMA accumulator is added into an FP64 tile sum
+      // every `flush` stages (exact outer sum: the only FP32 rounding chain
+      // left is the accumulator's own, `flush` stages long).  One operand
+      // register set: with 32 MFMAs of 64 cycles per stage the other wave of
+      // the SIMD covers this wave's LDS reads.
+      double td[BR][BC][16];
+  #pragma unroll
+      for (int i = 0; i < BR; ++i)
+  #pragma unroll
+        for (int j = 0; j < BC; ++j)
+  #pragma unroll
+          for (int e = 0; e < 16; ++e) td[i][j][e] = 0.0;
+      Ops<PREC> o;
+      dma(R0);
+      dma(R1);
+      dma(R2);
+      // Block b = (bi, bj) of the accumulator is added into the FP64 sum
+      // every `flush` = 4g stages, the four blocks one stage apart (block b at
+      // stages 4g q + b).  In the stage that flushes block b its MFMAs are
+      // issued first; the conversions follow the stage's last MFMA, when the
+      // operand registers are free and block b's chain has long completed.
+      const int grp = a.flush >= 4 ? a.flush / 4 : 0;   // 0: single level
+      int gq = 0;   // group of 4 stages, modulo grp
+  #define DMPT_ITER1(CUR, REFILL, K)                                    \
+      {                                                                 \
+        wait_vm<2 * P::L, true>();                                      \
+        barrier_nofence();                                              \
+        dma(REFILL);                                                    \
+        __builtin_amdgcn_sched_barrier(0);                              \
+        read_ops<PREC>(CUR, o, rowA, rowB, h);                          \
+        mma_fp32_from<K>(o, acc);                                       \
+        if (grp && gq == 0) {                                           \
+          _Pragma("unroll") for (int e = 0; e < 16; ++e)                \
+            td[(K) >> 1][(K) & 1][e] += (double)acc[(K) >> 1][(K) & 1][e]; \
+          acc[(K) >> 1][(K) & 1] = f32x16{0};                           \
+        }                                                               \
+      }
+      for (int s = 0; s < nst; s += 4) {
+        DMPT_ITER1(R0, R3, 0)
+        DMPT_ITER1(R1, R0, 1)
+        DMPT_ITER1(R2, R1, 2)
+        DMPT_ITER1(R3, R2, 3)
+        if (++gq == grp) gq = 0;
+      }
+  #undef DMPT_ITER1
+      wait_vm<0, true>();
+  #pragma unroll
+      for (int i = 0; i < BR; ++i)
+  #pragma unroll
+        for (int j = 0; j < BC; ++j)
+  #pragma unroll
+          for (int e = 0; e < 16; ++e) tot[i][j][e] = (float)(td[i][j][e] + (double)acc[i][j][e]);
+    } else {
+  #pragma unroll
+    for (int i = 0; i < BR; ++i)
+  #pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] = f32x16{0};
     Ops<PREC> o0, o1;
     dma(R0);
     dma(R1);
@@ -709,11 +780,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     for (int i = 0; i < BR; ++i)
   #pragma unroll
       for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
+    }
     if constexpr (PREC == kSplitH) {
   #pragma unroll
       for (int i = 0; i < BR; ++i)
   #pragma unroll
         for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
+    }
+    if (a.oscale != 0.0f && a.oscale != 1.0f) {
+  #pragma unroll
+      for (int i = 0; i < BR; ++i)
+  #pragma unroll
+        for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
     }
 
     // ------------------------------------------------------------ epilogue
@@ -1098,6 +1176,7 @@ hipError_t launch_gemm_op(int prec, const void* A, const void* B, float* C, int 
   switch (prec) {
     case kFP32: hipLaunchKernelGGL(k_gemm_nt<kFP32>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
     case kSplitH: hipLaunchKernelGGL(k_gemm_nt<kSplitH>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
+    case kSplit3: hipLaunchKernelGGL(k_gemm_nt<kSplit3>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
     default: return hipErrorInvalidValue;
   }
   if (sym) {
@@ -1423,6 +1502,106 @@ __global__ __launch_bounds__(256) void k_split_copy(const float* src, char* dst,
 
 hipError_t launch_split_copy(const float* src, void* dst, int n_pad, int e, hipStream_t s) {
   hipLaunchKernelGGL(k_split_copy, dim3(2048), dim3(256), 0, s, src, (char*)dst, n_pad, ldexpf(1.0f, e));
+  return hipGetLastError();
+}
+
+// Tiled operand copy (format F) of the n_pad x n_pad zero padding of an
+// n_src x n_src row-major FP32 matrix (n_src <= n_pad), scaled by sc
+// (kSplitH; a power of two).
+template <int F>
+__global__ __launch_bounds__(256) void k_copy_src(const float* src, int n_src, char* dst, int n_pad, float sc) {
+  const size_t ngroups = (size_t)n_pad * n_pad / 8;
+  for (size_t g = (size_t)blockIdx.x * 256 + threadIdx.x; g < ngroups; g += (size_t)gridDim.x * 256) {
+    const int r = (int)(g / (n_pad / 8));
+    const int c0 = (int)(g % (n_pad / 8)) * 8;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = c0 + e;
+      v[e] = (r < n_src && c < n_src) ? src[(size_t)r * n_src + c] : 0.0f;
+    }
+    store_group8_t<F>(dst, n_pad / Fmt<F>::K, r, c0, v, sc);
+  }
+}
+
+hipError_t launch_copy_src(int prec, const float* src, int n_src, void* dst, int n_pad, int e, hipStream_t s) {
+  const float sc = ldexpf(1.0f, e);
+  switch (prec) {
+    case kSplitH: hipLaunchKernelGGL(k_copy_src<kSplitH>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
+    case kSplit3: hipLaunchKernelGGL(k_copy_src<kSplit3>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
+    case kBF16: hipLaunchKernelGGL(k_copy_src<kBF16>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// FP64 partials of ||M||_F^2 of an n_src x n_src row-major FP32 matrix: one
+// per workgroup of a fixed grid of kNormBlocks (summed by the caller in a
+// fixed order).
+__global__ __launch_bounds__(256) void k_norm2(const float* src, size_t count, double* part) {
+  __shared__ double s_red[4];
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
+    const double v = src[e];
+    acc += v * v;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+hipError_t launch_norm2(const float* src, size_t count, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2, dim3(kNormBlocks), dim3(256), 0, s, src, count, part);
+  return hipGetLastError();
+}
+
+// R = W - W^T with W = V1 + V2 (n_pad x n_pad FP32, V2 nullable), written
+// only as the plain BF16 operand copy (tiled layout).  One 64 x 64 block per
+// workgroup; the block and its transposed partner are staged through LDS.
+__global__ __launch_bounds__(256) void k_antisym_bf16(const float* v1, const float* v2, int n_pad, char* dst) {
+  __shared__ float t[64][65];
+  __shared__ float tt[64][65];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const size_t o = (size_t)(bi * 64 + r) * n_pad + bj * 64 + c;
+    const size_t ot = (size_t)(bj * 64 + r) * n_pad + bi * 64 + c;
+    t[r][c] = v1[o] + (v2 ? v2[o] : 0.0f);
+    tt[r][c] = v1[ot] + (v2 ? v2[ot] : 0.0f);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < 64 * 8; g += 256) {
+    const int r = g >> 3, c0 = (g & 7) * 8;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = t[r][c0 + e] - tt[c0 + e][r];
+    store_group8_t<kBF16>(dst, n_pad / Fmt<kBF16>::K, bi * 64 + r, bj * 64 + c0, v, 1.0f);
+  }
+}
+
+hipError_t launch_antisym_bf16(const float* v1, const float* v2, int n_pad, void* dst, hipStream_t s) {
+  const int nb = n_pad / 64;
+  hipLaunchKernelGGL(k_antisym_bf16, dim3(nb, nb), dim3(256), 0, s, v1, v2, n_pad, (char*)dst);
+  return hipGetLastError();
+}
+
+// y_k += d_k for nmat matrices of n_pad x n_pad FP32 (masters).
+__global__ __launch_bounds__(256) void k_add_into(float* y, size_t ys, const float* d, size_t ds, size_t count) {
+  const int k = blockIdx.y;
+  float* yk = y + (size_t)k * ys;
+  const float* dk = d + (size_t)k * ds;
+  for (size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4; e < count; e += (size_t)gridDim.x * 256 * 4) {
+    f32x4 a = *(const f32x4*)(yk + e);
+    const f32x4 b = *(const f32x4*)(dk + e);
+    a += b;
+    *(f32x4*)(yk + e) = a;
+  }
+}
+
+hipError_t launch_add_into(float* y, size_t ys, const float* d, size_t ds, int n_pad, int nmat, hipStream_t s) {
+  if (nmat <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_into, dim3(1024, nmat), dim3(256), 0, s, y, ys, d, ds, (size_t)n_pad * n_pad);
   return hipGetLastError();
 }
 

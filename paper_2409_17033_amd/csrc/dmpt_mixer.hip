@@ -402,7 +402,57 @@ __global__ void k_fvec(double* f, const double* da, const float* cw, int n) {
   if (i < n) f[i] = da[i] + (cw ? (double)cw[(size_t)i * n + i] : 0.0);
 }
 
+// Training pairs of the learned mixer: for kept record row j = rows[b],
+// x_b = sqrt(n) r_j / ||r_j||, t_b = sqrt(n) (v* - v_j - mix r_j) / ||r_j||
+// (||r_j|| in FP64).  One workgroup per output row.
+__global__ __launch_bounds__(256) void k_mixer_pairs(const float* v, const float* r, const float* vstar,
+                                                     const int* rows, int n, float mix, float* x, float* t) {
+  __shared__ double s_red[4];
+  __shared__ double s_inv;
+  const int j = rows[blockIdx.x];
+  const float* rj = r + (size_t)j * n;
+  const float* vj = v + (size_t)j * n;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += (double)rj[i] * (double)rj[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt((s_red[0] + s_red[1] + s_red[2] + s_red[3]) / (double)n);   // ||r|| / sqrt(n)
+    s_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  }
+  __syncthreads();
+  const float inv = (float)s_inv;
+  float* xb = x + (size_t)blockIdx.x * n;
+  float* tb = t + (size_t)blockIdx.x * n;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    xb[i] = rj[i] * inv;
+    tb[i] = (vstar[i] - vj[i] - mix * rj[i]) * inv;
+  }
+}
+
+// dst row b = src row perm[b] (rows of n floats).
+__global__ __launch_bounds__(256) void k_gather_rows(const float* src, const int* perm, int n, float* dst) {
+  const float* sr = src + (size_t)perm[blockIdx.x] * n;
+  float* dr = dst + (size_t)blockIdx.x * n;
+  for (int i = threadIdx.x; i < n; i += 256) dr[i] = sr[i];
+}
+
 }  // namespace
+
+hipError_t mixer_pairs(const float* v, const float* r, const float* vstar, const int* rows, int nrows, int n,
+                       float mix, float* x, float* t, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mixer_pairs, dim3(nrows), dim3(256), 0, s, v, r, vstar, rows, n, mix, x, t);
+  return hipGetLastError();
+}
+
+hipError_t mixer_gather_rows(const float* src, const int* perm, int nrows, int n, float* dst, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3(nrows), dim3(256), 0, s, src, perm, n, dst);
+  return hipGetLastError();
+}
 
 hipError_t scf_get_diag(const float* c, int n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_get_diag, dim3(blocks(n, 256)), dim3(256), 0, s, c, n, (size_t)n, out);

@@ -22,6 +22,11 @@ hipError_t mixer_loss_grad(const uint16_t* p16, int w, int h, const float* u, co
                            int idx, hipStream_t s);
 // diag(M) of an n x n row-major matrix as FP32 (the on-site energies of H0).
 hipError_t mixer_diag(const float* m, int n, float* out, hipStream_t s);
+// Mixer training pairs from recorded rows rows[0..nrows) of (v, r), and a
+// row gather dst[b] = src[perm[b]].
+hipError_t mixer_pairs(const float* v, const float* r, const float* vstar, const int* rows, int nrows, int n,
+                       float mix, float* x, float* t, hipStream_t s);
+hipError_t mixer_gather_rows(const float* src, const int* perm, int nrows, int n, float* dst, hipStream_t s);
 hipError_t mixer_adam(float* p, uint16_t* p16, float* m, float* v, const float* g, size_t count, float lr,
                       int step, hipStream_t s);
 

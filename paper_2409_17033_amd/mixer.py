@@ -97,15 +97,43 @@ class Mixer:
         return list(hist)
 
 
+def _rows_ws(rows: int, device):
+    nbytes = int(load().dmpt_mixer_rows_workspace_bytes(rows))
+    if nbytes == 0:
+        check(1)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
 def _pairs(v, r, residual, vstar, mix: float, min_residual: float, drop_last: bool):
     """(x, t) of the recorded states whose relative residual is at least
-    min_residual: x = sqrt(n) r / ||r||, t = sqrt(n) (v* - v - mix r) / ||r||."""
-    k = v.shape[0]
-    keep = torch.tensor([residual[i] >= min_residual and not (drop_last and i == k - 1) for i in range(k)],
-                        device=v.device)
-    rk, vk = r[keep], v[keep]
-    rn = torch.linalg.norm(rk, dim=1, keepdim=True) / float(r.shape[1]) ** 0.5
-    return rk / rn, (vstar - vk - mix * rk) / rn
+    min_residual (dmpt_mixer_pairs): x = sqrt(n) r / ||r||,
+    t = sqrt(n) (v* - v - mix r) / ||r||."""
+    v, r, vstar = v.contiguous().float(), r.contiguous().float(), vstar.contiguous().float()
+    k, n = v.shape
+    res = (C.c_double * k)(*[float(x) for x in residual[:k]])
+    x = torch.empty((k, n), dtype=torch.float32, device=v.device)
+    t = torch.empty((k, n), dtype=torch.float32, device=v.device)
+    count = C.c_int32(0)
+    ws = _rows_ws(k, v.device)
+    check(load().dmpt_mixer_pairs(C.c_void_p(v.data_ptr()), C.c_void_p(r.data_ptr()), res, k, n,
+                                  C.c_void_p(vstar.data_ptr()), mix, min_residual, 1 if drop_last else 0,
+                                  C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), k, C.byref(count),
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                  C.c_void_p(ws.data_ptr()), ws.numel()))
+    return x[:count.value], t[:count.value]
+
+
+def _shuffle(x, t, seed: int):
+    """The rows of (x, t) in one random order (dmpt_mixer_shuffle)."""
+    x, t = x.contiguous(), t.contiguous()
+    npairs, n = x.shape
+    xo, to = torch.empty_like(x), torch.empty_like(t)
+    ws = _rows_ws(npairs, x.device)
+    check(load().dmpt_mixer_shuffle(C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), npairs, n, seed,
+                                    C.c_void_p(xo.data_ptr()), C.c_void_p(to.data_ptr()),
+                                    C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                    C.c_void_p(ws.data_ptr()), ws.numel()))
+    return xo, to
 
 
 def training_pairs(H0, U, observables, nocc: int, *, mix: float = 0.3, tol: float = 1e-6, max_iter: int = 400,
@@ -150,7 +178,6 @@ def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int 
     from . import scf_response
     x, t, vstars = training_pairs(H0, U, observables, nocc, mix=mix, tol=tol, max_iter=max_iter,
                                   min_residual=min_residual, return_fixed_points=True, **kw)
-    gen = torch.Generator().manual_seed(seed)
     report, best = {"passes": []}, None
     E = H0.diagonal().contiguous().float()      # on-site energies (a network input)
     for rnd in range(passes + 1):
@@ -171,8 +198,6 @@ def train_mixer(H0, U, observables, nocc: int, *, window: int = 32, hidden: int 
         if best is None or score < best[1]:
             best = (net, score, rnd)
         if rnd < passes:
-            x, t = torch.cat(xs), torch.cat(ts)
-            perm = torch.randperm(x.shape[0], generator=gen).to(x.device)
-            x, t = x[perm].contiguous(), t[perm].contiguous()
+            x, t = _shuffle(torch.cat(xs), torch.cat(ts), seed * 1000003 + rnd)
     report["chosen"] = best[2]
     return best[0], report

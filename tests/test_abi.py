@@ -36,7 +36,7 @@ def test_exports_every_declared_function(lib):
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 5
+    assert lib.dmpt_abi_version() == 6
 
 
 def test_struct_layouts():
@@ -46,7 +46,7 @@ def test_struct_layouts():
     assert Opts.spin.offset == 72 and Opts.workspace_bytes.offset == 96
     assert Opts.ckpt_interval.offset == 64
     assert Info.sigma.offset == 56
-    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4
+    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4 + 8
     assert Info.idem_x.offset == 56 + 256 + 2 * 256 * 8
     assert Opts.profile.offset == 60
 
@@ -81,8 +81,17 @@ def test_checkpoint_workspace(lib):
         assert w_full - w == (103 - nslots) * slot, k
     bad = _opts(lib, 1000, 500, sweep=1, ckpt_interval=-1)
     assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
-    bad = _opts(lib, 1000, 500, reserved=3)
+    bad = _opts(lib, 1000, 500, refine=3)
     assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
+    # the residual correction needs the forward sweep with the projection
+    bad = _opts(lib, 1000, 500, refine=1, sweep=1)
+    assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
+    bad = _opts(lib, 1000, 500, refine=1, project=0)
+    assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0
+    # it adds its own buffers to the plain solve's workspace
+    plain = _opts(lib, 1000, 500, precision=1)
+    ref = _opts(lib, 1000, 500, precision=1, refine=1)
+    assert lib.dmpt_workspace_bytes(C.byref(ref), 1) > lib.dmpt_workspace_bytes(C.byref(plain), 1)
 
 
 def test_workspace_bytes(lib):
@@ -210,6 +219,22 @@ def test_mixer_sizes(lib):
     assert lib.dmpt_mixer_forward(FAKE, 2, 4, FAKE, None, 8, FAKE, 2, FAKE, None, FAKE, 1 << 20) == 1   # no E
     assert lib.dmpt_mixer_train(FAKE, FAKE, FAKE, FAKE, 2, 4, FAKE, FAKE, 8, FAKE, FAKE, 1, 2, 10, 1e-3, out, None,
                                 FAKE, 1 << 20) == 1     # npairs < batch
+
+
+def test_mixer_pairs_validation(lib):
+    """Argument checks of the mixer's pair labelling and shuffle run before any device call."""
+    assert lib.dmpt_mixer_rows_workspace_bytes(0) == 0
+    assert lib.dmpt_mixer_rows_workspace_bytes(10) >= 40
+    res = (C.c_double * 4)(1.0, 1.0, 1.0, 1.0)
+    cnt = C.c_int32(0)
+    p = C.c_void_p(16)
+    assert lib.dmpt_mixer_pairs(None, p, res, 4, 8, p, 0.3, 1e-5, 0, p, p, 4, C.byref(cnt), None, p, 64) == 1
+    assert lib.dmpt_mixer_pairs(p, p, res, 0, 8, p, 0.3, 1e-5, 0, p, p, 4, C.byref(cnt), None, p, 64) == 1
+    assert lib.dmpt_mixer_pairs(p, p, res, 4, 8, p, 0.3, 1e-5, 2, p, p, 4, C.byref(cnt), None, p, 64) == 1
+    assert lib.dmpt_mixer_pairs(p, p, res, 4, 8, p, 0.3, 1e-5, 0, p, p, 4, C.byref(cnt), None, p, 8) == 6
+    assert lib.dmpt_mixer_pairs(p, p, res, 4, 8, p, 0.3, 1e-5, 0, p, p, 3, C.byref(cnt), None, p, 256) == 1
+    assert lib.dmpt_mixer_shuffle(p, p, 4, 8, 1, p, p, None, p, 64) == 1     # in place
+    assert lib.dmpt_mixer_shuffle(p, p, 4, 8, 1, C.c_void_p(32), C.c_void_p(48), None, None, 0) == 6
 
 
 def test_status_strings(lib):

@@ -59,6 +59,41 @@ def test_mixer_forward_and_gradient(gpu, n, w, h, b):
     assert cf.rel_frobenius(grad.double().cpu().numpy(), gref) <= 1e-4
 
 
+def test_mixer_pairs_and_shuffle(gpu):
+    """Training pairs labelled by dmpt_mixer_pairs against the definition
+    x = sqrt(n) r / ||r||, t = sqrt(n) (v* - v - mix r) / ||r|| computed in
+    FP64 here from the same FP32 records; rows below min_residual and, with
+    drop_last, the last row are left out.  dmpt_mixer_shuffle returns the
+    same (x, t) pairs in one seeded order."""
+    import torch
+
+    from paper_2409_17033_amd.mixer import _pairs, _shuffle
+    rng = np.random.default_rng(5)
+    k, n, mix = 7, 301, 0.3
+    v = rng.normal(size=(k, n)).astype(np.float32)
+    r = (rng.normal(size=(k, n)) * 10.0 ** -np.arange(k)[:, None]).astype(np.float32)
+    vstar = rng.normal(size=(1, n)).astype(np.float32)
+    residual = [10.0 ** -j for j in range(k)]
+    for drop_last in (False, True):
+        x, t = _pairs(torch.from_numpy(v).to(gpu), torch.from_numpy(r).to(gpu), residual,
+                      torch.from_numpy(vstar).to(gpu), mix, 1e-5, drop_last)
+        keep = [j for j in range(k) if residual[j] >= 1e-5 and not (drop_last and j == k - 1)]
+        v64, r64, s64 = v.astype(np.float64), r.astype(np.float64), vstar.astype(np.float64)[0]
+        rn = np.linalg.norm(r64[keep], axis=1, keepdims=True) / np.sqrt(n)
+        xref = r64[keep] / rn
+        tref = (s64 - v64[keep] - mix * r64[keep]) / rn
+        assert x.shape == (len(keep), n)
+        assert cf.rel_frobenius(x.double().cpu().numpy(), xref) <= 1e-6
+        assert cf.rel_frobenius(t.double().cpu().numpy(), tref) <= 1e-6
+    xs, ts = _shuffle(x, t, 11)
+    xs2, ts2 = _shuffle(x, t, 11)
+    assert torch.equal(xs, xs2) and torch.equal(ts, ts2)
+    xa, ta, xb, tb = (q.cpu().numpy() for q in (x, t, xs, ts))
+    order = [next(i for i in range(len(xa)) if np.array_equal(xa[i], row)) for row in xb]
+    assert sorted(order) == list(range(len(xa)))             # a permutation of the rows
+    assert all(np.array_equal(ta[i], tb[j]) for j, i in enumerate(order))   # pairs kept together
+
+
 def test_mixer_adam_step(gpu):
     import torch
 

@@ -11,10 +11,9 @@ of A and s = 1.  The FP64 oracle is the Daleckii-Krein closed form.
 
 Tolerances (relative Frobenius of chi, D and D1; response errors relative to
 ||chi||_F ||H1||_F, which bounds them by Cauchy-Schwarz): 1e-5 for FP32 and
-the scaled FP16 split, 1e-4 for the three-term BF16 split at N = 2400; 2e-5
-for both paths at N = 7224, where the FP32 accumulation floor (which grows
-with N, as at the timed size N = 8192) puts FP32 at about 1.3e-5, above the
-1e-5 it meets at smaller sizes.
+the scaled FP16 split, 1e-4 for the three-term BF16 split at N = 2400; at
+N = 7224 1e-5 for FP32 (its products sum their K-chunks in FP64) and the
+1e-4 of split products for the FP16 split (measured there: 1.0e-5).
 """
 import numpy as np
 import pytest
@@ -83,6 +82,9 @@ def water301():
     return wl, chi, rref, np.linalg.norm(chi) * np.linalg.norm(h1)
 
 
+TOL_WATER = {"fp32": 1e-5, "split_fp16": 1e-4}
+
+
 @pytest.mark.parametrize("prec", ["fp32", "split_fp16"])
 def test_water_shape_largest(gpu, water301, prec):
     """The largest shape of Table 2 (301 molecules, N = 7224, padded to 7424)
@@ -107,6 +109,8 @@ def test_water_shape_largest(gpu, water301, prec):
     print(f"\nwater N=7224 {prec}: M={info['m']} (D1 route M={info1['m']}) errchi={ec:.2e} "
           f"Tr[chi H1]={r_chi:.6f} ({abs(r_chi - rref) / abs(rref):.1e} of the value) "
           f"2Tr[A D1]={r_d1:.6f} ({abs(r_d1 - rref) / abs(rref):.1e})")
-    tol = 2e-5
+    # spec targets: 1e-5 for the FP32 path, 1e-4 for split products
+    # (the FP16 split measures 1.0e-5 here)
+    tol = TOL_WATER[prec]
     assert ec <= tol
     assert abs(r_chi - rref) <= tol * scale and abs(r_d1 - rref) <= tol * scale
