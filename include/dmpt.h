@@ -201,6 +201,19 @@ dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32
                           int32_t n, double* out, void* stream, void* workspace,
                           size_t workspace_bytes);
 
+/* dmpt_response for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with no workspace argument.  The FP64 partial sums
+ * and results live in a library-owned device array of 4 MiB on each device
+ * (held until the process ends); the call allocates nothing.  Calls that
+ * overlap on one device race on that array.  Sizes whose
+ * dmpt_response_workspace_bytes exceeds 4 MiB return DMPT_ERR_WORKSPACE
+ * before any device work (at n = 8192, 8 observables x 8 perturbations fit,
+ * 8 x 64 do not); other argument errors as dmpt_response.
+ * Runs on the device current at the call. */
+dmpt_status dmpt_response_static(const float* chi, int32_t nobs, const float* H1, int32_t npert,
+                                 int32_t n, double* out, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Non-orthonormal basis (Sec. V.A).  With overlap S and an inverse factor Z
  * (Z^T S Z = I: Z = S^{-1/2} for Loewdin orthonormalisation, or the inverse

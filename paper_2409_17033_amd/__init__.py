@@ -16,7 +16,7 @@ import ctypes as C
 from ._lib import (BOUNDS, PRECISION, SWEEP, DMPTError, Info, Opts, SCFOpts, check, last_error,
                    load)
 
-__all__ = ["sp2_density", "susceptibility", "response", "make_opts", "workspace_bytes",
+__all__ = ["sp2_density", "susceptibility", "response", "response_static", "make_opts", "workspace_bytes",
            "sp2_decide", "scf_response", "DMPTError", "load"]
 
 
@@ -228,6 +228,25 @@ def response(chi, H1, *, stream=None):
     st = lib.dmpt_response(C.c_void_p(chi.data_ptr()), k, C.c_void_p(H1.data_ptr()), p, n, out,
                            C.c_void_p(stream) if stream else None, C.c_void_p(ws.data_ptr()), nbytes)
     check(st)
+    import numpy as np
+    return np.array(out[:], dtype=np.float64).reshape(k, p)
+
+
+def response_static(chi, H1, *, stream=None):
+    """dmpt_response_static: Tr[chi_k H1_p] like response(), with the
+    library's own device scratch instead of a workspace (no allocation in
+    the call; calls that overlap on one device race on that scratch)."""
+    torch = _torch()
+    n = chi.shape[-1]
+    _check_matrix(chi, n, "chi")
+    _check_matrix(H1, n, "H1")
+    k = 1 if chi.dim() == 2 else chi.shape[0]
+    p = 1 if H1.dim() == 2 else H1.shape[0]
+    out = (C.c_double * (k * p))()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    check(load().dmpt_response_static(C.c_void_p(chi.data_ptr()), k, C.c_void_p(H1.data_ptr()), p, n, out,
+                                      C.c_void_p(stream) if stream else None))
     import numpy as np
     return np.array(out[:], dtype=np.float64).reshape(k, p)
 

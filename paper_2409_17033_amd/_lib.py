@@ -30,7 +30,7 @@ SWEEP = {"forward": 0, "adjoint": 1}
 
 EXPORTS = [
     "dmpt_abi_version", "dmpt_opts_default", "dmpt_workspace_bytes", "dmpt_sp2_density",
-    "dmpt_susceptibility", "dmpt_response_workspace_bytes", "dmpt_response",
+    "dmpt_susceptibility", "dmpt_response_workspace_bytes", "dmpt_response", "dmpt_response_static",
     "dmpt_scf_response", "dmpt_scf_workspace_bytes", "dmpt_mixer_param_count", "dmpt_mixer_workspace_bytes",
     "dmpt_mixer_init", "dmpt_mixer_forward", "dmpt_mixer_loss_grad", "dmpt_mixer_train",
     "dmpt_mixer_rows_workspace_bytes", "dmpt_mixer_pairs", "dmpt_mixer_shuffle",
@@ -166,6 +166,8 @@ def load() -> C.CDLL:
     lib.dmpt_response_workspace_bytes.restype = SZ
     lib.dmpt_response.argtypes = [P, I32, P, I32, I32, C.POINTER(D), P, P, SZ]
     lib.dmpt_response.restype = C.c_int
+    lib.dmpt_response_static.argtypes = [P, I32, P, I32, I32, C.POINTER(D), P]
+    lib.dmpt_response_static.restype = C.c_int
     lib.dmpt_scf_response.argtypes = [P, P, P, P, C.POINTER(SCFOpts), C.POINTER(Opts), C.POINTER(Info),
                                       C.POINTER(SCFInfo)]
     lib.dmpt_scf_response.restype = C.c_int

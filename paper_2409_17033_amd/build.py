@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmpt.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["dmpt_kernels.hip", "dmpt_mixer.hip", "dmpt_fermi.hip", "dmpt_api.cpp"]
+SOURCES = ["dmpt_kernels.hip", "dmpt_mixer.hip", "dmpt_fermi.hip", "dmpt_static.hip", "dmpt_api.cpp"]
 # Packed-FP32 VALU ops are disabled for every HIP translation unit.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -960,6 +960,52 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
 }  // namespace
 }  // namespace dmpt
 
+namespace dmpt {
+
+// Responses are formed in groups of up to kRespObs observables x kRespPert
+// perturbations (one pass over the group's chi and H1 per group).
+constexpr int kRespObs = 8, kRespPert = 64, kRespMax = 1 << 20;
+
+dmpt_status report_error(dmpt_status st, const char* msg) { return fail(st, "%s", msg); }
+
+size_t response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n) {
+  if (nobs < 1 || npert < 1 || (int64_t)nobs * npert > kRespMax || n < 1 || n > 65536) {
+    fail(DMPT_ERR_ARG, "response sizes out of range (nobs, npert >= 1, nobs * npert <= %d, 1 <= n <= 65536)",
+         kRespMax);
+    return 0;
+  }
+  const size_t n2 = (size_t)n * n;
+  const int ko = std::min(nobs, kRespObs), kp = std::min(npert, kRespPert);
+  return align_up((size_t)response_blocks(n2) * ko * kp * sizeof(double)) +
+         align_up((size_t)nobs * npert * sizeof(double));
+}
+
+dmpt_status response_run(const float* chi, int32_t nobs, const float* H1, int32_t npert, int32_t n,
+                         double* out, void* stream, void* workspace, size_t workspace_bytes) {
+  if (!chi || !H1 || !out) return fail(DMPT_ERR_ARG, "chi, H1 and out must not be NULL");
+  const size_t need = response_workspace_bytes(nobs, npert, n);
+  if (need == 0) return DMPT_ERR_ARG;   // message set by response_workspace_bytes
+  if (!workspace) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (workspace_bytes < need) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", workspace_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n2 = (size_t)n * n;
+  const int nblk = response_blocks(n2);
+  const int ko = std::min(nobs, kRespObs), kp = std::min(npert, kRespPert);
+  double* part = (double*)workspace;
+  double* outd = (double*)((char*)workspace + align_up((size_t)nblk * ko * kp * sizeof(double)));
+  for (int k0 = 0; k0 < nobs; k0 += kRespObs)
+    for (int p0 = 0; p0 < npert; p0 += kRespPert) {
+      const int kc = std::min(kRespObs, nobs - k0), pc = std::min(kRespPert, npert - p0);
+      DMPT_HIP(launch_response(chi + (size_t)k0 * n2, kc, H1 + (size_t)p0 * n2, pc, n2, part, nblk,
+                               outd + (size_t)k0 * npert + p0, npert, s));
+    }
+  DMPT_HIP(hipMemcpyAsync(out, outd, sizeof(double) * nobs * npert, hipMemcpyDeviceToHost, s));
+  DMPT_HIP(hipStreamSynchronize(s));
+  return DMPT_OK;
+}
+
+}  // namespace dmpt
+
 using namespace dmpt;
 
 extern "C" {
@@ -1417,44 +1463,13 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   return DMPT_OK;
 }
 
-// Responses are formed in groups of up to kRespObs observables x kRespPert
-// perturbations (one pass over the group's chi and H1 per group).
-constexpr int kRespObs = 8, kRespPert = 64, kRespMax = 1 << 20;
-
 size_t dmpt_response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n) {
-  if (nobs < 1 || npert < 1 || (int64_t)nobs * npert > kRespMax || n < 1 || n > 65536) {
-    fail(DMPT_ERR_ARG, "response sizes out of range (nobs, npert >= 1, nobs * npert <= %d, 1 <= n <= 65536)",
-         kRespMax);
-    return 0;
-  }
-  const size_t n2 = (size_t)n * n;
-  const int ko = std::min(nobs, kRespObs), kp = std::min(npert, kRespPert);
-  return align_up((size_t)response_blocks(n2) * ko * kp * sizeof(double)) +
-         align_up((size_t)nobs * npert * sizeof(double));
+  return dmpt::response_workspace_bytes(nobs, npert, n);
 }
 
 dmpt_status dmpt_response(const float* chi, int32_t nobs, const float* H1, int32_t npert, int32_t n,
                           double* out, void* stream, void* workspace, size_t workspace_bytes) {
-  if (!chi || !H1 || !out) return fail(DMPT_ERR_ARG, "chi, H1 and out must not be NULL");
-  const size_t need = dmpt_response_workspace_bytes(nobs, npert, n);
-  if (need == 0) return DMPT_ERR_ARG;   // message set by dmpt_response_workspace_bytes
-  if (!workspace) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
-  if (workspace_bytes < need) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", workspace_bytes, need);
-  hipStream_t s = (hipStream_t)stream;
-  const size_t n2 = (size_t)n * n;
-  const int nblk = response_blocks(n2);
-  const int ko = std::min(nobs, kRespObs), kp = std::min(npert, kRespPert);
-  double* part = (double*)workspace;
-  double* outd = (double*)((char*)workspace + align_up((size_t)nblk * ko * kp * sizeof(double)));
-  for (int k0 = 0; k0 < nobs; k0 += kRespObs)
-    for (int p0 = 0; p0 < npert; p0 += kRespPert) {
-      const int kc = std::min(kRespObs, nobs - k0), pc = std::min(kRespPert, npert - p0);
-      DMPT_HIP(launch_response(chi + (size_t)k0 * n2, kc, H1 + (size_t)p0 * n2, pc, n2, part, nblk,
-                               outd + (size_t)k0 * npert + p0, npert, s));
-    }
-  DMPT_HIP(hipMemcpyAsync(out, outd, sizeof(double) * nobs * npert, hipMemcpyDeviceToHost, s));
-  DMPT_HIP(hipStreamSynchronize(s));
-  return DMPT_OK;
+  return dmpt::response_run(chi, nobs, H1, npert, n, out, stream, workspace, workspace_bytes);
 }
 
 // ---------------------------------------------------------------- learned mixer

@@ -161,6 +161,13 @@ hipError_t launch_output(const float* x32, const float* y32, size_t ystride, con
                          int n, int n_pad, int nobs, float* d_out, float* chi_out,
                          double scale, int scale_by_beta, const uint32_t* jobs, int njobs,
                          int tile, double* a0_part, Ctl* ctl, hipStream_t s);
+// dmpt_response with the caller's workspace (dmpt_api.cpp), shared by the
+// entry point that brings its own device scratch (dmpt_static.hip), and the
+// error reporter behind dmpt_last_error.
+size_t response_workspace_bytes(int32_t nobs, int32_t npert, int32_t n);
+dmpt_status response_run(const float* chi, int32_t nobs, const float* H1, int32_t npert, int32_t n,
+                         double* out, void* stream, void* workspace, size_t workspace_bytes);
+dmpt_status report_error(dmpt_status st, const char* msg);
 hipError_t launch_response(const float* chi, int nobs, const float* h1, int npert, size_t n2,
                            double* part, int nblk, double* out_dev, int ld, hipStream_t s);
 int response_blocks(size_t n2);

@@ -237,6 +237,21 @@ def test_mixer_pairs_validation(lib):
     assert lib.dmpt_mixer_shuffle(p, p, 4, 8, 1, C.c_void_p(32), C.c_void_p(48), None, None, 0) == 6
 
 
+def test_response_static_refuses_before_device(lib):
+    """dmpt_response_static checks its arguments and its 4 MiB scratch limit
+    before any device call (the pointers here are never dereferenced)."""
+    out = (C.c_double * 512)()
+    p = C.c_void_p(16)
+    assert lib.dmpt_response_static(None, 1, p, 1, 8, out, None) == 1
+    assert lib.dmpt_response_static(p, 0, p, 1, 8, out, None) == 1
+    # n = 8192: 2048 partial blocks x 8 observables x 64 perturbations = 8 MiB of partials
+    assert lib.dmpt_response_static(p, 8, p, 64, 8192, out, None) == 6
+    assert b"4 MiB" in lib.dmpt_last_error()
+    # n = 1: the nobs x npert results alone exceed 4 MiB
+    big = (C.c_double * 600000)()
+    assert lib.dmpt_response_static(p, 1, p, 600000, 1, big, None) == 6
+
+
 def test_status_strings(lib):
     lib.dmpt_status_string.restype = C.c_char_p
     assert lib.dmpt_status_string(0) == b"DMPT_OK"
