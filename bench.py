@@ -3,7 +3,13 @@
 One "step" is one pass of the whole hot path for one synthetic problem:
 spectral bounds -> X_1, Y_1 -> SP2 recursion merged with the susceptibility
 sweep (Eq. DMSuscept) with device-side sigma/stop decisions -> occupied-virtual
-projection -> D, chi, a0 -> responses Tr[chi H1] for 8 perturbations (Eq. dual).
+projection -> (with "+refine": the residual correction of chi) -> D, chi, a0
+-> responses Tr[chi H1] for 8 perturbations (Eq. dual).
+
+A path is a product precision, optionally with "+refine".  The headline is
+a BF16 path (the metric is split-BF16 against FP32); every path's D, chi and
+a0 are compared once, outside the timed region, with the FP64 closed form
+(one eigendecomposition on the host), and reported with its time.
 
 Workload: N = 8192, N_occ = 4096, banded tight-binding H (half-bandwidth 64,
 hopping ~ N(0, 0.05^2), onsite ~ U(-1, 1)) with a 0.1 gap opened at N_occ,
@@ -27,6 +33,9 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-χ (ms) + MFMA TFLOP/s at N=8192, split-BF16 vs FP32, at stated error"
 PEAK = {"bf16": 2516.6, "f16": 2516.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X)
 PRODUCTS = {"split3_bf16": 6, "split3x_bf16": 4, "split_bf16": 3, "split_fp16": 3, "fp32": 1, "bf16": 1}   # MFMA products per FP32-equivalent product (split3x: 6 for X^2, 3 for YX + XY)
+# The dominant kernel of each path: the step launch (kSplit3 for split3x's X^2
+# launch, which is the larger of its two launches per step).
+KERNEL = {"split3x_bf16": "k_step<split3_bf16> + k_step<split_bf16> (X^2 / sweep launches of one step)"}
 
 
 def log(msg):
@@ -39,11 +48,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="split_fp16")
-    ap.add_argument("--compare", default="fp32,split3_bf16,split_bf16", help="other precisions timed for context")
+    ap.add_argument("--precision", default="split3x_bf16+refine",
+                    help="headline path: a precision, optionally with +refine (the residual correction)")
+    ap.add_argument("--compare", default="fp32,split3_bf16,split_fp16,split_fp16+refine,split_bf16",
+                    help="other paths timed for context")
     ap.add_argument("--compare-steps", type=int, default=1)
+    ap.add_argument("--no-errors", action="store_true", help="skip the closed-form errors of each path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=5, help="FP64 oracle SP2+chi steps in the CPU sample")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="CPU baseline in full instead of the bounded sample: the whole FP64 recursion and "
+                         "the closed form on all host threads, and one recursion step and the closed form "
+                         "of the same recipe at N/2 on one thread")
+    ap.add_argument("--nobs", type=int, default=1, help="--extra fermi: observables in one batch")
     ap.add_argument("--extra", choices=["fermi", "nonorth", "shapes"], default=None,
                     help="instead of the headline metric, time the finite-temperature path (Sec. V.B: "
                          "gapless banded H, kT = 0.01, one random observable), the non-orthonormal one "
@@ -67,22 +84,24 @@ def run_shapes(args, dm, torch, W, dev):
         H, A, H1 = (torch.from_numpy(x).to(dev) for x in (wl.H, wl.A[0], wl.H1[0]))
         n_pad = -(-wl.n // 256) * 256
         row = {"molecules": mol, "n": wl.n, "nocc": wl.nocc, "n_pad": n_pad, "paths": {}}
-        for prec in dict.fromkeys([args.precision, "fp32"]):
-            ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, prec, args.steps, args.warmup)
+        for path in dict.fromkeys([args.precision, "fp32"]):
+            prec = path.partition("+")[0]
+            ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, path, args.steps, args.warmup)
             info = infos[-1]
             m = info["m"]
             step_avg = info["step_ms"] / max(m, 1)
             executed = 3.0 * float(n_pad) ** 3 * PRODUCTS[prec] / (step_avg * 1e-3) / 1e12
-            d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, precision=prec, spin=1.0, want_density=False)
+            d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, precision=prec, spin=1.0, want_density=False,
+                                                refine=path.endswith("+refine"))
             r_d1 = 2.0 * float(dm.response(d1, A)[0, 0])
-            row["paths"][prec] = {
+            row["paths"][path] = {
                 "ms": round(ms, 3), "m": m, "step_avg_ms": round(step_avg, 4),
                 "mfma_tflops": round(executed, 1), "mfma_tflops_fma1": round(executed / 2, 1),
                 "algorithmic_tflops": round(3.0 * float(wl.n) ** 3 * m / (ms * 1e-3) / 1e12, 1),
                 "tr_chi_h1": float(resp[0, 0]), "s_tr_a_d1": r_d1, "m_d1": info1["m"],
                 "props": property_errors(torch, H, A, D, chi, wl.nocc, 2.0),
             }
-            log(f"N={wl.n} {prec}: {ms:.1f} ms  M={m}  step {step_avg:.3f} ms  MFMA {executed:.1f} TF/s  "
+            log(f"N={wl.n} {path}: {ms:.1f} ms  M={m}  step {step_avg:.3f} ms  MFMA {executed:.1f} TF/s  "
                 f"Tr[chi H1]={resp[0, 0]:.8f}  2Tr[A D1]={r_d1:.8f}")
             del chi, D, d1
             torch.cuda.empty_cache()
@@ -101,10 +120,11 @@ def run_extra(args, dm, torch, W, dev):
     calls after warmup ones, inputs resident); prints one JSON line."""
     t = time.perf_counter()
     if args.extra == "fermi":
-        wl = W.banded_gapless(args.n, half_bandwidth=256, nobs=1)
-        H, A = torch.from_numpy(wl.H).to(dev), torch.from_numpy(wl.A[0]).to(dev)
+        wl = W.banded_gapless(args.n, half_bandwidth=256, nobs=args.nobs)
+        H, A = torch.from_numpy(wl.H).to(dev), torch.from_numpy(wl.A).to(dev)
         call = lambda prec: dm.susceptibility_fermi(H, A, wl.nocc, 0.01, precision=prec)
-        workload = f"gapless banded H (half-bandwidth 256), N={wl.n}, N_occ={wl.nocc}, kT=0.01, one random observable"
+        workload = (f"gapless banded H (half-bandwidth 256), N={wl.n}, N_occ={wl.nocc}, kT=0.01, "
+                    f"{args.nobs} random observable(s) in one batch")
     else:
         wl = W.banded_gapped(args.n, cfg=2)
         H, A = torch.from_numpy(wl.H).to(dev), torch.from_numpy(wl.A[0]).to(dev)
@@ -115,7 +135,10 @@ def run_extra(args, dm, torch, W, dev):
     log(f"{args.extra} workload N={wl.n} generated in {time.perf_counter() - t:.1f} s")
     torch.cuda.synchronize()
     paths = {}
-    for prec in dict.fromkeys([args.precision, "fp32"]):
+    base = args.precision.partition("+")[0]
+    if args.extra == "fermi" and base == "split3x_bf16":
+        base = "split3_bf16"   # the finite-temperature products take one format for all operands
+    for prec in dict.fromkeys([base, "fp32"]):
         for _ in range(args.warmup):
             call(prec)
         torch.cuda.synchronize()
@@ -153,15 +176,17 @@ def property_errors(torch, H, A, D, chi, nocc, spin):
     return out
 
 
-def run_path(dm, torch, H, A, H1, nocc, prec, steps, warmup):
+def run_path(dm, torch, H, A, H1, nocc, path, steps, warmup):
+    prec, _, rf = path.partition("+")
+    kw = dict(precision=prec, profile=True, refine=rf == "refine")
     for _ in range(warmup):
-        chi, D, a0, info = dm.susceptibility(H, A, nocc, precision=prec, profile=True)
+        chi, D, a0, info = dm.susceptibility(H, A, nocc, **kw)
         dm.response(chi, H1)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        chi, D, a0, info = dm.susceptibility(H, A, nocc, precision=prec, profile=True)
+        chi, D, a0, info = dm.susceptibility(H, A, nocc, **kw)
         resp = dm.response(chi, H1)
         infos.append(info)
     torch.cuda.synchronize()
@@ -169,18 +194,57 @@ def run_path(dm, torch, H, A, H1, nocc, prec, steps, warmup):
     return ms, chi, D, a0, resp, infos
 
 
-def cpu_baseline(wl, m_steps, steps):
-    """The FP64 oracle's merged recursion (Eq. DMSuscept) on the host cores for
-    `steps` SP2 steps at the full size, scaled to the GPU's step count M."""
+def closed_form(wl):
+    """FP64 closed form of the workload on the host (test infrastructure, off
+    the timed region): D, chi = s L o A, a0 = s Tr[A D]; also its wall time."""
     import numpy as np
-    from oracle import sp2
+    from oracle import closed_form as cf
+    t = time.perf_counter()
+    h, a = wl.H.astype(np.float64), wl.A[0].astype(np.float64)
+    w, v = cf.eigensystem(h)
+    vo = v[:, :wl.nocc]
+    d = vo @ vo.T
+    chi = 2.0 * (v @ (cf.loewner_step(w, wl.nocc) * (v.T @ a @ v)) @ v.T)
+    a0 = 2.0 * cf.expectation(a, d)
+    return {"d": d, "chi": chi, "a0": a0, "seconds": time.perf_counter() - t}
+
+
+def path_errors(ref, D, chi, a0, resp, wl):
+    """Relative Frobenius errors of D and chi, the response error relative to
+    ||chi_ref||_F (the H1 are Frobenius-normalised: Cauchy-Schwarz) and the
+    a0 error relative to 2 ||A||_F ||D_ref||_F."""
+    import numpy as np
+    from oracle import closed_form as cf
+    c = chi.double().cpu().numpy()
+    rref = cf.response(ref["chi"], wl.H1)
+    a64 = wl.A[0].astype(np.float64)
+    return {"d": cf.rel_frobenius(D.double().cpu().numpy(), ref["d"]),
+            "chi": cf.rel_frobenius(c, ref["chi"]),
+            "response": float(np.max(np.abs(np.asarray(resp)[0] - rref)) / np.linalg.norm(ref["chi"])),
+            "a0": abs(a0[0] - ref["a0"]) / (2.0 * np.linalg.norm(a64) * np.linalg.norm(ref["d"]))}
+
+
+def _threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max((p.get("num_threads", 0) for p in threadpool_info()), default=os.cpu_count())
+        return max((p.get("num_threads", 0) for p in threadpool_info()), default=os.cpu_count())
     except Exception:
-        threads = os.cpu_count()
+        return os.cpu_count()
+
+
+def _oracle_steps(wl, steps):
+    """Seconds per step of the FP64 oracle's merged recursion (Eq. DMSuscept)
+    over `steps` steps (all of them when steps is None: the oracle's own
+    stopping rule), and the steps run."""
+    import numpy as np
+    from oracle import sp2
     h = wl.H.astype(np.float64)
     a = wl.A[0].astype(np.float64)
+    t0 = time.perf_counter()
+    if steps is None:
+        out = sp2.sp2_susceptibility(h, a, wl.nocc)
+        m = out[-1].m if hasattr(out[-1], "m") else len(out[-1].sigmas)
+        return (time.perf_counter() - t0) / max(m, 1), m
     emin, emax = sp2.gershgorin_bounds(h)
     alpha, beta = sp2.sp2_coefficients(emin, emax)
     x = alpha * np.eye(wl.n) + beta * h
@@ -190,15 +254,53 @@ def cpu_baseline(wl, m_steps, steps):
         s = sp2.choose_sigma(np.trace(x), np.sum(x * x), wl.nocc)
         y = sp2.response_update(y, x, s)
         x = sp2.sp2_update(x, s)
-    per_step = (time.perf_counter() - t0) / steps
+    return (time.perf_counter() - t0) / steps, steps
+
+
+def cpu_baseline(wl, m_steps, steps, closed_s):
+    """The FP64 oracle on the host cores: `steps` steps of its merged
+    recursion (Eq. DMSuscept) at the full size, scaled to the GPU's step
+    count M; the closed form's wall time (eigendecomposition + Loewner
+    product) beside it."""
+    per_step, _ = _oracle_steps(wl, steps)
     return {
         "value": per_step * m_steps * 1e3,
         "unit": "ms",
-        "cores": threads,
+        "cores": _threads(),
         "kind": "oracle",
         "sample": f"{steps} FP64 SP2+chi step(s) (Eq. DMSuscept, numpy GEMMs) at N={wl.n}, "
                   f"{per_step:.2f} s/step, scaled to the GPU's M={m_steps} steps",
+        "closed_form_ms": round(closed_s * 1e3, 1) if closed_s else None,
     }
+
+
+def cpu_baseline_full(wl, W, closed_s):
+    """The CPU baseline in full: the oracle's whole FP64 recursion (its own
+    sigma and stopping rules) and the closed form on all host threads; on one
+    thread (threadpoolctl) one recursion step and the closed form of the same
+    recipe at N/2, each with its N^3 scaling to the full size."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import closed_form as cf
+    out = {"cores": _threads()}
+    t0 = time.perf_counter()
+    per_step, m = _oracle_steps(wl, None)
+    out["recursion_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    out["recursion_steps"] = m
+    out["closed_form_ms"] = round(closed_s * 1e3, 1)
+    half = W.banded_gapped(wl.n // 2, cfg=2)
+    with threadpool_limits(limits=1):
+        step1, _ = _oracle_steps(half, 1)
+        t0 = time.perf_counter()
+        h = half.H.astype(np.float64)
+        w, v = cf.eigensystem(h)
+        _ = v @ (cf.loewner_step(w, half.nocc) * (v.T @ half.A[0].astype(np.float64) @ v)) @ v.T
+        cf1 = time.perf_counter() - t0
+    out["one_thread"] = {"n": half.n, "recursion_step_ms": round(step1 * 1e3, 1),
+                         "closed_form_ms": round(cf1 * 1e3, 1),
+                         "recursion_ms_scaled_to_full_n": round(step1 * 8 * m * 1e3, 1),
+                         "closed_form_ms_scaled_to_full_n": round(cf1 * 8 * 1e3, 1)}
+    return out
 
 
 def measured_traffic(prec, n):
@@ -250,35 +352,44 @@ def main():
     H1 = torch.from_numpy(wl.H1).to(dev)
     torch.cuda.synchronize()
 
+    ref = None
+    if not args.no_errors:
+        t = time.perf_counter()
+        ref = closed_form(wl)
+        log(f"closed form (FP64 eigendecomposition on {_threads()} host threads) in {time.perf_counter() - t:.1f} s")
+
     results = {}
-    for prec, steps, warm in [(args.precision, args.steps, args.warmup)] + \
+    for path, steps, warm in [(args.precision, args.steps, args.warmup)] + \
             [(p, args.compare_steps, 1) for p in args.compare.split(",") if p and p != args.precision]:
-        ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, prec, steps, warm)
+        prec = path.partition("+")[0]
+        ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, path, steps, warm)
         info = infos[-1]
         props = property_errors(torch, H, A, D, chi, wl.nocc, 2.0)
         m = info["m"]
-        n3 = float(wl.n) ** 3
-        step_flops = 3.0 * n3 * PRODUCTS[prec]                   # per SP2 step, upper triangle
+        n_pad = -(-wl.n // 256) * 256
+        step_flops = 3.0 * float(n_pad) ** 3 * PRODUCTS[prec]   # executed MFMA flops per SP2 step (triangle tiles)
         step_avg_ms = info["step_ms"] / max(m, 1)
-        results[prec] = {
+        results[path] = {
             "ms": ms, "m": m, "step_ms_total": info["step_ms"], "step_avg_ms": step_avg_ms,
-            "bounds_ms": info["bounds_ms"], "project_ms": info["project_ms"], "output_ms": info["output_ms"],
-            "elapsed_ms": info["elapsed_ms"],
+            "bounds_ms": info["bounds_ms"], "project_ms": info["project_ms"], "refine_ms": info["refine_ms"],
+            "output_ms": info["output_ms"], "elapsed_ms": info["elapsed_ms"],
             "mfma_tflops": step_flops / (step_avg_ms * 1e-3) / 1e12 if step_avg_ms > 0 else None,
-            "algorithmic_tflops": 3.0 * n3 * m / (ms * 1e-3) / 1e12,
-            "a0": a0[0], "response": [float(v) for v in resp[0]], "props": props,
+            "algorithmic_tflops": 3.0 * float(wl.n) ** 3 * m / (ms * 1e-3) / 1e12,
+            "a0": a0[0], "props": props,
+            "errors": path_errors(ref, D, chi, a0, resp, wl) if ref is not None else None,
         }
-        log(f"{prec}: {ms:.1f} ms/step  M={m}  kernel avg {step_avg_ms:.2f} ms/launch  "
-            f"MFMA {results[prec]['mfma_tflops']:.1f} TF/s  props {props}")
+        log(f"{path}: {ms:.1f} ms/step  M={m}  kernel avg {step_avg_ms:.2f} ms/step  "
+            f"MFMA {results[path]['mfma_tflops']:.1f} TF/s  errors {results[path]['errors']}")
         del chi, D
         torch.cuda.empty_cache()
 
-    main_prec = args.precision
-    r = results[main_prec]
+    main_path = args.precision
+    main_prec = main_path.partition("+")[0]
+    r = results[main_path]
     dtype = "fp32" if main_prec == "fp32" else "f16" if main_prec == "split_fp16" else "bf16"
     roof = {
         "bound": "mfma",
-        "kernel": f"k_step<{main_prec}> (one SP2 + chi step)",
+        "kernel": KERNEL.get(main_prec, f"k_step<{main_prec}> (one SP2 + chi step)"),
         "achieved": r["mfma_tflops"],
         "peak": PEAK[dtype],
         "unit": "TFLOP/s",
@@ -288,8 +399,14 @@ def main():
     cpu = None
     if not args.no_cpu:
         t = time.perf_counter()
-        cpu = cpu_baseline(wl, r["m"], args.cpu_steps)
+        closed_s = ref["seconds"] if ref is not None else None
+        if args.cpu_full:
+            cpu = cpu_baseline(wl, r["m"], args.cpu_steps, closed_s)
+            cpu["full"] = cpu_baseline_full(wl, W, closed_s)
+        else:
+            cpu = cpu_baseline(wl, r["m"], args.cpu_steps, closed_s)
         log(f"cpu baseline in {time.perf_counter() - t:.1f} s: {cpu}")
+    fp32 = results.get("fp32")
     line = {
         "metric": METRIC,
         "value": round(r["ms"], 3),
@@ -306,15 +423,16 @@ def main():
         "config": {
             "workload": f"banded gapped tight-binding H, N={wl.n}, N_occ={wl.nocc}, half-bandwidth 64, "
                         "gap 0.1, A = site position, 8 random H1",
-            "n": wl.n, "nocc": wl.nocc, "precision": main_prec,
-            "sweep": "forward merged (Eq. DMSuscept) + occupied-virtual projection",
+            "n": wl.n, "nocc": wl.nocc, "path": main_path,
+            "sweep": "forward merged (Eq. DMSuscept) + occupied-virtual projection"
+                     + (" + residual correction" if main_path.endswith("+refine") else ""),
             "bounds": "lanczos",
         },
         "roofline": roof,
         "cpu_baseline": cpu,
-        "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
-                      if kk not in ("response",)} for k, v in results.items()},
-        "speedup_vs_fp32": (results["fp32"]["ms"] / r["ms"]) if "fp32" in results and main_prec != "fp32" else None,
+        "paths": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in results.items()},
+        "speedup_vs_fp32": (fp32["ms"] / r["ms"]) if fp32 and main_path != "fp32" else None,
     }
     print(json.dumps(line), flush=True)
 

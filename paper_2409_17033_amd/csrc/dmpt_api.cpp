@@ -103,7 +103,8 @@ struct Plan {
   int n, n_pad, nobs, prec, tile, ntile, nb64, nparts_step;
   int xslots;
   int ckpt, nckpt;                 // adjoint checkpoint interval (0: every X_n kept) and slot count
-  size_t mat_f32, mat_op, mat_meta; // bytes per matrix: master, operand copy, metadata
+  size_t mat_f32, mat_op, mat_op2, mat_meta; // bytes per matrix: master, operand copy (and the
+                                             // two-term copy of the three-term-X^2 option), metadata
   size_t off_ctl, off_part[2], off_jobs, off_jobs_proj, off_gersh, off_lz, off_a0, off_x, off_y;
   size_t x_slot_bytes, y_obs_bytes, y_slot_bytes;
   // residual refinement (opts.refine): operand copies of D, H, A_k, Y_k in the
@@ -111,7 +112,7 @@ struct Plan {
   // D, the BF16 sweep's X and Y slots, and the norm partials
   int rprec;
   size_t rf_copy_bytes, rf_bslot_bytes;
-  size_t off_rf_copy, off_rf_v, off_rf_r, off_rf_dbf, off_rf_x, off_rf_y, off_rf_norm;
+  size_t off_rf_copy, off_rf_v, off_rf_r, off_rf_hist, off_rf_x, off_rf_y, off_rf_norm;
   size_t total;
   int njobs_max, njobs_proj_max, lz_steps;
 };
@@ -156,6 +157,7 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   const size_t np2 = (size_t)p->n_pad * p->n_pad;
   p->mat_f32 = np2 * 4;
   p->mat_op = o.prec == kFP32 ? 0 : np2 * operand_bytes(o.prec);
+  p->mat_op2 = np2 * operand2_bytes(o.prec);
   p->mat_meta = meta_bytes(std::max(p->nb64 * p->nb64, p->nparts_step));
   p->lz_steps = o.lanczos_steps;
   const int ut = p->nparts_step;                       // step tiles covering the upper triangle
@@ -171,7 +173,7 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   p->off_gersh = off; off = align_up(off + (size_t)gershgorin_blocks(o.n) * sizeof(double2));
   p->off_lz = off; off = align_up(off + (size_t)(3 * o.n + 2 * (p->lz_steps + 2)) * sizeof(double));
   p->off_a0 = off; off = align_up(off + (size_t)kOutBlocks * std::max(nobs, 1) * sizeof(double));
-  p->x_slot_bytes = align_up(p->mat_f32) + align_up(p->mat_op) + align_up(p->mat_meta);
+  p->x_slot_bytes = align_up(p->mat_f32) + align_up(p->mat_op) + align_up(p->mat_op2) + align_up(p->mat_meta);
   p->off_x = off; off = align_up(off + p->x_slot_bytes * p->xslots);
   p->y_obs_bytes = p->x_slot_bytes;
   p->y_slot_bytes = p->y_obs_bytes * std::max(nobs, 0);
@@ -184,8 +186,9 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
     p->off_rf_copy = off; off = align_up(off + p->rf_copy_bytes * (2 + 2 * (size_t)k));
     p->off_rf_v = off; off = align_up(off + np2 * 4 * 2);
     p->off_rf_r = off; off = align_up(off + np2 * 2 * k);
-    p->off_rf_dbf = off; off = align_up(off + np2 * 2);
-    p->off_rf_x = off; off = align_up(off + p->rf_bslot_bytes * 2);
+    // plain BF16 copies of X_1 .. X_{max_iter + 2} (slot n = X_n), written by the steps
+    p->off_rf_hist = off; off = align_up(off + np2 * 2 * (size_t)(o.max_iter + 3));
+    p->off_rf_x = off; off = align_up(off + p->rf_bslot_bytes);
     p->off_rf_y = off; off = align_up(off + p->rf_bslot_bytes * 2 * k);
     p->off_rf_norm = off; off = align_up(off + sizeof(double) * kNormBlocks * (2 + 2 * (size_t)k));
   }
@@ -211,9 +214,10 @@ MatRef x_ref(const Plan& p, char* ws, int slot) {
   MatRef m;
   m.f32 = (float*)base;
   m.op = p.prec == kFP32 ? (void*)base : (void*)(base + align_up(p.mat_f32));
+  m.op2 = p.mat_op2 ? (void*)(base + align_up(p.mat_f32) + align_up(p.mat_op)) : nullptr;
   m.stride_f32 = 0;
   m.stride_op = 0;
-  m.meta = base + align_up(p.mat_f32) + align_up(p.mat_op);
+  m.meta = base + align_up(p.mat_f32) + align_up(p.mat_op) + align_up(p.mat_op2);
   return m;
 }
 
@@ -224,7 +228,15 @@ MatRef y_ref(const Plan& p, char* ws, int slot) {
   m.op = p.prec == kFP32 ? (void*)base : (void*)(base + align_up(p.mat_f32));
   m.stride_f32 = p.y_obs_bytes / 4;
   m.stride_op = p.y_obs_bytes;
-  m.meta = base + align_up(p.mat_f32) + align_up(p.mat_op);
+  m.meta = base + align_up(p.mat_f32) + align_up(p.mat_op) + align_up(p.mat_op2);
+  return m;
+}
+
+// The X operand of a sweep (Z-job) launch: for the three-term-X^2 option the
+// two-term copy, otherwise the matrix set itself.
+MatRef sweep_x(MatRef m) {
+  if (m.op2) m.op = m.op2;
+  m.op2 = nullptr;
   return m;
 }
 
@@ -529,8 +541,11 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   // control state: Z-jobs first, then P-jobs (which write the partials the
   // next step's controller reads).
   const int xprec = p.prec == kSplit32 ? kSplit3 : p.prec;
-  const int yprec = p.prec;
+  const int yprec = p.prec == kSplit32 ? kSplit2 : p.prec;
   const bool split_launch = xprec != yprec && nobs > 0 && !adjoint;
+  // launches of P-jobs only: for the three-term-X^2 option the mixed kernel,
+  // whose P-jobs also write X's two-term copy (the sweep reads it)
+  const int xlaunch = p.prec == kSplit32 ? kSplit32 : xprec;
 
   // job tables: [Z-jobs][P-jobs] (one combined table when the step is one launch)
   std::vector<uint32_t> jobs;
@@ -612,6 +627,11 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.flush = flush_interval(xprec, p.n_pad);
   a.jobs = d_jobs;
   a.ctl = ctl;
+  const bool refining = nobs > 0 && o.refine && !adjoint;
+  if (refining) {   // every X_{n+1} also as plain BF16 for the correction sweep
+    a.hist = ws + p.off_rf_hist;
+    a.hist_stride = (size_t)p.n_pad * p.n_pad * 2;
+  }
   const int njobs_step = adjoint ? p.nparts_step : njobs_main;
   const uint32_t* step_jobs = adjoint ? d_jobs + 0 : d_jobs;
   // adjoint X-only run uses the P-jobs only (the table holds no Z-jobs then)
@@ -630,15 +650,15 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       a.nparts = n == 1 ? p.nb64 * p.nb64 : p.nparts_step;
       const int ma = prof.mark();
       if (split_launch) {
+        // one mixed launch: Z-jobs on two-term copies, then P-jobs on
+        // three-term ones (which also write X_{n+1}'s two-term copy)
         a.jobs = d_jobs;
-        a.flush = flush_interval(yprec, p.n_pad);
-        DMPT_HIP(run_step(yprec, a, njobs_z));
-        a.jobs = d_jobs + njobs_z;
         a.flush = flush_interval(xprec, p.n_pad);
-        DMPT_HIP(run_step(xprec, a, njobs_main - njobs_z));
+        a.flush_z = flush_interval(yprec, p.n_pad);
+        DMPT_HIP(run_step(kSplit32, a, njobs_main));
       } else {
         a.jobs = step_jobs;
-        DMPT_HIP(run_step(xprec, a, njobs_step));
+        DMPT_HIP(run_step(xlaunch, a, njobs_step));
       }
       step_marks.emplace_back(ma, prof.mark());
       ++launched;
@@ -685,11 +705,11 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
         r.step = n;
         r.x_in = x_ref(p, ws, xslot_bwd(n));
         r.x_out = x_ref(p, ws, xslot_bwd(n + 1));
-        DMPT_HIP(run_step(xprec, r, p.nparts_step));
+        DMPT_HIP(run_step(xlaunch, r, p.nparts_step));
       }
       for (int n = n1; n >= n0; --n) {
         b.step = n;
-        b.x_in = x_ref(p, ws, xslot_bwd(n));
+        b.x_in = sweep_x(x_ref(p, ws, xslot_bwd(n)));
         b.y_in = y_ref(p, ws, ys);
         b.y_out = y_ref(p, ws, ys ^ 1);
         DMPT_HIP(run_step(yprec, b, (int)zjobs.size()));
@@ -704,9 +724,9 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // Occupied-virtual projection: two sweep steps with X frozen at D
     // (sigma = +1 then -1) multiply the eigenbasis blocks of Y by
     // (f_i + f_j)(2 - f_i - f_j): 1 on occupied-virtual pairs, 0 elsewhere.
-    // They run in the precision of the recursion (FP32 for plain BF16), on
-    // the operand copies of D and Y the last step wrote.
-    const int pprec = p.prec == kBF16 ? kFP32 : xprec;
+    // They run in the precision of the sweep products (FP32 for plain BF16),
+    // on the operand copies of D and Y the last step wrote.
+    const int pprec = p.prec == kBF16 ? kFP32 : yprec;
     const std::vector<uint32_t> pjobs = build_jobs(p.n_pad, nobs, false);
     uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
     DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));
@@ -720,19 +740,19 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.jobs = d_pjobs;
     b.ctl = ctl;
     auto view = [&](MatRef m) { return pprec == kFP32 ? as_fp32(m) : m; };
-    b.x_in = view(x_ref(p, ws, xfin));
+    b.x_in = pprec == kFP32 ? as_fp32(x_ref(p, ws, xfin)) : sweep_x(x_ref(p, ws, xfin));
     // The launch after the last step (it ran before the stop was seen, since
     // the stopping test needs its idempotency error) formed Z = D Y + Y D from
     // D = X_{m+1} and Y_{m+1}, the product of the first projection step.
-    // When every product runs in one precision that launch replaces the first
-    // projection step: with sigma = +1 its Y_{m+2} = Z is bit for bit what the
+    // When the projection runs in the precision of the sweep products, that
+    // launch replaces the first projection step: with sigma = +1 its Y_{m+2} = Z is bit for bit what the
     // step would write (same kernel, inputs, tile products and accumulation
     // order); with sigma = -1, Y_{m+2} = 2 Y_{m+1} - Z and one elementwise pass
     // recovers Z = 2 Y_{m+1} - Y_{m+2} (one more FP32 rounding), with its
     // operand copy at the scale the step would use (Y_{m+2}'s own: both come
     // from Y_{m+1}) and fresh norm partials for the second step.
     const int sig_next = hctl.rec[m + 1].sigma;
-    const bool reuse_first = !adjoint && !split_launch && pprec == xprec && hctl.code == kDecideStop &&
+    const bool reuse_first = !adjoint && pprec == yprec && hctl.code == kDecideStop &&
                              (sig_next == 1 || sig_next == -1);
     int q0 = 0;
     if (reuse_first) {
@@ -820,9 +840,6 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
         DMPT_HIP(launch_copy_src(rp, src_of(q), nsrc_of(q), cpy(q), p.n_pad, ex[q], s));
       }
     }
-    // BF16 copy of D (the X operand of the B step and of the projection of delta)
-    char* dbf = ws + p.off_rf_dbf;
-    DMPT_HIP(launch_copy_src(kBF16, xf.f32, p.n_pad, dbf, p.n_pad, 0, s));
     const int flr = flush_interval(rp, p.n_pad);
     char* rbase = ws + p.off_rf_r;
     for (int k = 0; k < nobs; ++k) {
@@ -831,11 +848,14 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
                               std::ldexp(1.0f, -(ex[2 + nobs + k] + ex[1])), flr, 0, s));
       DMPT_HIP(launch_antisym_bf16(v1, v2, p.n_pad, rbase + (size_t)k * np2 * 2, s));
     }
-    // plain BF16 sweep of B over the recorded sigma sequence
+    // plain BF16 copies of the X_n: slot n of the history (X_1 from the
+    // initialisation below, X_2 .. X_{m+1} = D written by the steps)
+    char* hist = ws + p.off_rf_hist;
+    const size_t hstride = np2 * 2;
     const int flb = flush_interval(kBF16, p.n_pad);
     MatRef dref;
     dref.f32 = xf.f32;
-    dref.op = dbf;
+    dref.op = hist + (size_t)(m + 1) * hstride;
     dref.meta = xf.meta;
     dref.stride_f32 = 0;
     dref.stride_op = 0;
@@ -865,28 +885,22 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.y_out = by(1);
     b.oscale = (float)(-hctl.beta);
     DMPT_HIP(run_step(kBF16, b, nzj));
-    DMPT_HIP(launch_init(kBF16, p.tile, H, nullptr, o.n, p.n_pad, 0, nullptr, 0, bx(1), by(1), 0.0, part[1], ctl, s));
-    StepArgs r;
-    std::memset(&r, 0, sizeof(r));
-    r.n = o.n;
-    r.n_pad = p.n_pad;
-    r.ntile = p.ntile;
-    r.decide = 0;
+    // X_1 = alpha I + beta H in plain BF16 (its copy lands in history slot 1)
+    MatRef x1 = bx(0);
+    x1.op = hist + hstride;
+    DMPT_HIP(launch_init(kBF16, p.tile, H, nullptr, o.n, p.n_pad, 0, nullptr, 0, x1, by(1), 0.0, part[1], ctl, s));
+    // the sweep of B: Z-jobs only, X_n from the history, sigma_n as recorded
+    StepArgs r = b;
     r.sigma_src = ctl->rec;
+    r.oscale = 1.0f;
     r.write_split = 1;
-    r.flush = flb;
-    r.ctl = ctl;
-    r.jobs = d_jobs;
-    r.nparts = p.nparts_step;
     for (int n = 1; n <= m; ++n) {
       r.step = n;
-      r.x_in = bx(n & 1);
-      r.x_out = bx((n + 1) & 1);
+      r.x_in = x1;
+      r.x_in.op = hist + (size_t)n * hstride;
       r.y_in = by(n & 1);
       r.y_out = by((n + 1) & 1);
-      r.part_in = part[n & 1];
-      r.part_out = part[(n + 1) & 1];
-      DMPT_HIP(run_step(kBF16, r, njobs_main));
+      DMPT_HIP(run_step(kBF16, r, nzj));
     }
     // projection of delta with D, then Y += P(delta)
     int yd = (m + 1) & 1;
@@ -1158,10 +1172,16 @@ struct FermiWS {
   size_t e, e2, r, t, v, en, y, g, sm, u, w, ce, ce2, cr, ct, cen, cy, cs, cw, part, a0p, total;
 };
 
-FermiWS fermi_ws(size_t base, int n_pad, int nobs, bool split) {
+// Operand copy format of the finite-temperature products: none (FP32
+// masters), the scaled FP16 split, or the two- / three-term BF16 split.
+int fermi_copy_prec(int prec) {
+  return prec == kSplitH ? kSplitH : prec == kSplit3 ? kSplit3 : prec == kSplit2 ? kSplit2 : kFP32;
+}
+
+FermiWS fermi_ws(size_t base, int n_pad, int nobs, int cprec) {
   FermiWS w;
   const size_t m = (size_t)n_pad * n_pad * 4;
-  const size_t mc = split ? m : 0;   // FP16 split copy: 4 bytes per element
+  const size_t mc = cprec == kFP32 ? 0 : (size_t)n_pad * n_pad * operand_bytes(cprec);   // operand copy
   size_t off = align_up(base);
   w.e = off; off = align_up(off + m);
   w.e2 = off; off = align_up(off + m);
@@ -1192,8 +1212,9 @@ dmpt_status fermi_check(const dmpt_opts* opts, const dmpt_fermi_opts* f, int nob
   dmpt_status st = normalise(opts, o);
   if (st != DMPT_OK) return st;
   if (!f) return fail(DMPT_ERR_ARG, "fermi options are NULL");
-  if (o->prec != kFP32 && o->prec != kSplitH)
-    return fail(DMPT_ERR_UNSUPPORTED, "the finite-temperature path runs in DMPT_FP32 or DMPT_SPLIT_FP16");
+  if (o->prec != kFP32 && o->prec != kSplitH && o->prec != kSplit3 && o->prec != kSplit2)
+    return fail(DMPT_ERR_UNSUPPORTED, "the finite-temperature path runs in DMPT_FP32, DMPT_SPLIT_FP16, "
+                                      "DMPT_SPLIT3_BF16 or DMPT_SPLIT_BF16");
   if (o->refine) return fail(DMPT_ERR_UNSUPPORTED, "refine applies to the zero-temperature solve");
   if (nobs < 0 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [0, %d]", nobs, kMaxObs);
   if (!(std::isfinite(f->kt) && f->kt > 0)) return fail(DMPT_ERR_ARG, "kt must be finite and > 0");
@@ -1213,11 +1234,11 @@ size_t dmpt_fermi_workspace_bytes(const dmpt_opts* opts, const dmpt_fermi_opts* 
   Opts o;
   Plan p;
   if (fermi_check(opts, fopts, nobs, &o, &p) != DMPT_OK) return 0;
-  return fermi_ws(p.off_x, p.n_pad, nobs, o.prec == kSplitH).total;
+  return fermi_ws(p.off_x, p.n_pad, nobs, fermi_copy_prec(o.prec)).total;
 }
 
 // An operand of the finite-temperature products: FP32 master, and for the
-// FP16 split its tiled copy at the scale 2^e.
+// split formats its tiled copy (FP16 split: at the scale 2^e; BF16: e = 0).
 struct FMat {
   float* m;
   void* c;
@@ -1239,8 +1260,10 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   if (!H) return fail(DMPT_ERR_ARG, "H is NULL");
   if (nobs > 0 && (!A || !chi)) return fail(DMPT_ERR_ARG, "A and chi must not be NULL");
   const int n = o.n, np = p.n_pad;
-  const bool split = o.prec == kSplitH;
-  const FermiWS w = fermi_ws(p.off_x, np, nobs, split);
+  const int cprec = fermi_copy_prec(o.prec);
+  const bool split = cprec != kFP32;
+  const size_t cbytes = split ? (size_t)operand_bytes(cprec) : 0;
+  const FermiWS w = fermi_ws(p.off_x, np, nobs, cprec);
   if (!o.ws) return fail(DMPT_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", w.total);
   if (o.ws_bytes < w.total) return fail(DMPT_ERR_WORKSPACE, "workspace has %zu bytes, need %zu", o.ws_bytes, w.total);
   if (finfo) std::memset(finfo, 0, sizeof(*finfo));
@@ -1249,7 +1272,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   Ctl* ctl = (Ctl*)(ws + p.off_ctl);
   const size_t np2 = (size_t)np * np;
   auto fm = [&](size_t master, size_t copy, size_t k) {
-    return FMat{(float*)(ws + master) + k * np2, split ? (void*)(ws + copy + k * np2 * 4) : nullptr, 0};
+    return FMat{(float*)(ws + master) + k * np2, split ? (void*)(ws + copy + k * np2 * cbytes) : nullptr, 0};
   };
   FMat E = fm(w.e, w.ce, 0), E2 = fm(w.e2, w.ce2, 0), R = fm(w.r, w.cr, 0), T = fm(w.t, w.ct, 0);
   FMat En = fm(w.en, w.cen, 0), Sm = fm(w.sm, w.cs, 0), Wm = fm(w.w, w.cw, 0);
@@ -1259,7 +1282,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   float* G = (float*)(ws + w.g);
   float* U = (float*)(ws + w.u);
   double* part = (double*)(ws + w.part);
-  const int fl = flush_interval(split ? kSplitH : kFP32, np);
+  const int fl = flush_interval(cprec, np);
   const double beta = 1.0 / fopts->kt;
   ScopedEvents ev;
   DMPT_HIP(hipEventCreate(&ev.e0));
@@ -1292,12 +1315,18 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   // operand copy at a fixed exponent, or at 2^15 / ||M||_F
   auto refresh = [&](FMat& a, int e) -> dmpt_status {
     if (!split) return DMPT_OK;
+    if (cprec != kSplitH) {   // BF16 terms keep the FP32 exponent range: no scale
+      a.e = 0;
+      DMPT_HIP(launch_copy_src(cprec, a.m, np, a.c, np, 0, s));
+      return DMPT_OK;
+    }
     a.e = e;
     DMPT_HIP(launch_split_copy(a.m, a.c, np, e, s));
     return DMPT_OK;
   };
   auto refresh_dyn = [&](FMat& a) -> dmpt_status {
     if (!split) return DMPT_OK;
+    if (cprec != kSplitH) return refresh(a, 0);
     double tr = 0.0, sq = 0.0;
     dmpt_status e = trace_sq(a.m, &tr, &sq);
     if (e != DMPT_OK) return e;
@@ -1311,7 +1340,7 @@ dmpt_status dmpt_susceptibility_fermi(const float* H, const float* A, int32_t no
   auto prod = [&](const FMat& a, const FMat& b, float* out, double alpha, bool sym) -> dmpt_status {
     ++products;
     if (split)
-      DMPT_HIP(launch_gemm_op(kSplitH, a.c, b.c, out, np, (float)std::ldexp(alpha, -(a.e + b.e)), fl, sym ? 1 : 0, s));
+      DMPT_HIP(launch_gemm_op(cprec, a.c, b.c, out, np, (float)std::ldexp(alpha, -(a.e + b.e)), fl, sym ? 1 : 0, s));
     else
       DMPT_HIP(launch_gemm_op(kFP32, a.m, b.m, out, np, (float)alpha, fl, sym ? 1 : 0, s));
     return DMPT_OK;

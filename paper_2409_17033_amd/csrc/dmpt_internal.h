@@ -16,8 +16,8 @@ enum Prec : int {
   kSplit2 = 1,  // packed (hi, lo) BF16 pairs, BF16 MFMA, FP32 accumulate
   kSplit3 = 2,  // packed (hi, mid, lo) BF16 triples, BF16 MFMA, FP32 accumulate
   kBF16 = 3,    // plain BF16 row-major
-  kSplit32 = 4, // (hi, mid, lo) triples stored as for kSplit3; products use (hi, mid) only,
-                // i.e. the two-term split hh + hm + mh (mid = RNE(x - hi) is the two-term lo)
+  kSplit32 = 4, // precision option only (no kernel format): X^2 products in kSplit3, the sweep
+                // products in kSplit2; X_n carries both copies (MatRef::op, MatRef::op2)
   kSplitH = 5,  // packed (hi, lo) FP16 pairs of the operand scaled by 2^s, FP16 MFMA,
                 // FP32 accumulate; s = kXScaleExp for X, per matrix (MatMeta) for Y
 };
@@ -36,6 +36,8 @@ __host__ __device__ constexpr int operand_bytes(int prec) {
   return prec == kFP32 ? 4 : (prec == kSplit2 || prec == kSplitH) ? 4 : (prec == kSplit3 || prec == kSplit32) ? 6
        : prec == kBF16 ? 2 : 0;
 }
+// Bytes per element of the second (two-term) operand copy of the kSplit32 option.
+__host__ __device__ constexpr int operand2_bytes(int prec) { return prec == kSplit32 ? 4 : 0; }
 
 constexpr int kPadTo = 256;     // n is padded (with zeros in X-space) to a multiple of this
 constexpr int kMaxObs = 64;
@@ -103,6 +105,8 @@ struct MatRef {
   size_t stride_f32;   // elements
   size_t stride_op;    // bytes
   char* meta;
+  void* op2 = nullptr; // kSplit3 matrices of the kSplit32 option: their two-term (kSplit2) copy,
+                       // written next to the three-term one (same (hi, lo = RNE(x - hi)) terms)
 };
 
 struct StepArgs {
@@ -119,6 +123,9 @@ struct StepArgs {
                              // running tile sum every `flush` groups of 4 stages (FP32
                              // operands: into an FP64 tile sum every `flush` stages)
                              // (0: single level)
+  int flush_z;               // Z-jobs of a mixed launch (kSplit32): their own interval (0: flush)
+  char* hist;                // P-jobs also write a plain BF16 tiled copy of X_{n+1} at
+  size_t hist_stride;        //   hist + (n + 1) hist_stride bytes (nullptr: no copy)
   float oscale;              // tile sums are multiplied by this before the epilogue (0 or 1: none)
   const uint32_t* jobs;
   int njobs;                 // length of the job list

@@ -56,16 +56,14 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // Bytes per LDS row per pipeline stage: 16 k values of FP32 / packed split-2
 // (BF16 or FP16; 64 B = 4 slots of 16 B), 32 k values of plain BF16 (64 B),
-// 16 k values of packed split-3 (96 B = 6 slots); kSplit32 stages
-// split-2-shaped rows.
+// 16 k values of packed split-3 (96 B = 6 slots).
 template <int PREC> struct Fmt {
   static constexpr int RB = PREC == kSplit3 ? 96 : 64;
   static constexpr int S = RB / 16;
   static constexpr int K = PREC == kBF16 ? 32 : 16;
 };
-// Format of the operand copy in HBM: kSplit32 keeps the three-term copy and
-// stages only its (hi, mid) slots.
-template <int PREC> struct Store { static constexpr int F = PREC == kSplit32 ? kSplit3 : PREC; };
+// Format of the operand copy in HBM (the same as the staged one).
+template <int PREC> struct Store { static constexpr int F = PREC; };
 
 int stage_k(int prec) { return prec == kBF16 ? 32 : 16; }
 
@@ -129,7 +127,7 @@ __device__ __forceinline__ void split_terms_h(float x, float sc, unsigned short 
   p[1] = f16_bits(xs - f16_val(p[0]));
 }
 template <int PREC> struct Terms {
-  static constexpr int T = PREC == kSplit3 ? 3 : (PREC == kSplit2 || PREC == kSplit32 || PREC == kSplitH) ? 2 : 1;
+  static constexpr int T = PREC == kSplit3 ? 3 : (PREC == kSplit2 || PREC == kSplitH) ? 2 : 1;
 };
 // The split terms of one element in the operand format F (sc: kSplitH scale).
 template <int F>
@@ -254,29 +252,6 @@ __device__ __forceinline__ void dma_stage_tiled(LDS_AS char* slot, const char* a
   }
 }
 
-// DMA of one stage for kSplit32: LDS gets split-2-shaped rows (4 slots of
-// 16 B: hi and mid of the two 8-column k-groups, swizzled for 4 slots) gathered
-// from the three-term copy in HBM (6 slots per row, swizzled for 6).  Lane i of
-// instruction j fills LDS bytes j*1024 + 16 i: panel row 16 (j mod 8) + i/4 of
-// region j/8 (A rows 0-127, A rows 128-255, B rows 0-127), physical slot i mod 4.
-template <int PREC>
-__device__ __forceinline__ void dma_stage_t32(LDS_AS char* slot, const char* a0, const char* a1, const char* b,
-                                              int wave, int lane) {
-  using P = Pipe<PREC>;
-  static_assert(P::NI % NW == 0, "kSplit32 stage is a whole number of rounds");
-#pragma unroll
-  for (int jj = 0; jj < P::L; ++jj) {
-    const int j = wave + jj * NW;
-    const int region = j >> 3;
-    const int rr = ((j & 7) << 4) + (lane >> 2);                 // row within the 128-row chunk
-    const int ls4 = (lane & 3) ^ ((rr >> 2) & 3);                // logical split-2 slot at this position
-    const int ls6 = 3 * (ls4 >> 1) + (ls4 & 1);                  // same k-group and term in the 6-slot row
-    const int ph6 = ls6 ^ ((rr >> 3) & 1);
-    const char* src = (region == 0 ? a0 : region == 1 ? a1 : b) + rr * 96 + 16 * ph6;
-    __builtin_amdgcn_global_load_lds((const GLB_AS void*)src, (LDS_AS void*)(slot + j * 1024), 16, 0, 0);
-  }
-}
-
 // Byte offset of element (r, c), split term `part`, in the tiled operand copy.
 template <int PREC>
 __device__ __forceinline__ size_t op_off(int r, int c, int part, int nst) {
@@ -292,7 +267,6 @@ __device__ __forceinline__ size_t op_off(int r, int c, int part, int nst) {
 template <int PREC> struct Ops;
 template <> struct Ops<kSplit3> { bf16x8 a[BR][3], b[BC][3]; };
 template <> struct Ops<kSplit2> { bf16x8 a[BR][2], b[BC][2]; };
-template <> struct Ops<kSplit32> { bf16x8 a[BR][2], b[BC][2]; };
 template <> struct Ops<kSplitH> { f16x8 a[BR][2], b[BC][2]; };
 template <> struct Ops<kBF16> { bf16x8 a[BR][2], b[BC][2]; };     // [t]: k16 step
 template <> struct Ops<kFP32> { f32x4 a[BR][2], b[BC][2]; };       // [q]: slot h + 2q
@@ -307,7 +281,7 @@ __device__ __forceinline__ void read_ops(const LDS_AS char* slot, Ops<PREC>& o, 
   constexpr int S = Pipe<PREC>::S;
   const LDS_AS char* pA = slot;
   const LDS_AS char* pB = slot + Pipe<PREC>::A_BYTES;
-  if constexpr (PREC == kSplit3 || PREC == kSplit2 || PREC == kSplit32 || PREC == kSplitH) {
+  if constexpr (PREC == kSplit3 || PREC == kSplit2 || PREC == kSplitH) {
     constexpr int T = Terms<PREC>::T;
     using E = typename std::remove_reference<decltype(o.a[0][0])>::type;
 #pragma unroll
@@ -356,7 +330,7 @@ __device__ __forceinline__ void mma_ops(const Ops<PREC>& o, f32x16 (&acc)[BR][BC
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
-      } else if constexpr (PREC == kSplit2 || PREC == kSplit32) {
+      } else if constexpr (PREC == kSplit2) {
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][1], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][1], o.b[j][0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][0], o.b[j][0], c, 0, 0, 0);
@@ -403,7 +377,7 @@ __device__ __forceinline__ void mma_fp32_from(const Ops<kFP32>& o, f32x16 (&acc)
 // latency, queued behind every wave's reads, stalls the stage's barrier.
 template <int PREC> struct StageMix {
   static constexpr int R = (BR + BC) * (PREC == kSplit3 ? 3 : 2);   // ds_read_b128 per stage
-  static constexpr int M = BR * BC * (PREC == kSplit3 ? 6 : (PREC == kSplit2 || PREC == kSplit32 || PREC == kSplitH) ? 3 :
+  static constexpr int M = BR * BC * (PREC == kSplit3 ? 6 : (PREC == kSplit2 || PREC == kSplitH) ? 3 :
                                       PREC == kBF16 ? 2 : 8);           // MFMAs per stage
 };
 template <int PREC>
@@ -538,12 +512,445 @@ __device__ __forceinline__ int tile_index(int ti, int tj, int tcols) {
   return ti * tcols - ti * (ti - 1) + (tj - 2 * ti);
 }
 
-template <int PREC>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(StepArgs a) {
+// One job of the step kernel (one output tile of P = X_n^2 or of
+// Z = Y_n X_n + X_n Y_n) in operand format PREC: DMA + MFMA main loop and the
+// fused epilogue.  R0..R3: the LDS ring (each slot also holds two waves'
+// epilogue staging); s_red, s_nrm: workgroup scratch.
+// MIX: a job of the mixed launch of the three-term-X^2 option: its P-jobs
+// (kSplit3) also write the two-term copy of their output, its Z-jobs
+// (kSplit2) read X's two-term copy and take their own flush interval.
+template <int PREC, bool MIX = false>
+__device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, const int sigma, LDS_AS char* R0,
+                                         LDS_AS char* R1, LDS_AS char* R2, LDS_AS char* R3, double* s_red,
+                                         double* s_nrm) {
   using P = Pipe<PREC>;
+  const int kind = job & 1;
+  const int obs = (job >> 1) & 127;
+  const int ti = (job >> 8) & 4095;    // 256-row block
+  const int tj = (job >> 20) & 4095;   // 128-column block
+  constexpr int opb = operand_bytes(PREC);
+  const size_t ldb = (size_t)a.n_pad * opb;
+  const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
+  const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
+
+  // X operand: the two-term copy for the Z-jobs of the mixed launch (op2),
+  // the copy in this job's format otherwise
+  const char* xop = (const char*)(MIX && kind == kJobZ ? a.x_in.op2 : a.x_in.op);
+  const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
+  // row block I / J starts at the same byte offset in both layouts:
+  // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
+  const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
+  const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
+  const char* b0 = xop + rowJ;
+  const char* a1 = xop + rowI;
+  const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
+
+  // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
+  // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
+  // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
+  // exponent bounded from ||Y_n||_F.
+  float usc = 1.0f, sc_out = 1.0f;
+  int s_out = 0;
+  if constexpr (PREC == kSplitH) {
+    if (kind == kJobZ) {
+      const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
+      usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
+      const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
+      s_out = yscale_exp(meta_norm(mi, nb * nb, s_nrm), kYBound);
+    } else {
+      usc = ldexpf(1.0f, -2 * kXScaleExp);
+      s_out = kXScaleExp;
+    }
+    sc_out = ldexpf(1.0f, s_out);
+  }
+
+  // The thread index is made opaque per job so that the compiler keeps the
+  // lane-dependent address arithmetic inside the job (hoisted out of the
+  // job loop it would stay live through the main loop and spill).
+  unsigned int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
+  const int h = lane >> 5, l32 = lane & 31;
+  const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
+
+  f32x16 acc[BR][BC], tot[BR][BC];
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) acc[i][j] = f32x16{0};
+
+  // The stages of the job's K stream are fetched in order, each call of dma
+  // the next one: cA / cB address stage cs of the A / B panel (tiled: its
+  // chunk, which advances by one chunk per stage; row-major: its column
+  // offset).  A Z-job's stream switches to the second product at stage
+  // spass; stages past the end re-fetch stage 0 into a slot that is never
+  // read again, which keeps the vmcnt bookkeeping uniform.
+  const uint32_t ldb32 = (uint32_t)ldb;
+  const size_t chunkb = (size_t)P::CHUNK;
+  const size_t step_b = P::TILED ? chunkb : (size_t)P::RB;   // bytes from one stage to the next
+  const size_t a_hi = (size_t)spass * chunkb;                // tiled: A rows 128-255 (next row block)
+  const char* cA = a0;
+  const char* cB = b0;
+  int cs = 0;
+  auto dma = [&](LDS_AS char* slot) {
+    if constexpr (P::TILED) dma_stage_tiled<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
+    else dma_stage_rows<PREC>(slot, cA, cB, ldb32, wave, lane);
+    ++cs;   // selects, not branches: the stage body stays one basic block
+    const bool wrap = cs >= nst, second = cs == spass;
+    cA = wrap ? a0 : second ? a1 : cA + step_b;
+    cB = wrap ? b0 : second ? b1 : cB + step_b;
+  };
+
+  if constexpr (PREC == kFP32) {
+    // FP32 products: the MFMA accumulator is added into an FP64 tile sum
+    // every `flush` stages (exact outer sum: the only FP32 rounding chain
+    // left is the accumulator's own, `flush` stages long).  One operand
+    // register set: with 32 MFMAs of 64 cycles per stage the other wave of
+    // the SIMD covers this wave's LDS reads.
+    double td[BR][BC][16];
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) td[i][j][e] = 0.0;
+    Ops<PREC> o;
+    dma(R0);
+    dma(R1);
+    dma(R2);
+    // Block b = (bi, bj) of the accumulator is added into the FP64 sum
+    // every `flush` = 4g stages, the four blocks one stage apart (block b at
+    // stages 4g q + b).  In the stage that flushes block b its MFMAs are
+    // issued first; the conversions follow the stage's last MFMA, when the
+    // operand registers are free and block b's chain has long completed.
+    const int grp = a.flush >= 4 ? a.flush / 4 : 0;   // 0: single level
+    int gq = 0;   // group of 4 stages, modulo grp
+#define DMPT_ITER1(CUR, REFILL, K)                                    \
+    {                                                                 \
+      wait_vm<2 * P::L, true>();                                      \
+      barrier_nofence();                                              \
+      dma(REFILL);                                                    \
+      __builtin_amdgcn_sched_barrier(0);                              \
+      read_ops<PREC>(CUR, o, rowA, rowB, h);                          \
+      mma_fp32_from<K>(o, acc);                                       \
+      if (grp && gq == 0) {                                           \
+        _Pragma("unroll") for (int e = 0; e < 16; ++e)                \
+          td[(K) >> 1][(K) & 1][e] += (double)acc[(K) >> 1][(K) & 1][e]; \
+        acc[(K) >> 1][(K) & 1] = f32x16{0};                           \
+      }                                                               \
+    }
+    for (int s = 0; s < nst; s += 4) {
+      DMPT_ITER1(R0, R3, 0)
+      DMPT_ITER1(R1, R0, 1)
+      DMPT_ITER1(R2, R1, 2)
+      DMPT_ITER1(R3, R2, 3)
+      if (++gq == grp) gq = 0;
+    }
+#undef DMPT_ITER1
+    wait_vm<0, true>();
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tot[i][j][e] = (float)(td[i][j][e] + (double)acc[i][j][e]);
+  } else {
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) tot[i][j] = f32x16{0};
+  Ops<PREC> o0, o1;
+  dma(R0);
+  dma(R1);
+  dma(R2);
+  wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
+  barrier_nofence();
+  dma(R3);
+  __builtin_amdgcn_sched_barrier(0);
+  read_ops<PREC>(R0, o0, rowA, rowB, h);
+
+  // Iteration s: the operands of stage s are in registers (OC).  Wait until
+  // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
+  // LDS reads of stage s are done, barrier (so has every wave), refill the
+  // slot of stage s with stage s+4, read stage s+1 into the other register
+  // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
+  // of the previous one.
+#define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
+  {                                                       \
+    wait_vm<2 * P::L, true>();                            \
+    barrier_nofence();                                    \
+    dma(REFILL);   /* stage (S_) + 4 */                   \
+    __builtin_amdgcn_sched_barrier(0);                    \
+    read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
+    mma_ops<PREC>(OC, acc);                               \
+    stage_order<PREC>();                                  \
+  }
+  const int flj = MIX && kind == kJobZ && a.flush_z > 0 ? a.flush_z : a.flush;
+  const int fl4 = flj > 0 ? flj : 1 << 30;   // flush every fl4 groups of 4 stages
+  int since = 0;
+  for (int s = 0; s < nst; s += 4) {
+    DMPT_ITER(s + 0, R1, R0, o0, o1)
+    DMPT_ITER(s + 1, R2, R1, o1, o0)
+    DMPT_ITER(s + 2, R3, R2, o0, o1)
+    DMPT_ITER(s + 3, R0, R3, o1, o0)
+    if (++since == fl4) {
+      since = 0;
+#pragma unroll
+      for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int j = 0; j < BC; ++j) {
+          tot[i][j] += acc[i][j];
+          acc[i][j] = f32x16{0};
+        }
+    }
+  }
+#undef DMPT_ITER
+  wait_vm<0, true>();
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
+  }
+  if constexpr (PREC == kSplitH) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
+  }
+  if (a.oscale != 0.0f && a.oscale != 1.0f) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
+  }
+
+  // ------------------------------------------------------------ epilogue
+  const size_t np = a.n_pad;
+  const MatRef& in = kind == kJobZ ? a.y_in : a.x_in;
+  const MatRef& out = kind == kJobZ ? a.y_out : a.x_out;
+  const float* cur = in.f32 + (kind == kJobZ ? obs * in.stride_f32 : 0);
+  float* o32 = out.f32 + (kind == kJobZ ? obs * out.stride_f32 : 0);
+  char* oop = (char*)out.op + (kind == kJobZ ? obs * out.stride_op : 0);
+  // kSplit3 matrices of the three-term-X^2 option also get their two-term copy
+  char* oop2 = MIX && out.op2 ? (char*)out.op2 + (kind == kJobZ ? obs * out.stride_op : 0) : nullptr;
+  const int nstp = a.n_pad / Fmt<PREC>::K;   // stages per row (tiled layout)
+  // P-jobs of a run with the residual correction keep every X_{n+1} as plain BF16
+  char* hop = kind == kJobP && a.hist ? a.hist + (size_t)(a.step + 1) * a.hist_stride : nullptr;
+  const int nsth = a.n_pad / Fmt<kBF16>::K;
+  const bool wsplit = a.write_split && PREC != kFP32;
+  const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
+  double tr = 0.0, sq = 0.0, ep = 0.0;
+  double yq = 0.0;   // kSplitH Z-jobs: ||Y_{n+1}||_F^2 over this tile (and its mirror)
+  const bool need_cur = kind == kJobP || sigma < 0;
+  if (!onDiag) {
+    // Off-diagonal tile: every element is stored twice (direct and mirror).
+    // Each wave stages its 64 x 64 region in LDS (private area, no cross-wave
+    // traffic) and writes rows of 16-byte vectors: direct rows, mirror rows,
+    // and 16-byte split-term slots of 8 consecutive columns in both
+    // orientations.  The barrier makes sure every wave is past its last ring
+    // read and every ring DMA has landed.
+    barrier_nofence();
+    LDS_AS char* rb = (wave >> 1) == 0 ? R0 : (wave >> 1) == 1 ? R1 : (wave >> 1) == 2 ? R2 : R3;
+    LDS_AS float* T = (LDS_AS float*)(rb + (wave & 1) * kStageBytes);
+    // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+#pragma unroll
+    for (int bi = 0; bi < BR; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BC; ++bj)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) T[(bi * 32 + 8 * g + 4 * h + e) * kLS + bj * 32 + l32] = tot[bi][bj][4 * g + e];
+    wait_vm<63, true>();
+    const int gr0 = ti * TM + wr * 64, gc0 = tj * TN + wc * 64;   // global origin of the region
+    // direct rows: 4 rows x 64 columns per round, 4 columns per lane
+#pragma unroll 4
+    for (int rd = 0; rd < 16; ++rd) {
+      const int r = 4 * rd + (lane >> 4), c = 4 * (lane & 15);
+      f32x4 v = f32x4{T[r * kLS + c], T[r * kLS + c + 1], T[r * kLS + c + 2], T[r * kLS + c + 3]};
+      if (need_cur) {
+        const f32x4 x = *(const f32x4*)(cur + (size_t)(gr0 + r) * np + gc0 + c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float p = v[k];
+          v[k] = sigma > 0 ? p : 2.0f * x[k] - p;
+          if (kind == kJobP) {
+            const double d = x[k] - p;                // X_n - X_n^2
+            sq += 2.0 * (double)v[k] * (double)v[k];
+            ep += 2.0 * d * d;
+          }
+        }
+        if (sigma < 0) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) T[r * kLS + c + k] = v[k];
+        }
+      }
+      if constexpr (PREC == kSplitH) {
+        if (kind == kJobZ)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) yq += 2.0 * (double)v[k] * (double)v[k];
+      }
+      *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
+    }
+    wait_vm<63, true>();
+    // mirror rows: 4 mirror rows x 64 columns per round
+#pragma unroll 4
+    for (int rd = 0; rd < 16; ++rd) {
+      const int c = 4 * rd + (lane >> 4), q = 4 * (lane & 15);
+      *(f32x4*)(o32 + (size_t)(gc0 + c) * np + gr0 + q) =
+          f32x4{T[q * kLS + c], T[(q + 1) * kLS + c], T[(q + 2) * kLS + c], T[(q + 3) * kLS + c]};
+    }
+    if constexpr (PREC != kFP32) {
+      if (wsplit) {
+        // split-term slots: 8 rows x 8 groups of 8 columns per round, both orientations
+#pragma unroll 2
+        for (int rd = 0; rd < 8; ++rd) {
+          const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
+          float v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
+          store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v, sc_out);
+          if constexpr (MIX) {
+            if (oop2) store_group8_t<kSplit2>(oop2, nstp, gr0 + r, gc0 + c, v, 1.0f);
+          }
+        }
+#pragma unroll 2
+        for (int rd = 0; rd < 8; ++rd) {
+          const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
+          float v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
+          store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v, sc_out);
+          if constexpr (MIX) {
+            if (oop2) store_group8_t<kSplit2>(oop2, nstp, gc0 + c, gr0 + q, v, 1.0f);
+          }
+        }
+      }
+    }
+    if (hop) {
+      // plain BF16 copy of X_{n+1}, both orientations
+#pragma unroll 2
+      for (int rd = 0; rd < 8; ++rd) {
+        const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
+        store_group8_t<kBF16>(hop, nsth, gr0 + r, gc0 + c, v, 1.0f);
+      }
+#pragma unroll 2
+      for (int rd = 0; rd < 8; ++rd) {
+        const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
+        store_group8_t<kBF16>(hop, nsth, gc0 + c, gr0 + q, v, 1.0f);
+      }
+    }
+  } else {
+    // Diagonal tile: keep the upper triangle (row <= col) and mirror it.
+    // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+#pragma unroll
+    for (int bi = 0; bi < BR; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BC; ++bj) {
+        const int col = tj * TN + wc * 64 + bj * 32 + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = row0 + e;
+            if (r > col) continue;
+            const float p = tot[bi][bj][4 * g + e];
+            float v = p, dd = 0.0f;
+            if (need_cur) {
+              const float c0 = cur[(size_t)r * np + col];
+              v = sigma > 0 ? p : 2.0f * c0 - p;
+              dd = c0 - p;                               // X_n - X_n^2 (P-jobs)
+            }
+            o32[(size_t)r * np + col] = v;
+            o32[(size_t)col * np + r] = v;
+            if (wsplit) {
+              store_split1<Store<PREC>::F>(oop, nstp, r, col, v, sc_out);
+              if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v, sc_out);
+              if constexpr (MIX) {
+                if (oop2) {
+                  store_split1<kSplit2>(oop2, nstp, r, col, v, 1.0f);
+                  if (r != col) store_split1<kSplit2>(oop2, nstp, col, r, v, 1.0f);
+                }
+              }
+            }
+            if (hop) {
+              store_split1<kBF16>(hop, nsth, r, col, v, 1.0f);
+              if (r != col) store_split1<kBF16>(hop, nsth, col, r, v, 1.0f);
+            }
+            if constexpr (PREC == kSplitH) {
+              if (kind == kJobZ) yq += (r == col ? 1.0 : 2.0) * (double)v * (double)v;
+            }
+            if (kind == kJobP) {
+              const double w = r == col ? 1.0 : 2.0;
+              if (r == col) tr += v;
+              sq += w * (double)v * (double)v;
+              ep += w * (double)dd * (double)dd;
+            }
+          }
+        }
+      }
+  }
+
+  if (kind == kJobP) {
+    tr = wave_sum(tr);
+    sq = wave_sum(sq);
+    ep = wave_sum(ep);
+    if (lane == 0) {
+      s_red[3 * wave] = tr;
+      s_red[3 * wave + 1] = sq;
+      s_red[3 * wave + 2] = ep;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Part p = {0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < NW; ++w) {
+        p.tr += s_red[3 * w];
+        p.sq += s_red[3 * w + 1];
+        p.eps += s_red[3 * w + 2];
+      }
+      a.part_out[tile_index(ti, tj, a.ntile)] = p;
+    }
+  }
+  if constexpr (PREC == kSplitH) {
+    if (kind == kJobZ) {
+      yq = wave_sum(yq);
+      if (lane == 0) s_red[wave] = yq;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += s_red[w];
+        MatMeta* mo = (MatMeta*)(a.y_out.meta + obs * a.y_out.stride_op);
+        const int idx = tile_index(ti, tj, a.ntile);
+        mo->nrm[idx] = t;
+        if (idx == 0) {
+          const int tr_ = a.n_pad / TM;
+          mo->scale = s_out;
+          mo->count = tr_ * (tr_ + 1);
+        }
+      }
+    }
+  }
+}
+
+// The step kernel: a persistent grid over the job list.  PP is the operand
+// format of the P-jobs, PZ of the Z-jobs (equal except for the three-term-X^2
+// option, whose sweep products read two-term copies).
+template <int PP, int PZ>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(StepArgs a) {
   // Ring slots; after the main loop each holds the 64 x 65 FP32 staging
   // areas of two waves for the epilogue.
-  constexpr int RSZ = P::SLOT > 2 * kStageBytes ? P::SLOT : 2 * kStageBytes;
+  constexpr int SLOTP = Pipe<PP>::SLOT, SLOTZ = Pipe<PZ>::SLOT;
+  constexpr int SLOTM = SLOTP > SLOTZ ? SLOTP : SLOTZ;
+  constexpr int RSZ = SLOTM > 2 * kStageBytes ? SLOTM : 2 * kStageBytes;
   __shared__ __attribute__((aligned(1024))) char ring0[RSZ];
   __shared__ __attribute__((aligned(1024))) char ring1[RSZ];
   __shared__ __attribute__((aligned(1024))) char ring2[RSZ];
@@ -590,382 +997,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const int jpos = s_job;
     if (jpos < 0) break;
     const uint32_t job = a.jobs[jpos];
-    const int kind = job & 1;
-    const int obs = (job >> 1) & 127;
-    const int ti = (job >> 8) & 4095;    // 256-row block
-    const int tj = (job >> 20) & 4095;   // 128-column block
-    constexpr int opb = operand_bytes(PREC);
-    const size_t ldb = (size_t)a.n_pad * opb;
-    const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
-    const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
-
-    const char* xop = (const char*)a.x_in.op;
-    const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
-    // row block I / J starts at the same byte offset in both layouts:
-    // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
-    const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
-    const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
-    const char* b0 = xop + rowJ;
-    const char* a1 = xop + rowI;
-    const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
-
-    // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
-    // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
-    // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
-    // exponent bounded from ||Y_n||_F.
-    float usc = 1.0f, sc_out = 1.0f;
-    int s_out = 0;
-    if constexpr (PREC == kSplitH) {
-      if (kind == kJobZ) {
-        const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
-        usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
-        const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
-        s_out = yscale_exp(meta_norm(mi, nb * nb, &s_nrm), kYBound);
-      } else {
-        usc = ldexpf(1.0f, -2 * kXScaleExp);
-        s_out = kXScaleExp;
-      }
-      sc_out = ldexpf(1.0f, s_out);
-    }
-
-    // The thread index is made opaque per job so that the compiler keeps the
-    // lane-dependent address arithmetic inside the job (hoisted out of the
-    // job loop it would stay live through the main loop and spill).
-    unsigned int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
-    const int h = lane >> 5, l32 = lane & 31;
-    const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
-
-    f32x16 acc[BR][BC], tot[BR][BC];
-  #pragma unroll
-    for (int i = 0; i < BR; ++i)
-  #pragma unroll
-      for (int j = 0; j < BC; ++j) acc[i][j] = f32x16{0};
-
-    // The stages of the job's K stream are fetched in order, each call of dma
-    // the next one: cA / cB address stage cs of the A / B panel (tiled: its
-    // chunk, which advances by one chunk per stage; row-major: its column
-    // offset).  A Z-job's stream switches to the second product at stage
-    // spass; stages past the end re-fetch stage 0 into a slot that is never
-    // read again, which keeps the vmcnt bookkeeping uniform.
-    const uint32_t ldb32 = (uint32_t)ldb;
-    const size_t chunkb = (size_t)P::CHUNK;
-    const size_t step_b = P::TILED ? chunkb : (size_t)P::RB;   // bytes from one stage to the next
-    const size_t a_hi = (size_t)spass * chunkb;                // tiled: A rows 128-255 (next row block)
-    const char* cA = a0;
-    const char* cB = b0;
-    int cs = 0;
-    auto dma = [&](LDS_AS char* slot) {
-      if constexpr (PREC == kSplit32) dma_stage_t32<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
-      else if constexpr (P::TILED) dma_stage_tiled<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
-      else dma_stage_rows<PREC>(slot, cA, cB, ldb32, wave, lane);
-      ++cs;   // selects, not branches: the stage body stays one basic block
-      const bool wrap = cs >= nst, second = cs == spass;
-      cA = wrap ? a0 : second ? a1 : cA + step_b;
-      cB = wrap ? b0 : second ? b1 : cB + step_b;
-    };
     LDS_AS char* R0 = (LDS_AS char*)ring0;
     LDS_AS char* R1 = (LDS_AS char*)ring1;
     LDS_AS char* R2 = (LDS_AS char*)ring2;
     LDS_AS char* R3 = (LDS_AS char*)ring3;
-
-    if constexpr (PREC == kFP32) {
-      // FP32 products: the MFMA accumulator is added into an FP64 tile sum
-      // every `flush` stages (exact outer sum: the only FP32 rounding chain
-      // left is the accumulator's own, `flush` stages long).  One operand
-      // register set: with 32 MFMAs of 64 cycles per stage the other wave of
-      // the SIMD covers this wave's LDS reads.
-      double td[BR][BC][16];
-  #pragma unroll
-      for (int i = 0; i < BR; ++i)
-  #pragma unroll
-        for (int j = 0; j < BC; ++j)
-  #pragma unroll
-          for (int e = 0; e < 16; ++e) td[i][j][e] = 0.0;
-      Ops<PREC> o;
-      dma(R0);
-      dma(R1);
-      dma(R2);
-      // Block b = (bi, bj) of the accumulator is added into the FP64 sum
-      // every `flush` = 4g stages, the four blocks one stage apart (block b at
-      // stages 4g q + b).  In the stage that flushes block b its MFMAs are
-      // issued first; the conversions follow the stage's last MFMA, when the
-      // operand registers are free and block b's chain has long completed.
-      const int grp = a.flush >= 4 ? a.flush / 4 : 0;   // 0: single level
-      int gq = 0;   // group of 4 stages, modulo grp
-  #define DMPT_ITER1(CUR, REFILL, K)                                    \
-      {                                                                 \
-        wait_vm<2 * P::L, true>();                                      \
-        barrier_nofence();                                              \
-        dma(REFILL);                                                    \
-        __builtin_amdgcn_sched_barrier(0);                              \
-        read_ops<PREC>(CUR, o, rowA, rowB, h);                          \
-        mma_fp32_from<K>(o, acc);                                       \
-        if (grp && gq == 0) {                                           \
-          _Pragma("unroll") for (int e = 0; e < 16; ++e)                \
-            td[(K) >> 1][(K) & 1][e] += (double)acc[(K) >> 1][(K) & 1][e]; \
-          acc[(K) >> 1][(K) & 1] = f32x16{0};                           \
-        }                                                               \
-      }
-      for (int s = 0; s < nst; s += 4) {
-        DMPT_ITER1(R0, R3, 0)
-        DMPT_ITER1(R1, R0, 1)
-        DMPT_ITER1(R2, R1, 2)
-        DMPT_ITER1(R3, R2, 3)
-        if (++gq == grp) gq = 0;
-      }
-  #undef DMPT_ITER1
-      wait_vm<0, true>();
-  #pragma unroll
-      for (int i = 0; i < BR; ++i)
-  #pragma unroll
-        for (int j = 0; j < BC; ++j)
-  #pragma unroll
-          for (int e = 0; e < 16; ++e) tot[i][j][e] = (float)(td[i][j][e] + (double)acc[i][j][e]);
+    if constexpr (PP == PZ) {
+      step_job<PP>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
     } else {
-  #pragma unroll
-    for (int i = 0; i < BR; ++i)
-  #pragma unroll
-      for (int j = 0; j < BC; ++j) tot[i][j] = f32x16{0};
-    Ops<PREC> o0, o1;
-    dma(R0);
-    dma(R1);
-    dma(R2);
-    wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
-    barrier_nofence();
-    dma(R3);
-    __builtin_amdgcn_sched_barrier(0);
-    read_ops<PREC>(R0, o0, rowA, rowB, h);
-
-    // Iteration s: the operands of stage s are in registers (OC).  Wait until
-    // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
-    // LDS reads of stage s are done, barrier (so has every wave), refill the
-    // slot of stage s with stage s+4, read stage s+1 into the other register
-    // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
-    // of the previous one.
-  #define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
-    {                                                       \
-      wait_vm<2 * P::L, true>();                            \
-      barrier_nofence();                                    \
-      dma(REFILL);   /* stage (S_) + 4 */                   \
-      __builtin_amdgcn_sched_barrier(0);                    \
-      read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
-      mma_ops<PREC>(OC, acc);                               \
-      stage_order<PREC>();                                  \
-    }
-    const int fl4 = a.flush > 0 ? a.flush : 1 << 30;   // flush every fl4 groups of 4 stages
-    int since = 0;
-    for (int s = 0; s < nst; s += 4) {
-      DMPT_ITER(s + 0, R1, R0, o0, o1)
-      DMPT_ITER(s + 1, R2, R1, o1, o0)
-      DMPT_ITER(s + 2, R3, R2, o0, o1)
-      DMPT_ITER(s + 3, R0, R3, o1, o0)
-      if (++since == fl4) {
-        since = 0;
-  #pragma unroll
-        for (int i = 0; i < BR; ++i)
-  #pragma unroll
-          for (int j = 0; j < BC; ++j) {
-            tot[i][j] += acc[i][j];
-            acc[i][j] = f32x16{0};
-          }
-      }
-    }
-  #undef DMPT_ITER
-    wait_vm<0, true>();
-  #pragma unroll
-    for (int i = 0; i < BR; ++i)
-  #pragma unroll
-      for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
-    }
-    if constexpr (PREC == kSplitH) {
-  #pragma unroll
-      for (int i = 0; i < BR; ++i)
-  #pragma unroll
-        for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
-    }
-    if (a.oscale != 0.0f && a.oscale != 1.0f) {
-  #pragma unroll
-      for (int i = 0; i < BR; ++i)
-  #pragma unroll
-        for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
-    }
-
-    // ------------------------------------------------------------ epilogue
-    const size_t np = a.n_pad;
-    const MatRef& in = kind == kJobZ ? a.y_in : a.x_in;
-    const MatRef& out = kind == kJobZ ? a.y_out : a.x_out;
-    const float* cur = in.f32 + (kind == kJobZ ? obs * in.stride_f32 : 0);
-    float* o32 = out.f32 + (kind == kJobZ ? obs * out.stride_f32 : 0);
-    char* oop = (char*)out.op + (kind == kJobZ ? obs * out.stride_op : 0);
-    const int nstp = a.n_pad / Fmt<PREC>::K;   // stages per row (tiled layout)
-    const bool wsplit = a.write_split && PREC != kFP32;
-    const bool onDiag = tj <= 2 * ti + 1;   // tile straddles the diagonal
-    double tr = 0.0, sq = 0.0, ep = 0.0;
-    double yq = 0.0;   // kSplitH Z-jobs: ||Y_{n+1}||_F^2 over this tile (and its mirror)
-    const bool need_cur = kind == kJobP || sigma < 0;
-    if (!onDiag) {
-      // Off-diagonal tile: every element is stored twice (direct and mirror).
-      // Each wave stages its 64 x 64 region in LDS (private area, no cross-wave
-      // traffic) and writes rows of 16-byte vectors: direct rows, mirror rows,
-      // and 16-byte split-term slots of 8 consecutive columns in both
-      // orientations.  The barrier makes sure every wave is past its last ring
-      // read and every ring DMA has landed.
-      barrier_nofence();
-      LDS_AS char* rb = (wave >> 1) == 0 ? R0 : (wave >> 1) == 1 ? R1 : (wave >> 1) == 2 ? R2 : R3;
-      LDS_AS float* T = (LDS_AS float*)(rb + (wave & 1) * kStageBytes);
-      // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
-  #pragma unroll
-      for (int bi = 0; bi < BR; ++bi)
-  #pragma unroll
-        for (int bj = 0; bj < BC; ++bj)
-  #pragma unroll
-          for (int g = 0; g < 4; ++g)
-  #pragma unroll
-            for (int e = 0; e < 4; ++e) T[(bi * 32 + 8 * g + 4 * h + e) * kLS + bj * 32 + l32] = tot[bi][bj][4 * g + e];
-      wait_vm<63, true>();
-      const int gr0 = ti * TM + wr * 64, gc0 = tj * TN + wc * 64;   // global origin of the region
-      // direct rows: 4 rows x 64 columns per round, 4 columns per lane
-  #pragma unroll 4
-      for (int rd = 0; rd < 16; ++rd) {
-        const int r = 4 * rd + (lane >> 4), c = 4 * (lane & 15);
-        f32x4 v = f32x4{T[r * kLS + c], T[r * kLS + c + 1], T[r * kLS + c + 2], T[r * kLS + c + 3]};
-        if (need_cur) {
-          const f32x4 x = *(const f32x4*)(cur + (size_t)(gr0 + r) * np + gc0 + c);
-  #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const float p = v[k];
-            v[k] = sigma > 0 ? p : 2.0f * x[k] - p;
-            if (kind == kJobP) {
-              const double d = x[k] - p;                // X_n - X_n^2
-              sq += 2.0 * (double)v[k] * (double)v[k];
-              ep += 2.0 * d * d;
-            }
-          }
-          if (sigma < 0) {
-  #pragma unroll
-            for (int k = 0; k < 4; ++k) T[r * kLS + c + k] = v[k];
-          }
-        }
-        if constexpr (PREC == kSplitH) {
-          if (kind == kJobZ)
-  #pragma unroll
-            for (int k = 0; k < 4; ++k) yq += 2.0 * (double)v[k] * (double)v[k];
-        }
-        *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
-      }
-      wait_vm<63, true>();
-      // mirror rows: 4 mirror rows x 64 columns per round
-  #pragma unroll 4
-      for (int rd = 0; rd < 16; ++rd) {
-        const int c = 4 * rd + (lane >> 4), q = 4 * (lane & 15);
-        *(f32x4*)(o32 + (size_t)(gc0 + c) * np + gr0 + q) =
-            f32x4{T[q * kLS + c], T[(q + 1) * kLS + c], T[(q + 2) * kLS + c], T[(q + 3) * kLS + c]};
-      }
-      if constexpr (PREC != kFP32) {
-        if (wsplit) {
-          // split-term slots: 8 rows x 8 groups of 8 columns per round, both orientations
-  #pragma unroll 2
-          for (int rd = 0; rd < 8; ++rd) {
-            const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
-            float v[8];
-  #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
-            store_group8_t<Store<PREC>::F>(oop, nstp, gr0 + r, gc0 + c, v, sc_out);
-          }
-  #pragma unroll 2
-          for (int rd = 0; rd < 8; ++rd) {
-            const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
-            float v[8];
-  #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
-            store_group8_t<Store<PREC>::F>(oop, nstp, gc0 + c, gr0 + q, v, sc_out);
-          }
-        }
-      }
-    } else {
-      // Diagonal tile: keep the upper triangle (row <= col) and mirror it.
-      // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
-  #pragma unroll
-      for (int bi = 0; bi < BR; ++bi)
-  #pragma unroll
-        for (int bj = 0; bj < BC; ++bj) {
-          const int col = tj * TN + wc * 64 + bj * 32 + l32;
-  #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int row0 = ti * TM + wr * 64 + bi * 32 + 8 * g + 4 * h;
-  #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int r = row0 + e;
-              if (r > col) continue;
-              const float p = tot[bi][bj][4 * g + e];
-              float v = p, dd = 0.0f;
-              if (need_cur) {
-                const float c0 = cur[(size_t)r * np + col];
-                v = sigma > 0 ? p : 2.0f * c0 - p;
-                dd = c0 - p;                               // X_n - X_n^2 (P-jobs)
-              }
-              o32[(size_t)r * np + col] = v;
-              o32[(size_t)col * np + r] = v;
-              if (wsplit) {
-                store_split1<Store<PREC>::F>(oop, nstp, r, col, v, sc_out);
-                if (r != col) store_split1<Store<PREC>::F>(oop, nstp, col, r, v, sc_out);
-              }
-              if constexpr (PREC == kSplitH) {
-                if (kind == kJobZ) yq += (r == col ? 1.0 : 2.0) * (double)v * (double)v;
-              }
-              if (kind == kJobP) {
-                const double w = r == col ? 1.0 : 2.0;
-                if (r == col) tr += v;
-                sq += w * (double)v * (double)v;
-                ep += w * (double)dd * (double)dd;
-              }
-            }
-          }
-        }
-    }
-
-    if (kind == kJobP) {
-      tr = wave_sum(tr);
-      sq = wave_sum(sq);
-      ep = wave_sum(ep);
-      if (lane == 0) {
-        s_red[3 * wave] = tr;
-        s_red[3 * wave + 1] = sq;
-        s_red[3 * wave + 2] = ep;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        Part p = {0.0, 0.0, 0.0, 0.0};
-        for (int w = 0; w < NW; ++w) {
-          p.tr += s_red[3 * w];
-          p.sq += s_red[3 * w + 1];
-          p.eps += s_red[3 * w + 2];
-        }
-        a.part_out[tile_index(ti, tj, a.ntile)] = p;
-      }
-    }
-    if constexpr (PREC == kSplitH) {
-      if (kind == kJobZ) {
-        yq = wave_sum(yq);
-        if (lane == 0) s_red[wave] = yq;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          double t = 0.0;
-          for (int w = 0; w < NW; ++w) t += s_red[w];
-          MatMeta* mo = (MatMeta*)(a.y_out.meta + obs * a.y_out.stride_op);
-          const int idx = tile_index(ti, tj, a.ntile);
-          mo->nrm[idx] = t;
-          if (idx == 0) {
-            const int tr_ = a.n_pad / TM;
-            mo->scale = s_out;
-            mo->count = tr_ * (tr_ + 1);
-          }
-        }
-      }
+      if ((job & 1) == kJobZ) step_job<PZ, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      else step_job<PP, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
     }
   }
 }
@@ -990,12 +1030,12 @@ hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s) {
   args.njobs = njobs;
   const dim3 grid(persistent_grid(njobs));
   switch (prec) {
-    case kFP32: hipLaunchKernelGGL(k_step<kFP32>, grid, dim3(NT), 0, s, args); break;
-    case kSplit2: hipLaunchKernelGGL(k_step<kSplit2>, grid, dim3(NT), 0, s, args); break;
-    case kSplit3: hipLaunchKernelGGL(k_step<kSplit3>, grid, dim3(NT), 0, s, args); break;
-    case kSplit32: hipLaunchKernelGGL(k_step<kSplit32>, grid, dim3(NT), 0, s, args); break;
-    case kBF16: hipLaunchKernelGGL(k_step<kBF16>, grid, dim3(NT), 0, s, args); break;
-    case kSplitH: hipLaunchKernelGGL(k_step<kSplitH>, grid, dim3(NT), 0, s, args); break;
+    case kFP32: hipLaunchKernelGGL((k_step<kFP32, kFP32>), grid, dim3(NT), 0, s, args); break;
+    case kSplit2: hipLaunchKernelGGL((k_step<kSplit2, kSplit2>), grid, dim3(NT), 0, s, args); break;
+    case kSplit3: hipLaunchKernelGGL((k_step<kSplit3, kSplit3>), grid, dim3(NT), 0, s, args); break;
+    case kSplit32: hipLaunchKernelGGL((k_step<kSplit3, kSplit2>), grid, dim3(NT), 0, s, args); break;
+    case kBF16: hipLaunchKernelGGL((k_step<kBF16, kBF16>), grid, dim3(NT), 0, s, args); break;
+    case kSplitH: hipLaunchKernelGGL((k_step<kSplitH, kSplitH>), grid, dim3(NT), 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1177,6 +1217,7 @@ hipError_t launch_gemm_op(int prec, const void* A, const void* B, float* C, int 
     case kFP32: hipLaunchKernelGGL(k_gemm_nt<kFP32>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
     case kSplitH: hipLaunchKernelGGL(k_gemm_nt<kSplitH>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
     case kSplit3: hipLaunchKernelGGL(k_gemm_nt<kSplit3>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
+    case kSplit2: hipLaunchKernelGGL(k_gemm_nt<kSplit2>, dim3(tiles), dim3(NT), 0, s, A, B, C, n_pad, alpha, flush, sym); break;
     default: return hipErrorInvalidValue;
   }
   if (sym) {
@@ -1455,7 +1496,7 @@ hipError_t launch_lanczos_step(const float* h, int n, double* v, double* vprev, 
 __device__ __forceinline__ void store_group8(int prec, char* op, int n_pad, int r, int c0, const float (&v)[8],
                                              float sc) {
   if (prec == kSplit2) store_group8_t<kSplit2>(op, n_pad / Fmt<kSplit2>::K, r, c0, v, sc);
-  else if (prec == kSplit3 || prec == kSplit32) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v, sc);
+  else if (prec == kSplit3) store_group8_t<kSplit3>(op, n_pad / Fmt<kSplit3>::K, r, c0, v, sc);
   else if (prec == kBF16) store_group8_t<kBF16>(op, n_pad / Fmt<kBF16>::K, r, c0, v, sc);
   else if (prec == kSplitH) store_group8_t<kSplitH>(op, n_pad / Fmt<kSplitH>::K, r, c0, v, sc);
 }
@@ -1529,6 +1570,7 @@ hipError_t launch_copy_src(int prec, const float* src, int n_src, void* dst, int
   switch (prec) {
     case kSplitH: hipLaunchKernelGGL(k_copy_src<kSplitH>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
     case kSplit3: hipLaunchKernelGGL(k_copy_src<kSplit3>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
+    case kSplit2: hipLaunchKernelGGL(k_copy_src<kSplit2>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
     case kBF16: hipLaunchKernelGGL(k_copy_src<kBF16>, dim3(2048), dim3(256), 0, s, src, n_src, (char*)dst, n_pad, sc); break;
     default: return hipErrorInvalidValue;
   }
@@ -1705,6 +1747,9 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
   // first, so here Y gets only its master and norm partials (k_resplit
   // writes the copy)
   const bool ycopy_later = prec == kSplitH && z != 0;
+  // three-term-X^2 option: X_1 gets its three- and two-term copies, Y_1 the two-term one
+  const int fmt = prec == kSplit32 ? (z == 0 ? kSplit3 : kSplit2) : prec;
+  char* oop2 = prec == kSplit32 && z == 0 ? (char*)x.op2 : nullptr;
   const float sc = prec == kSplitH ? ldexpf(1.0f, kXScaleExp) : 1.0f;
   double tr = 0.0, sq = 0.0;
   // each thread: 2 groups of 8 consecutive columns
@@ -1730,7 +1775,8 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
     float* dst = o32 + (size_t)gi * n_pad + bj * 64 + cg;
     *(f32x4*)dst = f32x4{v[0], v[1], v[2], v[3]};
     *(f32x4*)(dst + 4) = f32x4{v[4], v[5], v[6], v[7]};
-    if (!ycopy_later) store_group8(prec, oop, n_pad, gi, bj * 64 + cg, v, sc);
+    if (!ycopy_later) store_group8(fmt, oop, n_pad, gi, bj * 64 + cg, v, sc);
+    if (oop2) store_group8(kSplit2, oop2, n_pad, gi, bj * 64 + cg, v, 1.0f);
   }
   if (ycopy_later) {
     sq = wave_sum(sq);

@@ -154,10 +154,14 @@ def test_split3_accepted(lib, prec):
     assert lib.dmpt_sp2_density(FAKE, FAKE, C.byref(o), None) == 6   # passes validation
 
 
-def test_split3x_workspace_matches_split3(lib):
-    """The mixed mode keeps three-term operand copies: same workspace as split-3."""
+def test_split3x_workspace_adds_two_term_copies(lib):
+    """The mixed mode keeps the three-term copy of every matrix slot plus a
+    two-term copy (4 bytes per element): split-3's workspace plus 4 n_pad^2
+    bytes for each of the 2 X slots and 2 x nobs Y slots."""
     a, b = _opts(lib, 1000, 500, precision=2), _opts(lib, 1000, 500, precision=4)
-    assert lib.dmpt_workspace_bytes(C.byref(a), 2) == lib.dmpt_workspace_bytes(C.byref(b), 2)
+    n_pad, nobs = 1024, 2
+    extra = (2 + 2 * nobs) * 4 * n_pad * n_pad
+    assert lib.dmpt_workspace_bytes(C.byref(b), nobs) - lib.dmpt_workspace_bytes(C.byref(a), nobs) == extra
 
 
 def test_response_validation(lib):
@@ -356,7 +360,18 @@ def test_fermi_validation(lib):
                 FermiOpts(kt=0.01, canonical=0, mu=float("nan")), FermiOpts(kt=0.01, canonical=1, doublings=41),
                 FermiOpts(kt=0.01, canonical=1, reserved=1), FermiOpts(kt=0.01, canonical=1, count_tol=-1.0)):
         assert lib.dmpt_fermi_workspace_bytes(C.byref(o), C.byref(bad), 1) == 0
-    split = _opts(lib, 1000, 500, precision=1)
+    # product formats: FP32, the FP16 split, the two- and three-term BF16 splits
+    # (operand copies of 4, 4 and 6 bytes per element); plain BF16 and the
+    # three-term-X^2 option are not offered here
+    n_pad = 1024
+    copies = 7 + 2                                      # E, E^2, R, T, E_next, S, W + 2 Y
+    for prec, nbytes in ((5, 4), (1, 4), (2, 6)):
+        sp = _opts(lib, 1000, 500, precision=prec)
+        ws = lib.dmpt_fermi_workspace_bytes(C.byref(sp), C.byref(f), 2)
+        assert ws - w == copies * nbytes * n_pad * n_pad, prec
+    split = _opts(lib, 1000, 500, precision=3)
+    assert lib.dmpt_fermi_workspace_bytes(C.byref(split), C.byref(f), 1) == 0
+    split = _opts(lib, 1000, 500, precision=4)
     assert lib.dmpt_fermi_workspace_bytes(C.byref(split), C.byref(f), 1) == 0
     edge = _opts(lib, 1000, 0)                          # canonical needs 0 < nocc < n
     assert lib.dmpt_fermi_workspace_bytes(C.byref(edge), C.byref(f), 1) == 0

@@ -97,3 +97,48 @@ def test_duality_and_batching(gpu, c5):
     assert abs(lhs - rhs) <= 1e-4 * max(abs(lhs), 1e-3 * float(chi[0].double().norm()))
     one, _, _, _ = dm.susceptibility_fermi(H, A[2].contiguous(), wl.nocc, 0.01, bounds="gershgorin")
     assert torch.equal(one, chi[2])
+
+
+@pytest.fixture(scope="module")
+def c5_full():
+    """Config 5 at its size: N = 16384, gapless banded H (half-bandwidth 256),
+    kT = 0.01; four of its observables (the batch shape is what matters; the
+    32 of the full configuration are timed by bench.py --extra fermi)."""
+    return W.banded_gapless(16384, half_bandwidth=256, nobs=4)
+
+
+def test_config5_full_size(gpu, c5_full):
+    """N = 16384 with the three-term BF16 split (config 5's split-BF16
+    products) and FP32, four observables in one batch: the electron count,
+    Tr chi = 0 (the mu_1 shift), the self-adjointness Tr[chi_A B] = Tr[A chi_B]
+    of the canonical susceptibility, and the two precisions agreeing on D, mu
+    and chi.  No closed form at this size (an FP64 eigendecomposition of
+    16384 x 16384 takes minutes): the same checks pass against the oracle at
+    n = 1000 above."""
+    import torch
+
+    import paper_2409_17033_amd as dm
+    wl = c5_full
+    H, A = _dev(wl.H, gpu), _dev(wl.A, gpu)
+    out = {}
+    for prec in ("split3_bf16", "fp32"):
+        chi, D, a0, info = dm.susceptibility_fermi(H, A, wl.nocc, 0.01, precision=prec)
+        torch.cuda.synchronize()
+        cd = chi.double()
+        tr = max(abs(float(cd[k].trace())) / float(cd[k].norm()) for k in range(4))
+        lhs = float((cd[0] * A[1].double()).sum())
+        rhs = float((A[0].double() * cd[1]).sum())
+        dual = abs(lhs - rhs) / max(abs(lhs), 1e-3 * float(cd[0].norm()))
+        print(f"\nN=16384 {prec}: m={info['doublings']} newton={info['newton']} products={info['products']} "
+              f"mu={info['mu']:.6f} TrD-N={info['trace_d'] - wl.nocc:.2e} Tr chi {tr:.1e} duality {dual:.1e} "
+              f"{info['elapsed_ms'] / 1e3:.1f} s", flush=True)
+        assert abs(info["trace_d"] - wl.nocc) <= 1e-6 * wl.n
+        assert tr <= 1e-5 and dual <= 1e-4
+        out[prec] = (chi.cpu(), D.cpu(), info["mu"])
+        del chi, D, cd
+        torch.cuda.empty_cache()
+    (c3, d3, mu3), (c32, d32, mu32) = out["split3_bf16"], out["fp32"]
+    ec = float((c3.double() - c32.double()).norm() / c32.double().norm())
+    ed = float((d3.double() - d32.double()).norm() / d32.double().norm())
+    print(f"split3_bf16 vs fp32: chi {ec:.1e} D {ed:.1e} mu {abs(mu3 - mu32):.1e}")
+    assert ec <= 1e-4 and ed <= 1e-5 and abs(mu3 - mu32) <= 1e-6

@@ -4,7 +4,8 @@ H1 = diag(N(0, 0.01^2)), FP32, residual target 1e-6; the FP32 loop's
 residual floor is ~1.5e-7).
 
 References: the FP64 oracle (oracle/scf.py, oracle/mlp.py) for the loop's
-result and for the network's forward pass, gradient and Adam step; the
+result (at N = 256 and at config 4's N = 1024, every mixer) and for the
+network's forward pass, gradient and Adam step; the
 GPU's own duality Tr[chi_A H1] = Tr[A chi_H1] (both self-consistent).
 """
 import numpy as np
@@ -167,6 +168,34 @@ def c4():
     return W.scf_system(1024, cfg=4, ntrain=80)
 
 
+@pytest.fixture(scope="module")
+def c4_oracle(c4):
+    """The FP64 oracle's self-consistent chi of config 4's A (the paper's
+    linear loop on full matrices, Eq. CP_SCF, stopped when the update falls
+    below 1e-11 of ||L[A]||_F; about 70 iterations)."""
+    wl, u, _ = c4
+    h0, a = wl.H.astype(np.float64), wl.A[0].astype(np.float64)
+    scale = np.linalg.norm(oscf.FirstOrder(h0, wl.nocc)(a))
+    ref, it, _ = oscf.scf_susceptibility(h0, a, u.astype(np.float64), wl.nocc, spin=2.0, tol=1e-11 * scale)
+    return ref
+
+
+@pytest.mark.parametrize("mixer", ["linear", "anderson"])
+def test_scf_config4_matches_oracle(gpu, c4, c4_oracle, mixer):
+    """Config 4 at its size (N = 1024): the self-consistent chi of the GPU
+    loop against the oracle's fixed point."""
+    import torch
+
+    import paper_2409_17033_amd as dm
+    wl, u, _ = c4
+    chi, sinfo, _ = dm.scf_response(torch.from_numpy(wl.H).to(gpu), torch.from_numpy(u).to(gpu),
+                                    torch.from_numpy(wl.A[0]).to(gpu), wl.nocc, mixer=mixer, tol=1e-6)
+    err = cf.rel_frobenius(chi.double().cpu().numpy(), c4_oracle)
+    print(f"
+config 4 scf {mixer}: evaluations {sinfo['iters']} err {err:.2e}")
+    assert sinfo["converged"] and err <= 1e-5
+
+
 def test_scf_duality_config4(gpu, c4):
     """Tr[chi_A H1] = Tr[A chi_H1]: the self-consistent susceptibility of A and
     the self-consistent density response to H1 (the same loop with A := H1)."""
@@ -185,7 +214,7 @@ def test_scf_duality_config4(gpu, c4):
 
 
 @pytest.mark.timeout(600)
-def test_learned_mixer_gain_config4(gpu, c4):
+def test_learned_mixer_gain_config4(gpu, c4, c4_oracle):
     """Train the mixer on the method's own pairs from 72 training observables
     (linear-mixing states, then two passes of states the learned loop visits;
     over 2000 pairs), then solve for held-out observables (A and 8 more) with
@@ -211,6 +240,10 @@ def test_learned_mixer_gain_config4(gpu, c4):
             chis[mixer] = chi.double().cpu().numpy()
         for k in ("anderson", "learned", "learned_anderson"):
             assert cf.rel_frobenius(chis[k], chis["linear"]) <= 1e-5
+        if j == 0:   # A: every mixer's chi against the oracle's fixed point
+            errs = {k: cf.rel_frobenius(c, c4_oracle) for k, c in chis.items()}
+            print(f"\nconfig 4 A, error against the oracle: {errs}")
+            assert max(errs.values()) <= 1e-5
     print("evaluations to 1e-6 on held-out observables: " + "; ".join(f"{k} {v}" for k, v in ev.items()))
     assert report["passes"][-1][0] >= 2000
     assert sum(ev["learned"]) < 0.75 * sum(ev["linear"])

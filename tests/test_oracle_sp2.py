@@ -20,6 +20,20 @@ def test_gershgorin_encloses_spectrum(c1):
     assert lo <= w[0] and w[-1] <= hi
 
 
+def test_gershgorin_hand_worked_discs():
+    """Disc endpoints worked by hand (all dyadic, so exact in FP64).
+    Rows of h: centre 2, radius 1.5 -> [0.5, 3.5]; centre 0, radius 1.25 ->
+    [-1.25, 1.25]; centre -3, radius 0.75 -> [-3.75, -2.25].  The interval is
+    the union's hull [-3.75, 3.5]; a radius that also counted the diagonal,
+    or missed the absolute value, gives another interval."""
+    h = np.array([[2.0, -1.0, 0.5], [-1.0, 0.0, 0.25], [0.5, 0.25, -3.0]])
+    assert sp2.gershgorin_bounds(h) == (-3.75, 3.5)
+    # [[1, 1], [1, 1]]: both discs are [0, 2], which is exactly the spectrum {0, 2}
+    assert sp2.gershgorin_bounds(np.ones((2, 2))) == (0.0, 2.0)
+    # a diagonal matrix: radius 0, the bounds are its extreme entries
+    assert sp2.gershgorin_bounds(np.diag([0.3, -1.5, 4.0])) == (-1.5, 4.0)
+
+
 def test_sigma_rule_picks_closest_trace():
     rng = np.random.default_rng(1)
     for _ in range(20):
@@ -39,7 +53,14 @@ def test_diagonal_h_gives_exact_step_function():
     want = np.zeros(8)
     want[np.argsort(e)[:nocc]] = 1.0
     np.testing.assert_allclose(d, np.diag(want), atol=1e-12)
-    assert abs(sum(tr.sigmas) - sum(tr.sigmas)) == 0 and tr.m >= 10
+    assert tr.m >= 10
+    # on a diagonal H every step acts on each eigenvalue alone: the recorded
+    # sigma sequence, applied to the scalars x_i = (emax - e_i) / (emax - emin),
+    # must give the same step function
+    x = (tr.emax - e) / (tr.emax - tr.emin)
+    for s in tr.sigmas:
+        x = x * x if s > 0 else 2 * x - x * x
+    np.testing.assert_allclose(x, want, atol=1e-12)
 
 
 def test_diagonal_h_susceptibility_is_textbook():
