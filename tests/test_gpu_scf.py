@@ -191,8 +191,7 @@ def test_scf_config4_matches_oracle(gpu, c4, c4_oracle, mixer):
     chi, sinfo, _ = dm.scf_response(torch.from_numpy(wl.H).to(gpu), torch.from_numpy(u).to(gpu),
                                     torch.from_numpy(wl.A[0]).to(gpu), wl.nocc, mixer=mixer, tol=1e-6)
     err = cf.rel_frobenius(chi.double().cpu().numpy(), c4_oracle)
-    print(f"
-config 4 scf {mixer}: evaluations {sinfo['iters']} err {err:.2e}")
+    print(f"\nconfig 4 scf {mixer}: evaluations {sinfo['iters']} err {err:.2e}")
     assert sinfo["converged"] and err <= 1e-5
 
 
