@@ -124,7 +124,11 @@ typedef struct dmpt_opts {
                              sigma sequence, projected with D, and chi' = Y + delta.  On the
                              eigenbasis delta_ij = R_ij / (lambda_i - lambda_j) on the
                              occupied-virtual pairs, the error left in Y there; the sweep only
-                             has to be accurate relative to that small correction.  0 -> off. */
+                             has to be accurate relative to that small correction.  With
+                             DMPT_SPLIT3X_BF16 the sweep products of the steps, of the projection
+                             and of the correction then run on 256 x 256 output tiles with one
+                             FP32 accumulation level (the correction removes what that adds).
+                             2 -> the same correction on the regular tiles only.  0 -> off. */
   double spin;            /* s; 0 -> 2 */
   void* stream;           /* hipStream_t */
   void* workspace;        /* device memory owned by the caller */

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -69,7 +70,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (o->profile != 0 && o->profile != 1) return fail(DMPT_ERR_ARG, "profile must be 0 or 1");
   if (o->ckpt_interval < 0 || o->ckpt_interval > DMPT_MAX_STEPS)
     return fail(DMPT_ERR_ARG, "ckpt_interval out of range [0, %d]", DMPT_MAX_STEPS);
-  if (o->refine != 0 && o->refine != 1) return fail(DMPT_ERR_ARG, "refine must be 0 or 1");
+  if (o->refine < 0 || o->refine > 2) return fail(DMPT_ERR_ARG, "refine must be 0, 1 or 2");
   if (o->refine && (o->sweep != DMPT_SWEEP_FORWARD || !o->project))
     return fail(DMPT_ERR_ARG, "refine needs the forward sweep with the projection");
   r->n = o->n;
@@ -313,6 +314,87 @@ std::vector<uint32_t> build_jobs(int n_pad, int nobs_z, bool with_p) {
   return out;
 }
 
+// Sweep-product jobs (Z-jobs) with 256 x 256 output tiles (kJobWide): tile
+// (I, J), J >= I, on the 256 grid covers the regular tiles (I, 2J) and
+// (I, 2J + 1), and a 4 x 4 group of them the regular 4 x 8 group, so the
+// groups above are reused: a group is either wide as a whole or regular.
+// A wide tile streams two 256-row panels per stage where a regular one
+// streams 256 + 128 rows for half the products: a third fewer bytes and LDS
+// reads per unit of work.  Measured on MI355X at N = 8192 (Z-only launches
+// of 1056 regular, 528 wide tiles; two-term and plain BF16 alike), a wide
+// tile takes 1.6 - 1.7 times a regular one, and a P-job of the three-term
+// split about as long as a regular Z-job.
+constexpr double kWideCost = 1.65;
+
+std::vector<uint32_t> wide_group(const std::vector<std::pair<int, int>>& g, int obs) {
+  std::vector<uint32_t> w;
+  for (const auto& t : g) {
+    if (t.second & 1) continue;   // (I, 2J + 1) belongs to the wide tile of (I, 2J)
+    w.push_back(job_pack(kJobZ, obs, t.first, t.second / 2) | kJobWide);
+  }
+  // a diagonal group's (I, 2I + 1) has its partner (I, 2I) in the list: no tile is lost
+  return w;
+}
+
+// Makespan, in regular-tile units, of a persistent launch that deals
+// `costs` in order to `cus` workgroups (each takes the next job when free).
+double list_makespan(const std::vector<double>& costs, int cus) {
+  std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+  for (int c = 0; c < cus; ++c) q.push(0.0);
+  double end = 0.0;
+  for (double c : costs) {
+    const double t = q.top() + c;
+    q.pop();
+    q.push(t);
+    end = std::max(end, t);
+  }
+  return end;
+}
+
+// Z-jobs of nobs observables, followed in the launch by np_tail P-jobs (one
+// regular unit each; they are not part of the returned list): the leading
+// groups are wide and the rest regular, the split chosen to minimise the
+// launch's makespan on `cus` workgroups (whole rounds of wide tiles, then
+// regular tiles to even out the last round).
+std::vector<uint32_t> build_zjobs_wide(int n_pad, int nobs, int np_tail, int cus) {
+  const auto groups = tile_groups(n_pad);
+  std::vector<std::pair<int, size_t>> order;   // (obs, group)
+  for (int k = 0; k < nobs; ++k)
+    for (size_t g = 0; g < groups.size(); ++g) order.emplace_back(k, g);
+  size_t best_w = 0;
+  {
+    double best = 0.0;
+    std::vector<size_t> cand;   // many observables: a coarse search
+    const size_t stride = std::max<size_t>(1, order.size() / 64);
+    for (size_t nw = 0; nw < order.size(); nw += stride) cand.push_back(nw);
+    cand.push_back(order.size());
+    for (size_t nw : cand) {
+      std::vector<double> c;
+      for (size_t q = 0; q < nw; ++q)
+        c.insert(c.end(), (groups[order[q].second].size() + 1) / 2, kWideCost);
+      for (size_t q = nw; q < order.size(); ++q) c.insert(c.end(), groups[order[q].second].size(), 1.0);
+      c.insert(c.end(), (size_t)np_tail, 1.0);
+      const double t = list_makespan(c, cus);
+      if (nw == 0 || t < best - 1e-9) { best = t; best_w = nw; }
+    }
+  }
+  std::vector<uint32_t> out;
+  std::vector<std::vector<uint32_t>> wg, rg;
+  for (size_t q = 0; q < order.size(); ++q) {
+    const auto& g = groups[order[q].second];
+    if (q < best_w) {
+      wg.push_back(wide_group(g, order[q].first));
+    } else {
+      std::vector<uint32_t> r;
+      for (const auto& t : g) r.push_back(job_pack(kJobZ, order[q].first, t.first, t.second));
+      rg.push_back(std::move(r));
+    }
+  }
+  append_xcd_ordered(out, wg);
+  append_xcd_ordered(out, rg);
+  return out;
+}
+
 // ---------------------------------------------------------------- Lanczos (host part)
 
 // Number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm count).
@@ -547,13 +629,19 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   // whose P-jobs also write X's two-term copy (the sweep reads it)
   const int xlaunch = p.prec == kSplit32 ? kSplit32 : xprec;
 
+  const bool refining = nobs > 0 && o.refine && !adjoint;
+  // 256 x 256 sweep-product tiles (one accumulation level) when the residual
+  // correction follows: the three-term-X^2 option's steps and projection, and
+  // the correction's own launches
+  const bool wide = refining && o.refine == 1 && split_launch;
+  const int cus = persistent_grid(1 << 30);
   // job tables: [Z-jobs][P-jobs] (one combined table when the step is one launch)
   std::vector<uint32_t> jobs;
   int njobs_z = 0;
   if (split_launch) {
-    jobs = build_jobs(p.n_pad, nobs, false);
-    njobs_z = (int)jobs.size();
     const std::vector<uint32_t> pj = build_jobs(p.n_pad, 0, true);
+    jobs = wide ? build_zjobs_wide(p.n_pad, nobs, (int)pj.size(), cus) : build_jobs(p.n_pad, nobs, false);
+    njobs_z = (int)jobs.size();
     jobs.insert(jobs.end(), pj.begin(), pj.end());
   } else {
     jobs = build_jobs(p.n_pad, adjoint ? 0 : nobs, true);
@@ -576,10 +664,10 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   // kept clean by the launches themselves).
   DMPT_HIP(launch_queue_reset(ctl, s));
   unsigned qseq = 0;
-  auto run_step = [&](int prec_, StepArgs& args, int nj) {
+  auto run_step = [&](int prec_, StepArgs& args, int nj, bool wide_ = false) {
     if (nj <= 0) return hipSuccess;   // no launch: the counter sets stay in step
     step_queue_sets(ctl, qseq++, &args);
-    return launch_step(prec_, args, nj, s);
+    return launch_step(prec_, args, nj, s, wide_);
   };
 
   // Slot of X_n: forward sweep 2 ping-pong slots; adjoint slot n, or with
@@ -627,7 +715,6 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.flush = flush_interval(xprec, p.n_pad);
   a.jobs = d_jobs;
   a.ctl = ctl;
-  const bool refining = nobs > 0 && o.refine && !adjoint;
   if (refining) {   // every X_{n+1} also as plain BF16 for the correction sweep
     a.hist = ws + p.off_rf_hist;
     a.hist_stride = (size_t)p.n_pad * p.n_pad * 2;
@@ -655,7 +742,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
         a.jobs = d_jobs;
         a.flush = flush_interval(xprec, p.n_pad);
         a.flush_z = flush_interval(yprec, p.n_pad);
-        DMPT_HIP(run_step(kSplit32, a, njobs_main));
+        DMPT_HIP(run_step(kSplit32, a, njobs_main, wide));
       } else {
         a.jobs = step_jobs;
         DMPT_HIP(run_step(xlaunch, a, njobs_step));
@@ -720,6 +807,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     yfin = ys;
   }
 
+  int njobs_proj = 0;
   if (nobs > 0 && o.project && st == DMPT_OK) {
     // Occupied-virtual projection: two sweep steps with X frozen at D
     // (sigma = +1 then -1) multiply the eigenbasis blocks of Y by
@@ -727,9 +815,12 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // They run in the precision of the sweep products (FP32 for plain BF16),
     // on the operand copies of D and Y the last step wrote.
     const int pprec = p.prec == kBF16 ? kFP32 : yprec;
-    const std::vector<uint32_t> pjobs = build_jobs(p.n_pad, nobs, false);
+    // (the list also serves the launches of the residual correction)
+    const std::vector<uint32_t> pjobs =
+        wide ? build_zjobs_wide(p.n_pad, nobs, 0, cus) : build_jobs(p.n_pad, nobs, false);
     uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
     DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));
+    njobs_proj = (int)pjobs.size();
     StepArgs b;
     std::memset(&b, 0, sizeof(b));
     b.n = o.n;
@@ -745,9 +836,10 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // the stopping test needs its idempotency error) formed Z = D Y + Y D from
     // D = X_{m+1} and Y_{m+1}, the product of the first projection step.
     // When the projection runs in the precision of the sweep products, that
-    // launch replaces the first projection step: with sigma = +1 its Y_{m+2} = Z is bit for bit what the
-    // step would write (same kernel, inputs, tile products and accumulation
-    // order); with sigma = -1, Y_{m+2} = 2 Y_{m+1} - Z and one elementwise pass
+    // launch replaces the first projection step: with sigma = +1 its Y_{m+2} = Z is the product the
+    // step would form, in the same precision (bit for bit unless the two
+    // launches tile it differently, as the wide/regular mix of a corrected
+    // run may); with sigma = -1, Y_{m+2} = 2 Y_{m+1} - Z and one elementwise pass
     // recovers Z = 2 Y_{m+1} - Y_{m+2} (one more FP32 rounding), with its
     // operand copy at the scale the step would use (Y_{m+2}'s own: both come
     // from Y_{m+1}) and fresh norm partials for the second step.
@@ -766,7 +858,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.write_split = q == 0 && pprec != kFP32;   // the second step reads it
       b.y_in = view(y_ref(p, ws, yfin));
       b.y_out = view(y_ref(p, ws, yfin ^ 1));
-      DMPT_HIP(run_step(pprec, b, (int)pjobs.size()));
+      DMPT_HIP(run_step(pprec, b, (int)pjobs.size(), wide));
       yfin ^= 1;
     }
   }
@@ -868,7 +960,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     auto bx = [&](int q) { return bf16_ref(p, ws, p.off_rf_x, q, 1); };
     auto by = [&](int q) { return bf16_ref(p, ws, p.off_rf_y, q, nobs); };
     const uint32_t* d_pjobs = (const uint32_t*)(ws + p.off_jobs_proj);   // Z-jobs of every observable
-    const int nzj = p.nparts_step * nobs;
+    const int nzj = njobs_proj;
     StepArgs b;
     std::memset(&b, 0, sizeof(b));
     b.n = o.n;
@@ -884,7 +976,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.y_in = rref;
     b.y_out = by(1);
     b.oscale = (float)(-hctl.beta);
-    DMPT_HIP(run_step(kBF16, b, nzj));
+    DMPT_HIP(run_step(kBF16, b, nzj, wide));
     // X_1 = alpha I + beta H in plain BF16 (its copy lands in history slot 1)
     MatRef x1 = bx(0);
     x1.op = hist + hstride;
@@ -900,7 +992,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       r.x_in.op = hist + (size_t)n * hstride;
       r.y_in = by(n & 1);
       r.y_out = by((n + 1) & 1);
-      DMPT_HIP(run_step(kBF16, r, nzj));
+      DMPT_HIP(run_step(kBF16, r, nzj, wide));
     }
     // projection of delta with D, then Y += P(delta)
     int yd = (m + 1) & 1;
@@ -910,7 +1002,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.oscale = 1.0f;
       b.y_in = by(yd);
       b.y_out = by(yd ^ 1);
-      DMPT_HIP(run_step(kBF16, b, nzj));
+      DMPT_HIP(run_step(kBF16, b, nzj, wide));
       yd ^= 1;
     }
     const MatRef dl = by(yd);

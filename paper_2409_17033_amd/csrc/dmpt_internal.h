@@ -85,6 +85,9 @@ enum JobKind : uint32_t { kJobP = 0, kJobZ = 1 };
 inline uint32_t job_pack(uint32_t kind, uint32_t obs, uint32_t ti, uint32_t tj) {
   return kind | (obs << 1) | (ti << 8) | (tj << 20);
 }
+// Bit 7 of a Z-job (obs < 64 uses bits 1-6): a wide job, one 256 x 256 tile
+// (I, J >= I) of Z with tj counting 256-column blocks.
+constexpr uint32_t kJobWide = 1u << 7;
 
 // Per-matrix metadata next to each operand copy: the scale exponent of the
 // FP16 copy (kSplitH) and FP64 partials of ||M||_F^2 written by the producer
@@ -150,10 +153,14 @@ hipError_t launch_set_bounds(Ctl* ctl, double emin, double emax, hipStream_t s);
 hipError_t launch_init(int prec, int tile, const float* h, const float* a, int n, int n_pad,
                        int nobs, const uint32_t* jobs, int njobs, MatRef x, MatRef y,
                        double y_scale_mode, Part* part, Ctl* ctl, hipStream_t s);
+// Workgroups of a persistent step launch over njobs jobs (one per CU at most).
+int persistent_grid(int njobs);
 // Step launch: a persistent grid of at most one workgroup per CU working
 // through args.jobs[0, njobs) (njobs is stored into the arguments).  The
 // caller sets qhead / qclear from step_queue_sets.
-hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s);
+// wide: the list may hold wide Z-jobs (kJobWide; kSplit2, kSplit32 and kBF16
+// only), which accumulate on one level.
+hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s, bool wide = false);
 // Queue counter sets of the seq-th step launch since the last queue reset.
 inline void step_queue_sets(Ctl* ctl, unsigned seq, StepArgs* a) {
   a->qhead = ctl->qhead[seq % kQSets];

@@ -414,7 +414,7 @@ __device__ __forceinline__ void stage_order() {
 // bounds check of X_k, else sigma_k.  Every workgroup evaluates the same FP64
 // numbers in the same order and reaches the same decision; workgroup 0
 // records it.  Returns sigma_k (+1 / -1) or a stop code.
-__device__ int step_controller(const StepArgs& a, int* s_code) {
+__device__ __forceinline__ int step_controller(const StepArgs& a, int* s_code) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double tr = 0.0, sq = 0.0, eps = 0.0;
@@ -525,7 +525,7 @@ __device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, 
                                          double* s_nrm) {
   using P = Pipe<PREC>;
   const int kind = job & 1;
-  const int obs = (job >> 1) & 127;
+  const int obs = (job >> 1) & 63;
   const int ti = (job >> 8) & 4095;    // 256-row block
   const int tj = (job >> 20) & 4095;   // 128-column block
   constexpr int opb = operand_bytes(PREC);
@@ -728,13 +728,18 @@ __device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, 
 
   // ------------------------------------------------------------ epilogue
   const size_t np = a.n_pad;
-  const MatRef& in = kind == kJobZ ? a.y_in : a.x_in;
-  const MatRef& out = kind == kJobZ ? a.y_out : a.x_out;
-  const float* cur = in.f32 + (kind == kJobZ ? obs * in.stride_f32 : 0);
-  float* o32 = out.f32 + (kind == kJobZ ? obs * out.stride_f32 : 0);
-  char* oop = (char*)out.op + (kind == kJobZ ? obs * out.stride_op : 0);
+  // field-wise selects (a selected reference would keep the argument block in
+  // private memory)
+  const bool zk = kind == kJobZ;
+  const float* cur = zk ? a.y_in.f32 + obs * a.y_in.stride_f32 : a.x_in.f32;
+  float* o32 = zk ? a.y_out.f32 + obs * a.y_out.stride_f32 : a.x_out.f32;
+  char* oop = zk ? (char*)a.y_out.op + obs * a.y_out.stride_op : (char*)a.x_out.op;
   // kSplit3 matrices of the three-term-X^2 option also get their two-term copy
-  char* oop2 = MIX && out.op2 ? (char*)out.op2 + (kind == kJobZ ? obs * out.stride_op : 0) : nullptr;
+  char* oop2 = nullptr;
+  if constexpr (MIX) {
+    char* o2 = (char*)(zk ? a.y_out.op2 : a.x_out.op2);
+    oop2 = o2 ? o2 + (zk ? obs * a.y_out.stride_op : 0) : nullptr;
+  }
   const int nstp = a.n_pad / Fmt<PREC>::K;   // stages per row (tiled layout)
   // P-jobs of a run with the residual correction keep every X_{n+1} as plain BF16
   char* hop = kind == kJobP && a.hist ? a.hist + (size_t)(a.step + 1) * a.hist_stride : nullptr;
@@ -941,14 +946,289 @@ __device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, 
   }
 }
 
+// ---------------------------------------------------------------- wide sweep jobs
+
+// Z-jobs on 256 x 256 output tiles (I, J >= I): twice the columns of a
+// regular tile for the same A panel, so a stage brings 21 bytes per MFMA
+// cycle instead of 32 (two-term split) and the DMA-bound loop gets closer to
+// the MFMA rate.  Eight waves as 2 x 4, each a 128 x 64 region (4 x 2 blocks
+// of 32 x 32): 128 accumulator registers, so one accumulation level only —
+// these jobs run only when the residual correction of chi follows, which
+// removes the sweep's accumulation error.  Formats: the two-term BF16 split
+// and plain BF16 (stages of 64 bytes per row, 8 KB per 128-row chunk).
+constexpr int WTN = 256, WBR = 4, WBC = 2, WL = 4;
+template <int PREC> struct WPipe {
+  static_assert(PREC == kSplit2 || PREC == kBF16, "wide sweep jobs: two-term BF16 split or plain BF16");
+  static constexpr int RB = Fmt<PREC>::RB;
+  static constexpr int A_BYTES = TM * RB, B_BYTES = WTN * RB;
+  static constexpr int SLOT = A_BYTES + B_BYTES;     // 32 KB: 32 one-KB DMA copies, WL per wave
+  static constexpr int CHUNK = RBLK * RB;            // 8 KB: one 128-row stage chunk in HBM
+  static constexpr int R = (WBR + WBC) * 2;          // ds_read_b128 per stage
+  static constexpr int M = WBR * WBC * (PREC == kSplit2 ? 3 : 2);   // MFMAs per stage
+};
+struct WOps { bf16x8 a[WBR][2], b[WBC][2]; };        // [p]: split term (kSplit2) or k16 step (kBF16)
+template <int PREC> struct WSlot { static constexpr int V = TM * Fmt<PREC>::RB + WTN * Fmt<PREC>::RB; };
+
+// One stage into a ring slot: A rows 0-127, A rows 128-255, B rows 0-127,
+// B rows 128-255, each a contiguous 8 KB chunk; wave w copies kilobyte w of each.
+__device__ __forceinline__ void wdma(LDS_AS char* slot, const char* a0, const char* a1, const char* b0,
+                                     const char* b1, int wave, int lane) {
+  const size_t off = (size_t)wave * 1024 + (size_t)lane * 16;
+  __builtin_amdgcn_global_load_lds((const GLB_AS void*)(a0 + off), (LDS_AS void*)(slot + wave * 1024), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((const GLB_AS void*)(a1 + off), (LDS_AS void*)(slot + (wave + NW) * 1024), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((const GLB_AS void*)(b0 + off), (LDS_AS void*)(slot + (wave + 2 * NW) * 1024), 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((const GLB_AS void*)(b1 + off), (LDS_AS void*)(slot + (wave + 3 * NW) * 1024), 16, 0, 0);
+}
+
+template <int PREC>
+__device__ __forceinline__ void wread(const LDS_AS char* slot, WOps& o, int rowA, int rowB, int h) {
+  const LDS_AS char* pA = slot;
+  const LDS_AS char* pB = slot + WPipe<PREC>::A_BYTES;
+#pragma unroll
+  for (int i = 0; i < WBR; ++i)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+      o.a[i][p] = __builtin_bit_cast(bf16x8, lds16(pA + swz<4>(rowA + 32 * i, PREC == kSplit2 ? 2 * h + p : 2 * p + h)));
+#pragma unroll
+  for (int j = 0; j < WBC; ++j)
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+      o.b[j][p] = __builtin_bit_cast(bf16x8, lds16(pB + swz<4>(rowB + 32 * j, PREC == kSplit2 ? 2 * h + p : 2 * p + h)));
+}
+
+// acc[i][j] += A_i B_j^T for one stage, product-major so that eight
+// independent accumulator chains separate dependent MFMAs.
+template <int PREC>
+__device__ __forceinline__ void wmma(const WOps& o, f32x16 (&acc)[WBR][WBC]) {
+  if constexpr (PREC == kSplit2) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int i = 0; i < WBR; ++i)
+#pragma unroll
+        for (int j = 0; j < WBC; ++j) {
+          const int pa = q == 1 ? 1 : 0, pb = q == 0 ? 1 : 0;   // hl, lh, hh
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][pa], o.b[j][pb], acc[i][j], 0, 0, 0);
+        }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int i = 0; i < WBR; ++i)
+#pragma unroll
+        for (int j = 0; j < WBC; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[i][t], o.b[j][t], acc[i][j], 0, 0, 0);
+  }
+}
+
+// The next stage's LDS reads spread among this stage's MFMAs.
+template <int R, int M>
+__device__ __forceinline__ void stage_order_rm() {
+  if constexpr (M % R == 0) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, M / R, 0);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, M - R, 0);
+  }
+}
+
+// One wide Z-job: Z_IJ = Y_I X_J^T + X_I Y_J^T (256 x 256), then the
+// sigma-update, the direct and mirror stores and the operand copy of Y_{n+1}.
+// MIX: X's two-term copy is op2 (three-term-X^2 option).
+template <int PREC, bool MIX>
+__device__ __forceinline__ void step_job_wide(const StepArgs& a, const uint32_t job, const int sigma, LDS_AS char* R0,
+                                              LDS_AS char* R1, LDS_AS char* R2, LDS_AS char* R3) {
+  using P = WPipe<PREC>;
+  const int obs = (job >> 1) & 63;
+  const int ti = (job >> 8) & 4095;    // 256-row block
+  const int tj = (job >> 20) & 4095;   // 256-column block, tj >= ti
+  const size_t ldb = (size_t)a.n_pad * operand_bytes(PREC);
+  const int spass = a.n_pad / Fmt<PREC>::K;
+  const int nst = 2 * spass;
+  const char* xop = (const char*)(MIX ? a.x_in.op2 : a.x_in.op);
+  const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
+  const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * WTN * ldb;
+  const char* a0 = yop + rowI;   // Y_I, then X_I
+  const char* b0 = xop + rowJ;   // X_J, then Y_J
+  const char* a1 = xop + rowI;
+  const char* b1 = yop + rowJ;
+
+  unsigned int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 2, wc = wave & 3;   // 2 x 4 waves of 128 x 64
+  const int h = lane >> 5, l32 = lane & 31;
+  const int rowA = wr * 128 + l32, rowB = wc * 64 + l32;
+
+  f32x16 acc[WBR][WBC];
+#pragma unroll
+  for (int i = 0; i < WBR; ++i)
+#pragma unroll
+    for (int j = 0; j < WBC; ++j) acc[i][j] = f32x16{0};
+
+  const size_t chunkb = (size_t)P::CHUNK;
+  const size_t hi = (size_t)spass * chunkb;   // rows 128-255 of a 256-row panel: the next row block
+  const char* cA = a0;
+  const char* cB = b0;
+  int cs = 0;
+  auto dma = [&](LDS_AS char* slot) {
+    wdma(slot, cA, cA + hi, cB, cB + hi, wave, lane);
+    ++cs;
+    const bool wrap = cs >= nst, second = cs == spass;
+    cA = wrap ? a0 : second ? a1 : cA + chunkb;
+    cB = wrap ? b0 : second ? b1 : cB + chunkb;
+  };
+  WOps o0, o1;
+  dma(R0);
+  dma(R1);
+  dma(R2);
+  wait_vm<2 * WL, false>();
+  barrier_nofence();
+  dma(R3);
+  __builtin_amdgcn_sched_barrier(0);
+  wread<PREC>(R0, o0, rowA, rowB, h);
+#define DMPT_WITER(NEXT, REFILL, OC, ON)          \
+  {                                               \
+    wait_vm<2 * WL, true>();                      \
+    barrier_nofence();                            \
+    dma(REFILL);                                  \
+    __builtin_amdgcn_sched_barrier(0);            \
+    wread<PREC>(NEXT, ON, rowA, rowB, h);         \
+    wmma<PREC>(OC, acc);                          \
+    stage_order_rm<P::R, P::M>();                 \
+  }
+  for (int s = 0; s < nst; s += 4) {
+    DMPT_WITER(R1, R0, o0, o1)
+    DMPT_WITER(R2, R1, o1, o0)
+    DMPT_WITER(R3, R2, o0, o1)
+    DMPT_WITER(R0, R3, o1, o0)
+  }
+#undef DMPT_WITER
+  wait_vm<0, true>();
+  if (a.oscale != 0.0f && a.oscale != 1.0f) {
+#pragma unroll
+    for (int i = 0; i < WBR; ++i)
+#pragma unroll
+      for (int j = 0; j < WBC; ++j) acc[i][j] *= a.oscale;
+  }
+
+  // ---------------------------------------------------------- epilogue
+  const size_t np = a.n_pad;
+  const float* cur = a.y_in.f32 + obs * a.y_in.stride_f32;
+  float* o32 = a.y_out.f32 + obs * a.y_out.stride_f32;
+  char* oop = (char*)a.y_out.op + obs * a.y_out.stride_op;
+  const int nstp = a.n_pad / Fmt<PREC>::K;
+  const bool wsplit = a.write_split != 0;
+  const bool need_cur = sigma < 0;
+  const int gr_base = ti * TM + wr * 128, gc0 = tj * WTN + wc * 64;
+  if (ti != tj) {
+    // Off-diagonal tile: the wave's 128 x 64 region in two 64 x 64 halves,
+    // each staged in the wave's private LDS area (the ring, free after the
+    // barrier) and stored as rows of 16-byte vectors, direct and mirrored.
+    barrier_nofence();
+    LDS_AS char* rb = (wave >> 1) == 0 ? R0 : (wave >> 1) == 1 ? R1 : (wave >> 1) == 2 ? R2 : R3;
+    LDS_AS float* T = (LDS_AS float*)(rb + (wave & 1) * kStageBytes);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int gr0 = gr_base + half * 64;
+      if (half) wait_vm<63, true>();   // this wave's reads of the first half are done
+      // 32x32 MFMA output layout: lane l, register 4g+e holds row 8g + 4(l/32) + e, column l%32.
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < WBC; ++bj)
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              T[(bi * 32 + 8 * g + 4 * h + e) * kLS + bj * 32 + l32] = acc[2 * half + bi][bj][4 * g + e];
+      wait_vm<63, true>();
+#pragma unroll 4
+      for (int rd = 0; rd < 16; ++rd) {
+        const int r = 4 * rd + (lane >> 4), c = 4 * (lane & 15);
+        f32x4 v = f32x4{T[r * kLS + c], T[r * kLS + c + 1], T[r * kLS + c + 2], T[r * kLS + c + 3]};
+        if (need_cur) {
+          const f32x4 x = *(const f32x4*)(cur + (size_t)(gr0 + r) * np + gc0 + c);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            v[k] = 2.0f * x[k] - v[k];
+            T[r * kLS + c + k] = v[k];
+          }
+        }
+        *(f32x4*)(o32 + (size_t)(gr0 + r) * np + gc0 + c) = v;
+      }
+      wait_vm<63, true>();
+#pragma unroll 4
+      for (int rd = 0; rd < 16; ++rd) {
+        const int c = 4 * rd + (lane >> 4), q = 4 * (lane & 15);
+        *(f32x4*)(o32 + (size_t)(gc0 + c) * np + gr0 + q) =
+            f32x4{T[q * kLS + c], T[(q + 1) * kLS + c], T[(q + 2) * kLS + c], T[(q + 3) * kLS + c]};
+      }
+      if (wsplit) {
+#pragma unroll 2
+        for (int rd = 0; rd < 8; ++rd) {
+          const int r = 8 * rd + (lane >> 3), c = 8 * (lane & 7);
+          float v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = T[r * kLS + c + k];
+          store_group8_t<PREC>(oop, nstp, gr0 + r, gc0 + c, v, 1.0f);
+        }
+#pragma unroll 2
+        for (int rd = 0; rd < 8; ++rd) {
+          const int c = 8 * rd + (lane >> 3), q = 8 * (lane & 7);
+          float v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) v[k] = T[(q + k) * kLS + c];
+          store_group8_t<PREC>(oop, nstp, gc0 + c, gr0 + q, v, 1.0f);
+        }
+      }
+    }
+  } else {
+    // Diagonal tile: keep the upper triangle (row <= col) and mirror it.
+#pragma unroll
+    for (int bi = 0; bi < WBR; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < WBC; ++bj) {
+        const int col = gc0 + bj * 32 + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int row0 = gr_base + bi * 32 + 8 * g + 4 * h;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = row0 + e;
+            if (r > col) continue;
+            float v = acc[bi][bj][4 * g + e];
+            if (need_cur) v = 2.0f * cur[(size_t)r * np + col] - v;
+            o32[(size_t)r * np + col] = v;
+            o32[(size_t)col * np + r] = v;
+            if (wsplit) {
+              store_split1<PREC>(oop, nstp, r, col, v, 1.0f);
+              if (r != col) store_split1<PREC>(oop, nstp, col, r, v, 1.0f);
+            }
+          }
+        }
+      }
+  }
+}
+
 // The step kernel: a persistent grid over the job list.  PP is the operand
 // format of the P-jobs, PZ of the Z-jobs (equal except for the three-term-X^2
 // option, whose sweep products read two-term copies).
-template <int PP, int PZ>
+template <int PP, int PZ, bool ZW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step(StepArgs a) {
   // Ring slots; after the main loop each holds the 64 x 65 FP32 staging
-  // areas of two waves for the epilogue.
-  constexpr int SLOTP = Pipe<PP>::SLOT, SLOTZ = Pipe<PZ>::SLOT;
+  // areas of two waves for the epilogue.  ZW: the Z-jobs are wide (256 x 256).
+  constexpr int SLOTP = Pipe<PP>::SLOT;
+  constexpr int SLOTZ = ZW ? WSlot<PZ>::V : Pipe<PZ>::SLOT;
   constexpr int SLOTM = SLOTP > SLOTZ ? SLOTP : SLOTZ;
   constexpr int RSZ = SLOTM > 2 * kStageBytes ? SLOTM : 2 * kStageBytes;
   __shared__ __attribute__((aligned(1024))) char ring0[RSZ];
@@ -1001,7 +1281,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     LDS_AS char* R1 = (LDS_AS char*)ring1;
     LDS_AS char* R2 = (LDS_AS char*)ring2;
     LDS_AS char* R3 = (LDS_AS char*)ring3;
-    if constexpr (PP == PZ) {
+    constexpr bool MIX = PP != PZ;
+    if constexpr (ZW) {
+      if (job & kJobWide) step_job_wide<PZ, MIX>(a, job, sigma, R0, R1, R2, R3);
+      else if (MIX && (job & 1) == kJobZ) step_job<PZ, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      else step_job<PP, MIX>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+    } else if constexpr (!MIX) {
       step_job<PP>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
     } else {
       if ((job & 1) == kJobZ) step_job<PZ, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
@@ -1025,17 +1310,26 @@ int persistent_grid(int njobs) {
   return njobs < cus[dev] ? njobs : cus[dev];
 }
 
-hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s) {
+hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s, bool wide) {
   if (njobs <= 0) return hipSuccess;
   args.njobs = njobs;
   const dim3 grid(persistent_grid(njobs));
+  if (wide) {
+    switch (prec) {
+      case kSplit2: hipLaunchKernelGGL((k_step<kSplit2, kSplit2, true>), grid, dim3(NT), 0, s, args); break;
+      case kSplit32: hipLaunchKernelGGL((k_step<kSplit3, kSplit2, true>), grid, dim3(NT), 0, s, args); break;
+      case kBF16: hipLaunchKernelGGL((k_step<kBF16, kBF16, true>), grid, dim3(NT), 0, s, args); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (prec) {
-    case kFP32: hipLaunchKernelGGL((k_step<kFP32, kFP32>), grid, dim3(NT), 0, s, args); break;
-    case kSplit2: hipLaunchKernelGGL((k_step<kSplit2, kSplit2>), grid, dim3(NT), 0, s, args); break;
-    case kSplit3: hipLaunchKernelGGL((k_step<kSplit3, kSplit3>), grid, dim3(NT), 0, s, args); break;
-    case kSplit32: hipLaunchKernelGGL((k_step<kSplit3, kSplit2>), grid, dim3(NT), 0, s, args); break;
-    case kBF16: hipLaunchKernelGGL((k_step<kBF16, kBF16>), grid, dim3(NT), 0, s, args); break;
-    case kSplitH: hipLaunchKernelGGL((k_step<kSplitH, kSplitH>), grid, dim3(NT), 0, s, args); break;
+    case kFP32: hipLaunchKernelGGL((k_step<kFP32, kFP32, false>), grid, dim3(NT), 0, s, args); break;
+    case kSplit2: hipLaunchKernelGGL((k_step<kSplit2, kSplit2, false>), grid, dim3(NT), 0, s, args); break;
+    case kSplit3: hipLaunchKernelGGL((k_step<kSplit3, kSplit3, false>), grid, dim3(NT), 0, s, args); break;
+    case kSplit32: hipLaunchKernelGGL((k_step<kSplit3, kSplit2, false>), grid, dim3(NT), 0, s, args); break;
+    case kBF16: hipLaunchKernelGGL((k_step<kBF16, kBF16, false>), grid, dim3(NT), 0, s, args); break;
+    case kSplitH: hipLaunchKernelGGL((k_step<kSplitH, kSplitH, false>), grid, dim3(NT), 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -139,6 +139,29 @@ def test_refine_two_observables(gpu):
         assert cf.rel_frobenius(_np(one), _np(chi[k])) <= 1e-6
 
 
+def test_refined_wide_and_regular_tiles(gpu):
+    """split3x_bf16 with the correction at N = 2000 (padded to 2048), eight
+    random observables: the steps run their sweep products on 256 x 256 tiles
+    only, the projection and correction launches on a list of both kinds (72
+    wide and 432 regular tiles on 256 CUs), and refine = 2 runs everything on
+    the regular tiles.  Each observable is held to 1e-5 against the closed
+    form in both runs; the runs differ in accumulation order only."""
+    dm = _dm()
+    wl = W.banded_gapped(2000, nocc=1000, observable="random", nobs=8, npert=1, cfg=14, cache=False)
+    H, A = _dev(wl.H, gpu), _dev(wl.A, gpu)
+    chi_w, _, _, info_w = dm.susceptibility(H, A, wl.nocc, precision="split3x_bf16", refine=1, profile=True)
+    chi_r, _, _, info_r = dm.susceptibility(H, A, wl.nocc, precision="split3x_bf16", refine=2, profile=True)
+    refs = 2.0 * cf.first_order_responses(wl.H.astype(np.float64), wl.A.astype(np.float64), wl.nocc)
+    for k, ref in enumerate(refs):
+        ew = cf.rel_frobenius(_np(chi_w[k]), ref)
+        er = cf.rel_frobenius(_np(chi_r[k]), ref)
+        print(f"obs {k}: wide {ew:.2e} regular {er:.2e}")
+        assert ew <= 1e-5 and er <= 1e-5
+        assert cf.rel_frobenius(_np(chi_w[k]), _np(chi_r[k])) <= 5e-6
+    print(f"wide: steps {info_w['step_ms']:.2f} ms refine {info_w['refine_ms']:.2f} ms; "
+          f"regular: steps {info_r['step_ms']:.2f} ms refine {info_r['refine_ms']:.2f} ms")
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_sp2_density(gpu, prec):
     dm = _dm()
