@@ -6,10 +6,12 @@ sweep (Eq. DMSuscept) with device-side sigma/stop decisions -> occupied-virtual
 projection -> (with "+refine": the residual correction of chi) -> D, chi, a0
 -> responses Tr[chi H1] for 8 perturbations (Eq. dual).
 
-A path is a product precision, optionally with "+refine".  The headline is
-a BF16 path (the metric is split-BF16 against FP32); every path's D, chi and
-a0 are compared once, outside the timed region, with the FP64 closed form
-(one eigendecomposition on the host), and reported with its time.
+A path is a product precision, optionally with "+refine", and then with
+"@t": the sweeps stop once X_n is within t of idempotency (sweep_tol), the
+correction's within sqrt(t); the correction removes what that leaves.  The
+headline is a BF16 path (the metric is split-BF16 against FP32); every path's
+D, chi and a0 are compared once, outside the timed region, with the FP64
+closed form (one eigendecomposition on the host), and reported with its time.
 
 Workload: N = 8192, N_occ = 4096, banded tight-binding H (half-bandwidth 64,
 hopping ~ N(0, 0.05^2), onsite ~ U(-1, 1)) with a 0.1 gap opened at N_occ,
@@ -32,10 +34,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-χ (ms) + MFMA TFLOP/s at N=8192, split-BF16 vs FP32, at stated error"
 PEAK = {"bf16": 2516.6, "f16": 2516.6, "fp32": 157.3}          # dense MFMA TFLOP/s (MI355X)
-PRODUCTS = {"split3_bf16": 6, "split3x_bf16": 4, "split_bf16": 3, "split_fp16": 3, "fp32": 1, "bf16": 1}   # MFMA products per FP32-equivalent product (split3x: 6 for X^2, 3 for YX + XY)
-# The dominant kernel of each path: the step launch (kSplit3 for split3x's X^2
-# launch, which is the larger of its two launches per step).
-KERNEL = {"split3x_bf16": "k_step<split3_bf16> + k_step<split_bf16> (X^2 / sweep launches of one step)"}
+# MFMA products per FP32-equivalent product: (X^2, YX + XY) of one step
+PRODUCTS = {"split3_bf16": (6, 6), "split3x_bf16": (6, 3), "split_bf16": (3, 3), "split_fp16": (3, 3),
+            "fp32": (1, 1), "bf16": (1, 1)}
+
+
+def step_flops(prec, n_pad, m, sweep_steps, nobs=1):
+    """Executed MFMA flops of the m step launches on the upper-triangle
+    tiles: X^2 as a symmetric rank-n product (n^3 per product) in every
+    launch, YX + XY (2 n^3 per product) in the first sweep_steps launches
+    (all of them unless the sweep stopped early)."""
+    px, pz = PRODUCTS[prec]
+    n3 = float(n_pad) ** 3
+    return n3 * (m * px + sweep_steps * nobs * 2 * pz)
+
+
+# The dominant kernel of each path: the step launch (for split3x one mixed
+# launch: X^2 tiles in the three-term split, sweep tiles in the two-term one).
+KERNEL = {"split3x_bf16": "k_step<split3_bf16 X^2, split_bf16 sweep> (one mixed launch per SP2 + chi step)"}
 
 
 def log(msg):
@@ -48,9 +64,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="split3x_bf16+refine",
-                    help="headline path: a precision, optionally with +refine (the residual correction)")
-    ap.add_argument("--compare", default="fp32,split3_bf16,split_fp16,split_fp16+refine,split_bf16",
+    ap.add_argument("--precision", default="split3x_bf16+refine@1e-3",
+                    help="headline path: a precision, optionally with +refine (the residual correction) "
+                         "and @t (the sweeps stop at sweep_tol t)")
+    ap.add_argument("--compare", default="fp32,split3_bf16,split_fp16,split3x_bf16+refine,split_fp16+refine,"
+                                         "split_bf16",
                     help="other paths timed for context")
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--no-errors", action="store_true", help="skip the closed-form errors of each path")
@@ -90,9 +108,8 @@ def run_shapes(args, dm, torch, W, dev):
             info = infos[-1]
             m = info["m"]
             step_avg = info["step_ms"] / max(m, 1)
-            executed = 3.0 * float(n_pad) ** 3 * PRODUCTS[prec] / (step_avg * 1e-3) / 1e12
-            d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, precision=prec, spin=1.0, want_density=False,
-                                                refine=path.endswith("+refine"))
+            executed = step_flops(prec, n_pad, m, info["sweep_steps"]) / (info["step_ms"] * 1e-3) / 1e12
+            d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, spin=1.0, want_density=False, **path_kw(path))
             r_d1 = 2.0 * float(dm.response(d1, A)[0, 0])
             row["paths"][path] = {
                 "ms": round(ms, 3), "m": m, "step_avg_ms": round(step_avg, 4),
@@ -176,9 +193,15 @@ def property_errors(torch, H, A, D, chi, nocc, spin):
     return out
 
 
-def run_path(dm, torch, H, A, H1, nocc, path, steps, warmup):
+def path_kw(path):
+    """Options of a path "precision[+refine[@sweep_tol]]"."""
     prec, _, rf = path.partition("+")
-    kw = dict(precision=prec, profile=True, refine=rf == "refine")
+    rf, _, tol = rf.partition("@")
+    return dict(precision=prec, refine=rf == "refine", sweep_tol=float(tol) if tol else 0.0)
+
+
+def run_path(dm, torch, H, A, H1, nocc, path, steps, warmup):
+    kw = dict(path_kw(path), profile=True)
     for _ in range(warmup):
         chi, D, a0, info = dm.susceptibility(H, A, nocc, **kw)
         dm.response(chi, H1)
@@ -367,13 +390,14 @@ def main():
         props = property_errors(torch, H, A, D, chi, wl.nocc, 2.0)
         m = info["m"]
         n_pad = -(-wl.n // 256) * 256
-        step_flops = 3.0 * float(n_pad) ** 3 * PRODUCTS[prec]   # executed MFMA flops per SP2 step (triangle tiles)
+        flops = step_flops(prec, n_pad, m, info["sweep_steps"])   # executed MFMA flops of the m step launches
         step_avg_ms = info["step_ms"] / max(m, 1)
         results[path] = {
             "ms": ms, "m": m, "step_ms_total": info["step_ms"], "step_avg_ms": step_avg_ms,
             "bounds_ms": info["bounds_ms"], "project_ms": info["project_ms"], "refine_ms": info["refine_ms"],
             "output_ms": info["output_ms"], "elapsed_ms": info["elapsed_ms"],
-            "mfma_tflops": step_flops / (step_avg_ms * 1e-3) / 1e12 if step_avg_ms > 0 else None,
+            "sweep_steps": info["sweep_steps"], "correction_steps": info["correction_steps"],
+            "mfma_tflops": flops / (info["step_ms"] * 1e-3) / 1e12 if info["step_ms"] > 0 else None,
             "algorithmic_tflops": 3.0 * float(wl.n) ** 3 * m / (ms * 1e-3) / 1e12,
             "a0": a0[0], "props": props,
             "errors": path_errors(ref, D, chi, a0, resp, wl) if ref is not None else None,
@@ -425,7 +449,9 @@ def main():
                         "gap 0.1, A = site position, 8 random H1",
             "n": wl.n, "nocc": wl.nocc, "path": main_path,
             "sweep": "forward merged (Eq. DMSuscept) + occupied-virtual projection"
-                     + (" + residual correction" if main_path.endswith("+refine") else ""),
+                     + (" + residual correction" if path_kw(main_path)["refine"] else "")
+                     + (f", sweeps stopped at sweep_tol {path_kw(main_path)['sweep_tol']:g}"
+                        if path_kw(main_path)["sweep_tol"] else ""),
             "bounds": "lanczos",
         },
         "roofline": roof,

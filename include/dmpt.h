@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 6
+#define DMPT_ABI_VERSION 7
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -129,6 +129,16 @@ typedef struct dmpt_opts {
                              and of the correction then run on 256 x 256 output tiles with one
                              FP32 accumulation level (the correction removes what that adds).
                              2 -> the same correction on the regular tiles only.  0 -> off. */
+  double sweep_tol;       /* refine only, 0 <= sweep_tol < 1/4: the sweep products stop at the
+                             first X_n with ||X_n - X_n^2||_F^2 <= sweep_tol^2 (every eigenvalue
+                             of X_n within sweep_tol of 0 or 1; Y_{n+1} is kept, the recursion of
+                             X runs on to its stop), and the correction's sweep stops at the first
+                             X_n with ||X_n - X_n^2||_F^2 <= sweep_tol.  Stopped there, the sweep
+                             result differs from the converged one by O(sweep_tol) relative on the
+                             occupied-virtual pairs only (the projection removes the rest), which
+                             is the error the residual correction removes to first order; the
+                             correction itself only needs accuracy relative to its small size.
+                             0 -> the sweeps run to the end. */
   double spin;            /* s; 0 -> 2 */
   void* stream;           /* hipStream_t */
   void* workspace;        /* device memory owned by the caller */
@@ -156,6 +166,8 @@ typedef struct dmpt_info {
   int32_t step_launches;                /* step kernels launched (>= m + 1: the last one decides the stop) */
   int32_t tile;                         /* output tile edge of the step kernel */
   double refine_ms;                     /* residual correction (opts.refine), when profiled */
+  int32_t sweep_steps;                  /* sweep steps applied to the returned Y (m without sweep_tol) */
+  int32_t correction_steps;             /* sweep steps of the residual correction (0 without refine) */
 } dmpt_info;
 
 /* ABI version compiled into the library (DMPT_ABI_VERSION). */

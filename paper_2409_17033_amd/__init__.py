@@ -41,7 +41,8 @@ def make_opts(n: int, nocc: int, *, precision: str = "fp32", bounds: str = "lanc
               emin: float | None = None, emax: float | None = None, lanczos_steps: int = 0,
               max_iter: int = 0, min_iter: int = -1, sweep: str = "forward",
               idem_tol: float = 0.0, project: bool = True, spin: float = 2.0,
-              profile: bool = False, ckpt_interval: int = 0, refine: bool | int = False, stream=None) -> Opts:
+              profile: bool = False, ckpt_interval: int = 0, refine: bool | int = False,
+              sweep_tol: float = 0.0, stream=None) -> Opts:
     lib = load()
     o = Opts()
     lib.dmpt_opts_default(C.byref(o), n, nocc)
@@ -59,6 +60,7 @@ def make_opts(n: int, nocc: int, *, precision: str = "fp32", bounds: str = "lanc
     o.profile = 1 if profile else 0
     o.ckpt_interval = ckpt_interval
     o.refine = int(refine)   # True -> 1; 2: the correction on the regular tiles only
+    o.sweep_tol = sweep_tol
     if stream is None:
         torch = _torch()
         stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0

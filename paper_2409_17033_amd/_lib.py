@@ -23,7 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
-ABI_VERSION = 6   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
+ABI_VERSION = 7   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
 PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4, "split_fp16": 5}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
@@ -49,6 +49,7 @@ class Opts(C.Structure):
         ("idem_tol", C.c_double),
         ("project", C.c_int32), ("profile", C.c_int32),
         ("ckpt_interval", C.c_int32), ("refine", C.c_int32),
+        ("sweep_tol", C.c_double),
         ("spin", C.c_double),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
     ]
@@ -66,6 +67,7 @@ class Info(C.Structure):
         ("bounds_ms", C.c_double), ("step_ms", C.c_double), ("project_ms", C.c_double),
         ("output_ms", C.c_double), ("step_launches", C.c_int32), ("tile", C.c_int32),
         ("refine_ms", C.c_double),
+        ("sweep_steps", C.c_int32), ("correction_steps", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -80,7 +82,8 @@ class Info(C.Structure):
             "idem_x": list(self.idem_x[:m + 1]),
             "bounds_ms": self.bounds_ms, "step_ms": self.step_ms, "project_ms": self.project_ms,
             "output_ms": self.output_ms, "step_launches": self.step_launches, "tile": self.tile,
-            "refine_ms": self.refine_ms,
+            "refine_ms": self.refine_ms, "sweep_steps": self.sweep_steps,
+            "correction_steps": self.correction_steps,
         }
 
 

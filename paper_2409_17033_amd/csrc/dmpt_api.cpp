@@ -47,7 +47,7 @@ constexpr int kChunk = 8;   // step launches between host polls of the done flag
 
 struct Opts {
   int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile, ckpt, refine;
-  double emin, emax, idem_tol, spin;
+  double emin, emax, idem_tol, spin, sweep_tol;
   hipStream_t stream;
   char* ws;
   size_t ws_bytes;
@@ -73,6 +73,10 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (o->refine < 0 || o->refine > 2) return fail(DMPT_ERR_ARG, "refine must be 0, 1 or 2");
   if (o->refine && (o->sweep != DMPT_SWEEP_FORWARD || !o->project))
     return fail(DMPT_ERR_ARG, "refine needs the forward sweep with the projection");
+  if (!(std::isfinite(o->sweep_tol) && o->sweep_tol >= 0.0 && o->sweep_tol < 0.25))
+    return fail(DMPT_ERR_ARG, "sweep_tol must be in [0, 1/4)");
+  if (o->sweep_tol > 0.0 && !o->refine)
+    return fail(DMPT_ERR_ARG, "sweep_tol needs refine (the residual correction removes the truncation error)");
   r->n = o->n;
   r->nocc = o->nocc;
   r->prec = o->precision == DMPT_FP32 ? kFP32
@@ -93,6 +97,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   r->emax = o->emax;
   r->idem_tol = o->idem_tol;
   r->spin = o->spin == 0.0 ? 2.0 : o->spin;
+  r->sweep_tol = o->sweep_tol;
   r->stream = (hipStream_t)o->stream;
   r->ws = (char*)o->workspace;
   r->ws_bytes = o->workspace_bytes;
@@ -711,6 +716,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.idem_tol = o.idem_tol;
   a.decide = 1;
   a.unit = sp2_unit(xprec);   // both launches of a split step take the same decision
+  // sweep stop (opts.sweep_tol, with the residual correction only)
+  a.ytol2 = refining && o.sweep_tol > 0.0 ? o.sweep_tol * o.sweep_tol : 0.0;
   a.write_split = 1;
   a.flush = flush_interval(xprec, p.n_pad);
   a.jobs = d_jobs;
@@ -761,6 +768,9 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   st = decide_to_status(hctl.code);
   const int xfin = xslot(m + 1);
   int yfin = (m + 1) & 1;
+  // The sweep stopped at Y_k (opts.sweep_tol): later launches left it in its slot.
+  const int ystop = a.ytol2 > 0.0 && st == DMPT_OK ? hctl.ystop : 0;
+  if (ystop > 0) yfin = ystop & 1;
 
   const int mp0 = prof.mark();
   if (nobs > 0 && st == DMPT_OK && adjoint) {
@@ -844,7 +854,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // operand copy at the scale the step would use (Y_{m+2}'s own: both come
     // from Y_{m+1}) and fresh norm partials for the second step.
     const int sig_next = hctl.rec[m + 1].sigma;
-    const bool reuse_first = !adjoint && pprec == yprec && hctl.code == kDecideStop &&
+    const bool reuse_first = !adjoint && pprec == yprec && hctl.code == kDecideStop && ystop == 0 &&
                              (sig_next == 1 || sig_next == -1);
     int q0 = 0;
     if (reuse_first) {
@@ -864,6 +874,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   }
 
   const int mp1 = prof.mark();
+  int mcorr = 0;   // sweep steps of the residual correction
   if (nobs > 0 && o.refine && st == DMPT_OK) {
     // Residual correction of chi' (opts.refine; Appendix, proof of Eq.
     // Equivalence).  The exact chi' = L o A on the eigenbasis of H solves
@@ -981,12 +992,21 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     MatRef x1 = bx(0);
     x1.op = hist + hstride;
     DMPT_HIP(launch_init(kBF16, p.tile, H, nullptr, o.n, p.n_pad, 0, nullptr, 0, x1, by(1), 0.0, part[1], ctl, s));
-    // the sweep of B: Z-jobs only, X_n from the history, sigma_n as recorded
+    // the sweep of B: Z-jobs only, X_n from the history, sigma_n as recorded;
+    // with opts.sweep_tol it stops after the first X_n within sqrt(sweep_tol)
+    // of idempotency (the correction only needs accuracy relative to itself)
+    mcorr = m;
+    if (o.sweep_tol > 0.0)
+      for (int q = 1; q <= m; ++q)
+        if (hctl.rec[q].eps <= o.sweep_tol) {
+          mcorr = q;
+          break;
+        }
     StepArgs r = b;
     r.sigma_src = ctl->rec;
     r.oscale = 1.0f;
     r.write_split = 1;
-    for (int n = 1; n <= m; ++n) {
+    for (int n = 1; n <= mcorr; ++n) {
       r.step = n;
       r.x_in = x1;
       r.x_in.op = hist + (size_t)n * hstride;
@@ -995,7 +1015,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       DMPT_HIP(run_step(kBF16, r, nzj, wide));
     }
     // projection of delta with D, then Y += P(delta)
-    int yd = (m + 1) & 1;
+    int yd = (mcorr + 1) & 1;
     for (int q = 0; q < 2; ++q) {
       b.fixed_sigma = q == 0 ? 1 : -1;
       b.write_split = q == 0;
@@ -1044,6 +1064,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     info->elapsed_ms = ms;
     info->step_launches = launched;
     info->tile = p.tile;
+    info->sweep_steps = nobs > 0 && !adjoint ? (ystop > 0 ? ystop - 1 : m) : 0;
+    info->correction_steps = mcorr;
     if (prof.on) {
       info->bounds_ms = prof.ms(mb0, mb1);
       double t = 0.0;

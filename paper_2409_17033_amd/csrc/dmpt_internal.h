@@ -71,6 +71,8 @@ struct Ctl {
   int code;        // DecideCode at the stop (0 = converged)
   int m;           // steps taken (M) when done
   int nonfinite;   // an input matrix held NaN/Inf
+  int ystop;       // step k whose Y_k ended the sweep (StepArgs::ytol2; 0: not yet)
+  int pad_;
   double emin, emax, alpha, beta;
   double gmin, gmax;   // Gershgorin bounds
   StepRec rec[DMPT_MAX_STEPS + 3];
@@ -118,6 +120,8 @@ struct StepArgs {
   int max_iter, min_iter;
   double nocc, idem_tol;
   double unit;               // unit roundoff of X_n^2 for the stopping test (the X product precision)
+  double ytol2;              // > 0 (decide == 1): launch k skips its Z-jobs, and every later launch
+                             // too, once ||X_{k-1} - X_{k-1}^2||_F^2 <= ytol2; Y_k is the result
   int decide;                // 1: evaluate the controller on the partials of X_n
   int fixed_sigma;           // used when decide == 0 and sigma_src == nullptr
   const StepRec* sigma_src;  // decide == 0: sigma_n read from sigma_src[step].sigma

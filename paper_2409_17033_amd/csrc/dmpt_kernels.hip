@@ -414,7 +414,7 @@ __device__ __forceinline__ void stage_order() {
 // bounds check of X_k, else sigma_k.  Every workgroup evaluates the same FP64
 // numbers in the same order and reaches the same decision; workgroup 0
 // records it.  Returns sigma_k (+1 / -1) or a stop code.
-__device__ __forceinline__ int step_controller(const StepArgs& a, int* s_code) {
+__device__ __forceinline__ int step_controller(const StepArgs& a, int* s_code, int* s_zskip) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double tr = 0.0, sq = 0.0, eps = 0.0;
@@ -457,6 +457,17 @@ __device__ __forceinline__ int step_controller(const StepArgs& a, int* s_code) {
           }
         }
       }
+      // Sweep stop (ytol2 > 0): the Z-jobs of this launch would form Y_{k+1}
+      // from X_k; once X_{k-1} (the operand of Y_k) is within the tolerance
+      // they are skipped here and in every later launch, and Y_k is the
+      // result.  Every workgroup evaluates the same test on the same eps;
+      // workgroup 0 records k.
+      int zs = 0;
+      if (a.ytol2 > 0.0 && k >= 2 && m < 0) {
+        zs = (c->ystop != 0 || eps <= a.ytol2) ? 1 : 0;
+        if (zs && blockIdx.x == 0 && c->ystop == 0) c->ystop = k;
+      }
+      *s_zskip = zs;
       if (blockIdx.x == 0) {
         c->rec[k].tr = tr;
         c->rec[k].sq = sq;
@@ -1236,6 +1247,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   __shared__ __attribute__((aligned(1024))) char ring2[RSZ];
   __shared__ __attribute__((aligned(1024))) char ring3[RSZ];
   __shared__ int s_code;
+  __shared__ int s_zskip;
   __shared__ int s_job;
   __shared__ double s_red[3 * NW];
   __shared__ double s_nrm;
@@ -1243,10 +1255,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   if (blockIdx.x == 0 && threadIdx.x < kXcdQueues) a.qclear[threadIdx.x * kQStride] = 0u;
   if (a.decide && a.ctl->done) return;
   int sigma;
+  bool zskip = false;
   if (a.decide) {
-    const int code = step_controller(a, &s_code);
+    const int code = step_controller(a, &s_code, &s_zskip);
     if (!(code == 1 || code == -1)) return;
     sigma = code;
+    zskip = s_zskip != 0;
   } else {
     sigma = a.sigma_src ? a.sigma_src[a.step].sigma : a.fixed_sigma;
   }
@@ -1277,6 +1291,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     const int jpos = s_job;
     if (jpos < 0) break;
     const uint32_t job = a.jobs[jpos];
+    if (zskip && (job & 1) == kJobZ) {   // the sweep has stopped (ytol2)
+      __syncthreads();   // every thread has read s_job before thread 0 takes the next ticket
+      continue;
+    }
     LDS_AS char* R0 = (LDS_AS char*)ring0;
     LDS_AS char* R1 = (LDS_AS char*)ring1;
     LDS_AS char* R2 = (LDS_AS char*)ring2;

@@ -36,17 +36,18 @@ def test_exports_every_declared_function(lib):
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 6
+    assert lib.dmpt_abi_version() == 7
 
 
 def test_struct_layouts():
     from paper_2409_17033_amd._lib import Info, Opts
     # sizes follow from the C declarations with natural alignment
-    assert C.sizeof(Opts) == 104
-    assert Opts.spin.offset == 72 and Opts.workspace_bytes.offset == 96
+    assert C.sizeof(Opts) == 112
+    assert Opts.sweep_tol.offset == 72
+    assert Opts.spin.offset == 80 and Opts.workspace_bytes.offset == 104
     assert Opts.ckpt_interval.offset == 64
     assert Info.sigma.offset == 56
-    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4 + 8
+    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4 + 8 + 2 * 4
     assert Info.idem_x.offset == 56 + 256 + 2 * 256 * 8
     assert Opts.profile.offset == 60
 
@@ -92,6 +93,18 @@ def test_checkpoint_workspace(lib):
     plain = _opts(lib, 1000, 500, precision=1)
     ref = _opts(lib, 1000, 500, precision=1, refine=1)
     assert lib.dmpt_workspace_bytes(C.byref(ref), 1) > lib.dmpt_workspace_bytes(C.byref(plain), 1)
+
+
+def test_sweep_tol_validation(lib):
+    """The sweep stop is an option of the residual correction: without it,
+    or outside [0, 1/4), the options are refused before any device work."""
+    ok = _opts(lib, 1000, 500, precision=4, refine=1, sweep_tol=1e-4)
+    assert lib.dmpt_workspace_bytes(C.byref(ok), 1) > 0
+    for tol, refine in ((1e-4, 0), (-1e-4, 1), (0.25, 1), (float("nan"), 1), (float("inf"), 1)):
+        bad = _opts(lib, 1000, 500, precision=4, refine=refine, sweep_tol=tol)
+        assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0, (tol, refine)
+        assert lib.dmpt_susceptibility(FAKE, FAKE, 1, FAKE, None, None, C.byref(bad), None) == 1
+        assert b"sweep_tol" in lib.dmpt_last_error()
 
 
 def test_workspace_bytes(lib):

@@ -124,6 +124,34 @@ def test_refined_matches_closed_form(gpu, case, prec):
     assert abs(np.trace(c)) <= 1e-4 * np.linalg.norm(c) * np.sqrt(wl.n)
 
 
+@pytest.mark.parametrize("case", ["dense300", "band1000"])
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16", "split3x_bf16"])
+def test_sweep_tol_matches_closed_form(gpu, case, prec):
+    """opts.sweep_tol with the residual correction: the sweep stops once X_n
+    is within 1e-3 of idempotency and the correction's sweep within
+    sqrt(1e-3); the correction removes the truncation error, so chi is held
+    to the same 1e-5 as the full sweeps, and both sweeps must actually have
+    stopped early."""
+    dm = _dm()
+    wl = _case(case)
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    chi, D, a0, info = dm.susceptibility(H, A, wl.nocc, precision=prec, refine=True, sweep_tol=1e-3)
+    h, a = wl.H.astype(np.float64), wl.A[0].astype(np.float64)
+    chiref = cf.susceptibility(h, a, wl.nocc, spin=2.0)
+    ec = cf.rel_frobenius(_np(chi), chiref)
+    ed = cf.rel_frobenius(_np(D), cf.density_matrix(h, wl.nocc))
+    m = info["m"]
+    print(f"{case} {prec} sweep_tol 1e-3: M={m} sweep {info['sweep_steps']} correction "
+          f"{info['correction_steps']} errD={ed:.2e} errchi={ec:.2e}")
+    assert ec <= 1e-5 and ed <= 1e-5
+    assert info["sweep_steps"] < m and info["correction_steps"] < m
+    eps = info["idem_x"]
+    # the sweep kept Y_k for the first X_{k-1} within the tolerance
+    k = info["sweep_steps"] + 1
+    assert eps[k - 2] <= 1e-6 and all(e > 1e-6 for e in eps[:k - 2])
+    assert eps[info["correction_steps"] - 1] <= 1e-3
+
+
 def test_refine_two_observables(gpu):
     """The correction runs every observable through one BF16 sweep: each must
     match its own closed form, and the batch must equal the single runs."""
