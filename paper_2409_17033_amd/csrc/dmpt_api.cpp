@@ -1184,7 +1184,7 @@ struct NonorthWS {
   size_t run, zp, ztp, tp, up, hperp, dperp, aperp, cperp, total;
 };
 
-NonorthWS nonorth_ws(size_t run_bytes, int n, int n_pad, int nobs) {
+static NonorthWS nonorth_ws(size_t run_bytes, int n, int n_pad, int nobs) {
   NonorthWS w;
   const size_t pad2 = (size_t)n_pad * n_pad * 4, n2 = (size_t)n * n * 4;
   size_t off = align_up(run_bytes);
@@ -1201,7 +1201,7 @@ NonorthWS nonorth_ws(size_t run_bytes, int n, int n_pad, int nobs) {
   return w;
 }
 
-dmpt_status nonorth_check(const dmpt_opts* opts, int nobs, Opts* o, Plan* p) {
+static dmpt_status nonorth_check(const dmpt_opts* opts, int nobs, Opts* o, Plan* p) {
   dmpt_status st = normalise(opts, o);
   if (st != DMPT_OK) return st;
   if (nobs < 1 || nobs > kMaxObs) return fail(DMPT_ERR_ARG, "nobs = %d out of range [1, %d]", nobs, kMaxObs);
@@ -1288,11 +1288,11 @@ struct FermiWS {
 
 // Operand copy format of the finite-temperature products: none (FP32
 // masters), the scaled FP16 split, or the two- / three-term BF16 split.
-int fermi_copy_prec(int prec) {
+static int fermi_copy_prec(int prec) {
   return prec == kSplitH ? kSplitH : prec == kSplit3 ? kSplit3 : prec == kSplit2 ? kSplit2 : kFP32;
 }
 
-FermiWS fermi_ws(size_t base, int n_pad, int nobs, int cprec) {
+static FermiWS fermi_ws(size_t base, int n_pad, int nobs, int cprec) {
   FermiWS w;
   const size_t m = (size_t)n_pad * n_pad * 4;
   const size_t mc = cprec == kFP32 ? 0 : (size_t)n_pad * n_pad * operand_bytes(cprec);   // operand copy
@@ -1322,7 +1322,7 @@ FermiWS fermi_ws(size_t base, int n_pad, int nobs, int cprec) {
   return w;
 }
 
-dmpt_status fermi_check(const dmpt_opts* opts, const dmpt_fermi_opts* f, int nobs, Opts* o, Plan* p) {
+static dmpt_status fermi_check(const dmpt_opts* opts, const dmpt_fermi_opts* f, int nobs, Opts* o, Plan* p) {
   dmpt_status st = normalise(opts, o);
   if (st != DMPT_OK) return st;
   if (!f) return fail(DMPT_ERR_ARG, "fermi options are NULL");
@@ -1627,13 +1627,13 @@ struct MixWS {
   size_t scratch, part, grad, loss, total;
 };
 
-bool mixer_sizes_ok(int n, int w, int h, int batch) {
+static bool mixer_sizes_ok(int n, int w, int h, int batch) {
   return n >= 1 && n <= 65536 && w >= 0 && w <= 512 && h >= 1 && h <= 4096 && batch >= 1 &&
          (size_t)batch * n <= ((size_t)1 << 20) &&
          (size_t)batch * n * (mixer_features(w) + 2 * h) <= ((size_t)1 << 31);
 }
 
-MixWS mixer_ws(int n, int w, int h, int batch) {
+static MixWS mixer_ws(int n, int w, int h, int batch) {
   MixWS m;
   size_t off = 0;
   m.scratch = off; off = align_up(off + mixer_scratch_floats(n, w, h, batch) * 4);
@@ -1644,7 +1644,7 @@ MixWS mixer_ws(int n, int w, int h, int batch) {
   return m;
 }
 
-dmpt_status mixer_check(int n, int w, int h, int batch, void* ws, size_t wsb, MixWS* m) {
+static dmpt_status mixer_check(int n, int w, int h, int batch, void* ws, size_t wsb, MixWS* m) {
   if (!mixer_sizes_ok(n, w, h, batch))
     return fail(DMPT_ERR_ARG, "mixer sizes out of range (n %d, window %d, hidden %d, batch %d)", n, w, h, batch);
   *m = mixer_ws(n, w, h, batch);
@@ -1661,14 +1661,14 @@ struct ScfWS {
 };
 
 // History depth and hidden width the mixer uses (0 when it uses none).
-int scf_depth(const dmpt_scf_opts* scf) {
+static int scf_depth(const dmpt_scf_opts* scf) {
   return scf->mixer == DMPT_MIX_ANDERSON || scf->mixer == DMPT_MIX_LEARNED_ANDERSON ? scf->anderson_depth : 0;
 }
-int scf_hidden(const dmpt_scf_opts* scf) {
+static int scf_hidden(const dmpt_scf_opts* scf) {
   return scf->mixer == DMPT_MIX_LEARNED || scf->mixer == DMPT_MIX_LEARNED_ANDERSON ? scf->mlp_hidden : 0;
 }
 
-ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
+static ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
   ScfWS w;
   size_t off = align_up(run_bytes);
   const size_t mat = align_up((size_t)n * n * 4), vec = align_up((size_t)n * 8);
@@ -1699,7 +1699,7 @@ ScfWS scf_ws(size_t run_bytes, int n, int depth, int window, int hidden) {
   return w;
 }
 
-dmpt_status scf_check(const dmpt_opts* opts, const dmpt_scf_opts* scf, Opts* o, dmpt_opts* o2, size_t* run_bytes) {
+static dmpt_status scf_check(const dmpt_opts* opts, const dmpt_scf_opts* scf, Opts* o, dmpt_opts* o2, size_t* run_bytes) {
   dmpt_status st = normalise(opts, o);
   if (st != DMPT_OK) return st;
   if (!scf) return fail(DMPT_ERR_ARG, "scf options are NULL");
@@ -1731,7 +1731,7 @@ dmpt_status scf_check(const dmpt_opts* opts, const dmpt_scf_opts* scf, Opts* o, 
 
 // Solve the k x k system (g + lambda I) x = b by Gaussian elimination with
 // partial pivoting (k <= 16).
-void small_solve(std::vector<double> g, std::vector<double> b, int k, std::vector<double>* x) {
+static void small_solve(std::vector<double> g, std::vector<double> b, int k, std::vector<double>* x) {
   double tr = 0.0;
   for (int i = 0; i < k; ++i) tr += g[i * k + i];
   const double lambda = 1e-12 * (tr > 0 ? tr / k : 1.0);

@@ -35,6 +35,21 @@ def test_exports_every_declared_function(lib):
     assert not missing, missing
 
 
+def test_no_undeclared_c_exports():
+    """Every unmangled (C) symbol the library exports is a declared entry
+    point: the runtime's helpers have internal linkage."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    syms = [line.split()[-1] for line in out.splitlines() if line.split()[-2:-1] and line.split()[-2] in "TtWw"]
+    c_syms = [x for x in syms if not x.startswith("_Z")]
+    declared = set(declared_functions())
+    assert c_syms and not [x for x in c_syms if x not in declared], [x for x in c_syms if x not in declared]
+
+
 def test_abi_version(lib):
     assert lib.dmpt_abi_version() == 7
 
