@@ -19,19 +19,19 @@ def test_more_than_one_gpu_exits_with_message():
 def test_traffic_figure_follows_the_kernel_sources(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    committed = bench.measured_traffic("split_fp16", 8192)
+    committed = bench.measured_traffic("split3x_bf16", 8192)
     assert committed is None or committed > 0
     # a copy of the tree whose kernel source differs: the figure is not used
     (tmp_path / "profiles").mkdir()
-    src = os.path.join(ROOT, "profiles", "k_step_split_fp16_n8192_traffic.md")
+    src = os.path.join(ROOT, "profiles", "k_step_split3x_bf16_n8192_traffic.md")
     if os.path.exists(src):
-        (tmp_path / "profiles" / "k_step_split_fp16_n8192_traffic.md").write_text(open(src).read())
+        (tmp_path / "profiles" / "k_step_split3x_bf16_n8192_traffic.md").write_text(open(src).read())
     csrc = tmp_path / "paper_2409_17033_amd" / "csrc"
     csrc.mkdir(parents=True)
     (csrc / "dmpt_kernels.hip").write_text("// changed\n")
     (csrc / "dmpt_internal.h").write_text("// changed\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("split_fp16", 8192) is None
+    assert bench.measured_traffic("split3x_bf16", 8192) is None
     assert bench.measured_traffic("no_such_precision", 8192) is None
 
 
