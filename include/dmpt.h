@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define DMPT_ABI_VERSION 7
+#define DMPT_ABI_VERSION 8
 #define DMPT_MAX_STEPS 255
 
 typedef enum dmpt_status {
@@ -168,6 +168,9 @@ typedef struct dmpt_info {
   double refine_ms;                     /* residual correction (opts.refine), when profiled */
   int32_t sweep_steps;                  /* sweep steps applied to the returned Y (m without sweep_tol) */
   int32_t correction_steps;             /* sweep steps of the residual correction (0 without refine) */
+  int32_t split_tiles;                  /* tiles per step launch run as two half-K jobs and combined
+                                           (the tail of the 256 x 256-tile lists of refined runs) */
+  int32_t split_tiles_sweep;            /* the same for the projection and correction launches */
 } dmpt_info;
 
 /* ABI version compiled into the library (DMPT_ABI_VERSION). */

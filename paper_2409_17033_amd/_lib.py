@@ -23,7 +23,7 @@ STATUS = {
     7: "DMPT_ERR_UNSUPPORTED",
 }
 
-ABI_VERSION = 7   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
+ABI_VERSION = 8   # DMPT_ABI_VERSION of include/dmpt.h this binding is written against
 PRECISION = {"fp32": 0, "split_bf16": 1, "split3_bf16": 2, "bf16": 3, "split3x_bf16": 4, "split_fp16": 5}
 BOUNDS = {"lanczos": 0, "gershgorin": 1, "given": 2}
 SWEEP = {"forward": 0, "adjoint": 1}
@@ -68,6 +68,7 @@ class Info(C.Structure):
         ("output_ms", C.c_double), ("step_launches", C.c_int32), ("tile", C.c_int32),
         ("refine_ms", C.c_double),
         ("sweep_steps", C.c_int32), ("correction_steps", C.c_int32),
+        ("split_tiles", C.c_int32), ("split_tiles_sweep", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -83,7 +84,8 @@ class Info(C.Structure):
             "bounds_ms": self.bounds_ms, "step_ms": self.step_ms, "project_ms": self.project_ms,
             "output_ms": self.output_ms, "step_launches": self.step_launches, "tile": self.tile,
             "refine_ms": self.refine_ms, "sweep_steps": self.sweep_steps,
-            "correction_steps": self.correction_steps,
+            "correction_steps": self.correction_steps, "split_tiles": self.split_tiles,
+            "split_tiles_sweep": self.split_tiles_sweep,
         }
 
 

@@ -8,7 +8,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <queue>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -44,6 +47,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 constexpr int kOutBlocks = 1024;
 constexpr int kChunk = 8;   // step launches between host polls of the done flag
+constexpr int kMaxSplit = 256;   // K-split tail tiles per job list at most
 
 struct Opts {
   int n, nocc, prec, bounds, lanczos_steps, max_iter, min_iter, sweep, project, profile, ckpt, refine;
@@ -119,6 +123,10 @@ struct Plan {
   int rprec;
   size_t rf_copy_bytes, rf_bslot_bytes;
   size_t off_rf_copy, off_rf_v, off_rf_r, off_rf_hist, off_rf_x, off_rf_y, off_rf_norm;
+  // K-split tail tiles of the step and sweep lists (runs with the residual
+  // correction): list-position -> slot tables, the combine lists and the
+  // scratch of partial tile sums
+  size_t off_split_slot, off_split_slot_proj, off_cjobs, off_cjobs_proj, off_split_buf;
   size_t total;
   int njobs_max, njobs_proj_max, lz_steps;
 };
@@ -167,8 +175,8 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
   p->mat_meta = meta_bytes(std::max(p->nb64 * p->nb64, p->nparts_step));
   p->lz_steps = o.lanczos_steps;
   const int ut = p->nparts_step;                       // step tiles covering the upper triangle
-  p->njobs_max = ut * (1 + std::max(nobs, 0));
-  p->njobs_proj_max = ut * std::max(nobs, 1);
+  p->njobs_max = ut * (1 + std::max(nobs, 0)) + kMaxSplit;
+  p->njobs_proj_max = ut * std::max(nobs, 1) + kMaxSplit;
   size_t off = 0;
   p->off_ctl = off; off = align_up(off + sizeof(Ctl));
   const size_t part_bytes = (size_t)p->nb64 * p->nb64 * sizeof(Part);
@@ -197,6 +205,11 @@ void make_plan(const Opts& o, int nobs, Plan* p) {
     p->off_rf_x = off; off = align_up(off + p->rf_bslot_bytes);
     p->off_rf_y = off; off = align_up(off + p->rf_bslot_bytes * 2 * k);
     p->off_rf_norm = off; off = align_up(off + sizeof(double) * kNormBlocks * (2 + 2 * (size_t)k));
+    p->off_split_slot = off; off = align_up(off + (size_t)p->njobs_max * 4);
+    p->off_split_slot_proj = off; off = align_up(off + (size_t)p->njobs_proj_max * 4);
+    p->off_cjobs = off; off = align_up(off + (size_t)kMaxSplit * 4);
+    p->off_cjobs_proj = off; off = align_up(off + (size_t)kMaxSplit * 4);
+    p->off_split_buf = off; off = align_up(off + (size_t)kMaxSplit * 2 * kSplitTileFloats * sizeof(float));
   }
   p->total = off;
 }
@@ -330,6 +343,10 @@ std::vector<uint32_t> build_jobs(int n_pad, int nobs_z, bool with_p) {
 // tile takes 1.6 - 1.7 times a regular one, and a P-job of the three-term
 // split about as long as a regular Z-job.
 constexpr double kWideCost = 1.65;
+// K-split tail: the last regular tiles of a list run as two half-K jobs (cost
+// in regular-tile units, with the partial-sum store) and a combine launch
+// adds the halves and runs their epilogue (a fixed cost per launch).
+constexpr double kHalfCost = 0.53, kCombineCost = 0.08;
 
 std::vector<uint32_t> wide_group(const std::vector<std::pair<int, int>>& g, int obs) {
   std::vector<uint32_t> w;
@@ -356,17 +373,43 @@ double list_makespan(const std::vector<double>& costs, int cus) {
   return end;
 }
 
-// Z-jobs of nobs observables, followed in the launch by np_tail P-jobs (one
-// regular unit each; they are not part of the returned list): the leading
-// groups are wide and the rest regular, the split chosen to minimise the
-// launch's makespan on `cus` workgroups (whole rounds of wide tiles, then
-// regular tiles to even out the last round).
-std::vector<uint32_t> build_zjobs_wide(int n_pad, int nobs, int np_tail, int cus) {
+// Best K-split tail for a list of job costs: the last k regular tiles (k a
+// multiple of 8, at most kMaxSplit, only from the trailing run of regular
+// tiles) become 2k half-K jobs, plus the combine launch; returns the modelled
+// makespan and k (0: no split).
+std::pair<double, int> best_split(const std::vector<double>& base, int cus) {
+  int trailing = 0;
+  for (size_t q = base.size(); q > 0 && base[q - 1] == 1.0; --q) ++trailing;
+  std::pair<double, int> best(list_makespan(base, cus), 0);
+  std::vector<double> c;
+  for (int k = 8; k <= std::min(kMaxSplit, trailing); k += 8) {
+    c.assign(base.begin(), base.end() - k);
+    c.insert(c.end(), (size_t)(2 * k), kHalfCost);
+    const double t = list_makespan(c, cus) + kCombineCost;
+    if (t < best.first - 1e-9) best = {t, k};
+  }
+  return best;
+}
+
+// A step-launch list on 256 x 256 sweep tiles: the Z-jobs of nobs
+// observables (leading groups wide, the rest regular), then, with with_p, the
+// P-jobs (regular), then the K-split tail (see kJobSplit): the last k regular
+// tiles as pairs of half-K jobs with their scratch slots (slots: the slot of
+// every list position; cjobs: the tile of each slot).  The number of wide
+// groups and k together minimise the launch's modelled makespan on `cus`
+// workgroups.
+struct JobList {
+  std::vector<uint32_t> jobs, slots, cjobs;
+};
+
+JobList build_wide_list(int n_pad, int nobs, bool with_p, int cus) {
   const auto groups = tile_groups(n_pad);
+  const std::vector<uint32_t> pj = with_p ? build_jobs(n_pad, 0, true) : std::vector<uint32_t>();
   std::vector<std::pair<int, size_t>> order;   // (obs, group)
   for (int k = 0; k < nobs; ++k)
     for (size_t g = 0; g < groups.size(); ++g) order.emplace_back(k, g);
   size_t best_w = 0;
+  int best_k = 0;
   {
     double best = 0.0;
     std::vector<size_t> cand;   // many observables: a coarse search
@@ -378,12 +421,12 @@ std::vector<uint32_t> build_zjobs_wide(int n_pad, int nobs, int np_tail, int cus
       for (size_t q = 0; q < nw; ++q)
         c.insert(c.end(), (groups[order[q].second].size() + 1) / 2, kWideCost);
       for (size_t q = nw; q < order.size(); ++q) c.insert(c.end(), groups[order[q].second].size(), 1.0);
-      c.insert(c.end(), (size_t)np_tail, 1.0);
-      const double t = list_makespan(c, cus);
-      if (nw == 0 || t < best - 1e-9) { best = t; best_w = nw; }
+      c.insert(c.end(), pj.size(), 1.0);
+      const auto t = best_split(c, cus);
+      if (nw == 0 || t.first < best - 1e-9) { best = t.first; best_w = nw; best_k = t.second; }
     }
   }
-  std::vector<uint32_t> out;
+  JobList L;
   std::vector<std::vector<uint32_t>> wg, rg;
   for (size_t q = 0; q < order.size(); ++q) {
     const auto& g = groups[order[q].second];
@@ -395,9 +438,33 @@ std::vector<uint32_t> build_zjobs_wide(int n_pad, int nobs, int np_tail, int cus
       rg.push_back(std::move(r));
     }
   }
-  append_xcd_ordered(out, wg);
-  append_xcd_ordered(out, rg);
-  return out;
+  append_xcd_ordered(L.jobs, wg);
+  append_xcd_ordered(L.jobs, rg);
+  L.jobs.insert(L.jobs.end(), pj.begin(), pj.end());
+  // the tail: the last best_k regular tiles, re-appended as half pairs
+  std::vector<uint32_t> tail(L.jobs.end() - best_k, L.jobs.end());
+  L.jobs.resize(L.jobs.size() - best_k);
+  L.slots.assign(L.jobs.size() + 2 * (size_t)best_k, 0u);
+  for (int i = 0; i < best_k; ++i) {
+    L.cjobs.push_back(tail[i]);
+    L.slots[L.jobs.size()] = (uint32_t)i;
+    L.jobs.push_back(tail[i] | kJobSplit);
+    L.slots[L.jobs.size()] = (uint32_t)i;
+    L.jobs.push_back(tail[i] | kJobSplit | kJobHalf1);
+  }
+  return L;
+}
+
+// The lists depend only on the shape; the search runs once per shape and
+// process (the modelled makespans take milliseconds of host time).
+const JobList& cached_wide_list(int n_pad, int nobs, bool with_p, int cus) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, bool, int>, JobList> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(n_pad, nobs, with_p, cus);
+  auto it = cache.find(key);
+  if (it == cache.end()) it = cache.emplace(key, build_wide_list(n_pad, nobs, with_p, cus)).first;
+  return it->second;
 }
 
 // ---------------------------------------------------------------- Lanczos (host part)
@@ -642,11 +709,16 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   const int cus = persistent_grid(1 << 30);
   // job tables: [Z-jobs][P-jobs] (one combined table when the step is one launch)
   std::vector<uint32_t> jobs;
-  int njobs_z = 0;
-  if (split_launch) {
+  // K-split tail tiles (runs on the wide lists): slot tables and combine lists
+  std::vector<uint32_t> slots_main, cjobs_main;
+  if (split_launch && wide) {
+    const JobList& L = cached_wide_list(p.n_pad, nobs, true, cus);
+    jobs = L.jobs;
+    slots_main = L.slots;
+    cjobs_main = L.cjobs;
+  } else if (split_launch) {
     const std::vector<uint32_t> pj = build_jobs(p.n_pad, 0, true);
-    jobs = wide ? build_zjobs_wide(p.n_pad, nobs, (int)pj.size(), cus) : build_jobs(p.n_pad, nobs, false);
-    njobs_z = (int)jobs.size();
+    jobs = build_jobs(p.n_pad, nobs, false);
     jobs.insert(jobs.end(), pj.begin(), pj.end());
   } else {
     jobs = build_jobs(p.n_pad, adjoint ? 0 : nobs, true);
@@ -654,6 +726,17 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   uint32_t* d_jobs = (uint32_t*)(ws + p.off_jobs);
   DMPT_HIP(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * 4, hipMemcpyHostToDevice, s));
   const int njobs_main = (int)jobs.size();
+  uint32_t* d_slots_main = wide ? (uint32_t*)(ws + p.off_split_slot) : nullptr;
+  uint32_t* d_cjobs_main = wide ? (uint32_t*)(ws + p.off_cjobs) : nullptr;
+  float* d_split_buf = wide ? (float*)(ws + p.off_split_buf) : nullptr;
+  if (!cjobs_main.empty()) {
+    DMPT_HIP(hipMemcpyAsync(d_slots_main, slots_main.data(), slots_main.size() * 4, hipMemcpyHostToDevice, s));
+    DMPT_HIP(hipMemcpyAsync(d_cjobs_main, cjobs_main.data(), cjobs_main.size() * 4, hipMemcpyHostToDevice, s));
+  }
+  // a step launch, then the combine launch of its K-split tiles
+  auto combine = [&](int prec_, const StepArgs& args, const uint32_t* cj, size_t nc) {
+    return nc ? launch_step_combine(prec_, args, cj, (int)nc, s) : hipSuccess;
+  };
 
   Profiler prof;
   prof.on = o.profile != 0;
@@ -722,6 +805,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   a.flush = flush_interval(xprec, p.n_pad);
   a.jobs = d_jobs;
   a.ctl = ctl;
+  a.split_slot = d_slots_main;
+  a.split_buf = d_split_buf;
   if (refining) {   // every X_{n+1} also as plain BF16 for the correction sweep
     a.hist = ws + p.off_rf_hist;
     a.hist_stride = (size_t)p.n_pad * p.n_pad * 2;
@@ -750,6 +835,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
         a.flush = flush_interval(xprec, p.n_pad);
         a.flush_z = flush_interval(yprec, p.n_pad);
         DMPT_HIP(run_step(kSplit32, a, njobs_main, wide));
+        DMPT_HIP(combine(kSplit32, a, d_cjobs_main, cjobs_main.size()));
       } else {
         a.jobs = step_jobs;
         DMPT_HIP(run_step(xlaunch, a, njobs_step));
@@ -818,6 +904,10 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
   }
 
   int njobs_proj = 0;
+  // the projection's list (also the correction's) and its K-split tail
+  std::vector<uint32_t> slots_proj, cjobs_proj;
+  uint32_t* d_slots_proj = wide ? (uint32_t*)(ws + p.off_split_slot_proj) : nullptr;
+  uint32_t* d_cjobs_proj = wide ? (uint32_t*)(ws + p.off_cjobs_proj) : nullptr;
   if (nobs > 0 && o.project && st == DMPT_OK) {
     // Occupied-virtual projection: two sweep steps with X frozen at D
     // (sigma = +1 then -1) multiply the eigenbasis blocks of Y by
@@ -826,10 +916,21 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // on the operand copies of D and Y the last step wrote.
     const int pprec = p.prec == kBF16 ? kFP32 : yprec;
     // (the list also serves the launches of the residual correction)
-    const std::vector<uint32_t> pjobs =
-        wide ? build_zjobs_wide(p.n_pad, nobs, 0, cus) : build_jobs(p.n_pad, nobs, false);
+    std::vector<uint32_t> pjobs;
+    if (wide) {
+      const JobList& L = cached_wide_list(p.n_pad, nobs, false, cus);
+      pjobs = L.jobs;
+      slots_proj = L.slots;
+      cjobs_proj = L.cjobs;
+    } else {
+      pjobs = build_jobs(p.n_pad, nobs, false);
+    }
     uint32_t* d_pjobs = (uint32_t*)(ws + p.off_jobs_proj);
     DMPT_HIP(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * 4, hipMemcpyHostToDevice, s));
+    if (!cjobs_proj.empty()) {
+      DMPT_HIP(hipMemcpyAsync(d_slots_proj, slots_proj.data(), slots_proj.size() * 4, hipMemcpyHostToDevice, s));
+      DMPT_HIP(hipMemcpyAsync(d_cjobs_proj, cjobs_proj.data(), cjobs_proj.size() * 4, hipMemcpyHostToDevice, s));
+    }
     njobs_proj = (int)pjobs.size();
     StepArgs b;
     std::memset(&b, 0, sizeof(b));
@@ -840,6 +941,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.flush = flush_interval(pprec, p.n_pad);
     b.jobs = d_pjobs;
     b.ctl = ctl;
+    b.split_slot = d_slots_proj;
+    b.split_buf = d_split_buf;
     auto view = [&](MatRef m) { return pprec == kFP32 ? as_fp32(m) : m; };
     b.x_in = pprec == kFP32 ? as_fp32(x_ref(p, ws, xfin)) : sweep_x(x_ref(p, ws, xfin));
     // The launch after the last step (it ran before the stop was seen, since
@@ -869,6 +972,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.y_in = view(y_ref(p, ws, yfin));
       b.y_out = view(y_ref(p, ws, yfin ^ 1));
       DMPT_HIP(run_step(pprec, b, (int)pjobs.size(), wide));
+      DMPT_HIP(combine(pprec, b, d_cjobs_proj, cjobs_proj.size()));
       yfin ^= 1;
     }
   }
@@ -983,11 +1087,14 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.fixed_sigma = 1;
     b.write_split = 1;
     b.jobs = d_pjobs;
+    b.split_slot = d_slots_proj;
+    b.split_buf = d_split_buf;
     b.x_in = dref;
     b.y_in = rref;
     b.y_out = by(1);
     b.oscale = (float)(-hctl.beta);
     DMPT_HIP(run_step(kBF16, b, nzj, wide));
+    DMPT_HIP(combine(kBF16, b, d_cjobs_proj, cjobs_proj.size()));
     // X_1 = alpha I + beta H in plain BF16 (its copy lands in history slot 1)
     MatRef x1 = bx(0);
     x1.op = hist + hstride;
@@ -1013,6 +1120,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       r.y_in = by(n & 1);
       r.y_out = by((n + 1) & 1);
       DMPT_HIP(run_step(kBF16, r, nzj, wide));
+      DMPT_HIP(combine(kBF16, r, d_cjobs_proj, cjobs_proj.size()));
     }
     // projection of delta with D, then Y += P(delta)
     int yd = (mcorr + 1) & 1;
@@ -1023,6 +1131,7 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.y_in = by(yd);
       b.y_out = by(yd ^ 1);
       DMPT_HIP(run_step(kBF16, b, nzj, wide));
+      DMPT_HIP(combine(kBF16, b, d_cjobs_proj, cjobs_proj.size()));
       yd ^= 1;
     }
     const MatRef dl = by(yd);
@@ -1066,6 +1175,8 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     info->tile = p.tile;
     info->sweep_steps = nobs > 0 && !adjoint ? (ystop > 0 ? ystop - 1 : m) : 0;
     info->correction_steps = mcorr;
+    info->split_tiles = (int32_t)cjobs_main.size();
+    info->split_tiles_sweep = (int32_t)cjobs_proj.size();
     if (prof.on) {
       info->bounds_ms = prof.ms(mb0, mb1);
       double t = 0.0;

@@ -84,12 +84,23 @@ struct Ctl {
 // observable `obs` (kind 1).
 enum JobKind : uint32_t { kJobP = 0, kJobZ = 1 };
 
+// Bits: 0 kind, 1-6 observable, 7 wide / second half, 8-19 tile row block,
+// 20-30 tile column block, 31 split.
 inline uint32_t job_pack(uint32_t kind, uint32_t obs, uint32_t ti, uint32_t tj) {
   return kind | (obs << 1) | (ti << 8) | (tj << 20);
 }
 // Bit 7 of a Z-job (obs < 64 uses bits 1-6): a wide job, one 256 x 256 tile
 // (I, J >= I) of Z with tj counting 256-column blocks.
 constexpr uint32_t kJobWide = 1u << 7;
+// Bit 31: a K-split job of a regular tile, one of two that each run half of
+// the tile's pipeline stages (a Z-job's two products, or the first and second
+// half of a P-job's K range) and store the partial tile sum in slot
+// split_slot[list position] of the split scratch; bit 7 marks the second
+// half.  A combine launch (launch_step_combine) adds the two halves and runs
+// the tile's epilogue before the next launch reads the outputs.
+constexpr uint32_t kJobSplit = 1u << 31;
+constexpr uint32_t kJobHalf1 = 1u << 7;
+constexpr int kSplitTileFloats = 256 * 128;   // one partial tile sum
 
 // Per-matrix metadata next to each operand copy: the scale exponent of the
 // FP16 copy (kSplitH) and FP64 partials of ||M||_F^2 written by the producer
@@ -143,6 +154,8 @@ struct StepArgs {
   Part* part_out;
   int nparts;
   Ctl* ctl;
+  const uint32_t* split_slot; // kJobSplit jobs: scratch slot of list position p (split_slot[p])
+  float* split_buf;           // scratch: slot q, half h at split_buf + (2 q + h) kSplitTileFloats
 };
 
 // Launchers (dmpt_kernels.hip).  All return hipError_t of the launch.
@@ -171,6 +184,11 @@ inline void step_queue_sets(Ctl* ctl, unsigned seq, StepArgs* a) {
   a->qclear = ctl->qhead[(seq + 2) % kQSets];
 }
 hipError_t launch_queue_reset(Ctl* ctl, hipStream_t s);
+// After a step launch whose list holds K-split jobs: one workgroup per split
+// tile (cjobs[q], slot q) adds the two partial sums and runs the tile's
+// epilogue with the launch's sigma (nothing when that launch stopped, or for
+// Z tiles once the sweep has stopped).  prec as for launch_step with wide.
+hipError_t launch_step_combine(int prec, StepArgs args, const uint32_t* cjobs, int ncomb, hipStream_t s);
 // Step tiles are 256 rows x 128 columns; tile (I, J) with J >= 2I covers the
 // upper triangle.  ntile in StepArgs is the number of 128-column blocks.
 constexpr int kStepTM = 256, kStepTN = 128;

@@ -523,221 +523,28 @@ __device__ __forceinline__ int tile_index(int ti, int tj, int tcols) {
   return ti * tcols - ti * (ti - 1) + (tj - 2 * ti);
 }
 
-// One job of the step kernel (one output tile of P = X_n^2 or of
-// Z = Y_n X_n + X_n Y_n) in operand format PREC: DMA + MFMA main loop and the
-// fused epilogue.  R0..R3: the LDS ring (each slot also holds two waves'
-// epilogue staging); s_red, s_nrm: workgroup scratch.
-// MIX: a job of the mixed launch of the three-term-X^2 option: its P-jobs
-// (kSplit3) also write the two-term copy of their output, its Z-jobs
-// (kSplit2) read X's two-term copy and take their own flush interval.
-template <int PREC, bool MIX = false>
-__device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, const int sigma, LDS_AS char* R0,
-                                         LDS_AS char* R1, LDS_AS char* R2, LDS_AS char* R3, double* s_red,
-                                         double* s_nrm) {
-  using P = Pipe<PREC>;
+// Epilogue of one regular tile (256 x 128) of P = X_n^2 or Z = Y_n X_n + X_n Y_n
+// from the tile sums `tot` (MFMA accumulator layout): sigma-update, direct and
+// mirror stores, operand copies, and for P-jobs the FP64 partials of
+// Tr X_{n+1}, ||X_{n+1}||_F^2 and ||X_n - X_n^2||_F^2.  R0..R3: LDS areas of at
+// least two 64 x 65 FP32 staging blocks each; sc_out / s_out: the scale of the
+// FP16 copy (kSplitH).
+template <int PREC, bool MIX>
+__device__ __forceinline__ void step_epilogue(const StepArgs& a, const uint32_t job, const int sigma,
+                                              f32x16 (&tot)[BR][BC], LDS_AS char* R0, LDS_AS char* R1,
+                                              LDS_AS char* R2, LDS_AS char* R3, double* s_red, const float sc_out,
+                                              const int s_out) {
   const int kind = job & 1;
   const int obs = (job >> 1) & 63;
   const int ti = (job >> 8) & 4095;    // 256-row block
-  const int tj = (job >> 20) & 4095;   // 128-column block
-  constexpr int opb = operand_bytes(PREC);
-  const size_t ldb = (size_t)a.n_pad * opb;
-  const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
-  const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
-
-  // X operand: the two-term copy for the Z-jobs of the mixed launch (op2),
-  // the copy in this job's format otherwise
-  const char* xop = (const char*)(MIX && kind == kJobZ ? a.x_in.op2 : a.x_in.op);
-  const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
-  // row block I / J starts at the same byte offset in both layouts:
-  // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
-  const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
-  const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
-  const char* b0 = xop + rowJ;
-  const char* a1 = xop + rowI;
-  const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
-
-  // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
-  // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
-  // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
-  // exponent bounded from ||Y_n||_F.
-  float usc = 1.0f, sc_out = 1.0f;
-  int s_out = 0;
-  if constexpr (PREC == kSplitH) {
-    if (kind == kJobZ) {
-      const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
-      usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
-      const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
-      s_out = yscale_exp(meta_norm(mi, nb * nb, s_nrm), kYBound);
-    } else {
-      usc = ldexpf(1.0f, -2 * kXScaleExp);
-      s_out = kXScaleExp;
-    }
-    sc_out = ldexpf(1.0f, s_out);
-  }
-
-  // The thread index is made opaque per job so that the compiler keeps the
-  // lane-dependent address arithmetic inside the job (hoisted out of the
-  // job loop it would stay live through the main loop and spill).
+  const int tj = (job >> 20) & 2047;   // 128-column block
   unsigned int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
   const int h = lane >> 5, l32 = lane & 31;
-  const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
-
-  f32x16 acc[BR][BC], tot[BR][BC];
-#pragma unroll
-  for (int i = 0; i < BR; ++i)
-#pragma unroll
-    for (int j = 0; j < BC; ++j) acc[i][j] = f32x16{0};
-
-  // The stages of the job's K stream are fetched in order, each call of dma
-  // the next one: cA / cB address stage cs of the A / B panel (tiled: its
-  // chunk, which advances by one chunk per stage; row-major: its column
-  // offset).  A Z-job's stream switches to the second product at stage
-  // spass; stages past the end re-fetch stage 0 into a slot that is never
-  // read again, which keeps the vmcnt bookkeeping uniform.
-  const uint32_t ldb32 = (uint32_t)ldb;
-  const size_t chunkb = (size_t)P::CHUNK;
-  const size_t step_b = P::TILED ? chunkb : (size_t)P::RB;   // bytes from one stage to the next
-  const size_t a_hi = (size_t)spass * chunkb;                // tiled: A rows 128-255 (next row block)
-  const char* cA = a0;
-  const char* cB = b0;
-  int cs = 0;
-  auto dma = [&](LDS_AS char* slot) {
-    if constexpr (P::TILED) dma_stage_tiled<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
-    else dma_stage_rows<PREC>(slot, cA, cB, ldb32, wave, lane);
-    ++cs;   // selects, not branches: the stage body stays one basic block
-    const bool wrap = cs >= nst, second = cs == spass;
-    cA = wrap ? a0 : second ? a1 : cA + step_b;
-    cB = wrap ? b0 : second ? b1 : cB + step_b;
-  };
-
-  if constexpr (PREC == kFP32) {
-    // FP32 products: the MFMA accumulator is added into an FP64 tile sum
-    // every `flush` stages (exact outer sum: the only FP32 rounding chain
-    // left is the accumulator's own, `flush` stages long).  One operand
-    // register set: with 32 MFMAs of 64 cycles per stage the other wave of
-    // the SIMD covers this wave's LDS reads.
-    double td[BR][BC][16];
-#pragma unroll
-    for (int i = 0; i < BR; ++i)
-#pragma unroll
-      for (int j = 0; j < BC; ++j)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) td[i][j][e] = 0.0;
-    Ops<PREC> o;
-    dma(R0);
-    dma(R1);
-    dma(R2);
-    // Block b = (bi, bj) of the accumulator is added into the FP64 sum
-    // every `flush` = 4g stages, the four blocks one stage apart (block b at
-    // stages 4g q + b).  In the stage that flushes block b its MFMAs are
-    // issued first; the conversions follow the stage's last MFMA, when the
-    // operand registers are free and block b's chain has long completed.
-    const int grp = a.flush >= 4 ? a.flush / 4 : 0;   // 0: single level
-    int gq = 0;   // group of 4 stages, modulo grp
-#define DMPT_ITER1(CUR, REFILL, K)                                    \
-    {                                                                 \
-      wait_vm<2 * P::L, true>();                                      \
-      barrier_nofence();                                              \
-      dma(REFILL);                                                    \
-      __builtin_amdgcn_sched_barrier(0);                              \
-      read_ops<PREC>(CUR, o, rowA, rowB, h);                          \
-      mma_fp32_from<K>(o, acc);                                       \
-      if (grp && gq == 0) {                                           \
-        _Pragma("unroll") for (int e = 0; e < 16; ++e)                \
-          td[(K) >> 1][(K) & 1][e] += (double)acc[(K) >> 1][(K) & 1][e]; \
-        acc[(K) >> 1][(K) & 1] = f32x16{0};                           \
-      }                                                               \
-    }
-    for (int s = 0; s < nst; s += 4) {
-      DMPT_ITER1(R0, R3, 0)
-      DMPT_ITER1(R1, R0, 1)
-      DMPT_ITER1(R2, R1, 2)
-      DMPT_ITER1(R3, R2, 3)
-      if (++gq == grp) gq = 0;
-    }
-#undef DMPT_ITER1
-    wait_vm<0, true>();
-#pragma unroll
-    for (int i = 0; i < BR; ++i)
-#pragma unroll
-      for (int j = 0; j < BC; ++j)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) tot[i][j][e] = (float)(td[i][j][e] + (double)acc[i][j][e]);
-  } else {
-#pragma unroll
-  for (int i = 0; i < BR; ++i)
-#pragma unroll
-    for (int j = 0; j < BC; ++j) tot[i][j] = f32x16{0};
-  Ops<PREC> o0, o1;
-  dma(R0);
-  dma(R1);
-  dma(R2);
-  wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
-  barrier_nofence();
-  dma(R3);
-  __builtin_amdgcn_sched_barrier(0);
-  read_ops<PREC>(R0, o0, rowA, rowB, h);
-
-  // Iteration s: the operands of stage s are in registers (OC).  Wait until
-  // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
-  // LDS reads of stage s are done, barrier (so has every wave), refill the
-  // slot of stage s with stage s+4, read stage s+1 into the other register
-  // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
-  // of the previous one.
-#define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
-  {                                                       \
-    wait_vm<2 * P::L, true>();                            \
-    barrier_nofence();                                    \
-    dma(REFILL);   /* stage (S_) + 4 */                   \
-    __builtin_amdgcn_sched_barrier(0);                    \
-    read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
-    mma_ops<PREC>(OC, acc);                               \
-    stage_order<PREC>();                                  \
-  }
-  const int flj = MIX && kind == kJobZ && a.flush_z > 0 ? a.flush_z : a.flush;
-  const int fl4 = flj > 0 ? flj : 1 << 30;   // flush every fl4 groups of 4 stages
-  int since = 0;
-  for (int s = 0; s < nst; s += 4) {
-    DMPT_ITER(s + 0, R1, R0, o0, o1)
-    DMPT_ITER(s + 1, R2, R1, o1, o0)
-    DMPT_ITER(s + 2, R3, R2, o0, o1)
-    DMPT_ITER(s + 3, R0, R3, o1, o0)
-    if (++since == fl4) {
-      since = 0;
-#pragma unroll
-      for (int i = 0; i < BR; ++i)
-#pragma unroll
-        for (int j = 0; j < BC; ++j) {
-          tot[i][j] += acc[i][j];
-          acc[i][j] = f32x16{0};
-        }
-    }
-  }
-#undef DMPT_ITER
-  wait_vm<0, true>();
-#pragma unroll
-  for (int i = 0; i < BR; ++i)
-#pragma unroll
-    for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
-  }
-  if constexpr (PREC == kSplitH) {
-#pragma unroll
-    for (int i = 0; i < BR; ++i)
-#pragma unroll
-      for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
-  }
-  if (a.oscale != 0.0f && a.oscale != 1.0f) {
-#pragma unroll
-    for (int i = 0; i < BR; ++i)
-#pragma unroll
-      for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
-  }
-
-  // ------------------------------------------------------------ epilogue
+  (void)s_out;
   const size_t np = a.n_pad;
   // field-wise selects (a selected reference would keep the argument block in
   // private memory)
@@ -957,6 +764,244 @@ __device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, 
   }
 }
 
+// One job of the step kernel (one output tile of P = X_n^2 or of
+// Z = Y_n X_n + X_n Y_n) in operand format PREC: DMA + MFMA main loop and the
+// fused epilogue.  R0..R3: the LDS ring (each slot also holds two waves'
+// epilogue staging); s_red, s_nrm: workgroup scratch.
+// MIX: a job of the mixed launch of the three-term-X^2 option: its P-jobs
+// (kSplit3) also write the two-term copy of their output, its Z-jobs
+// (kSplit2) read X's two-term copy and take their own flush interval.
+// jpos: the job's list position (the scratch slot of a K-split job).
+template <int PREC, bool MIX = false>
+__device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, const int jpos, const int sigma,
+                                         LDS_AS char* R0, LDS_AS char* R1, LDS_AS char* R2, LDS_AS char* R3,
+                                         double* s_red, double* s_nrm) {
+  using P = Pipe<PREC>;
+  const int kind = job & 1;
+  const int obs = (job >> 1) & 63;
+  const int ti = (job >> 8) & 4095;    // 256-row block
+  const int tj = (job >> 20) & 2047;   // 128-column block
+  constexpr int opb = operand_bytes(PREC);
+  const size_t ldb = (size_t)a.n_pad * opb;
+  const int spass = a.n_pad / Fmt<PREC>::K;           // stages per product
+  const int nst = kind == kJobZ ? 2 * spass : spass;  // Z-job: Y_I X_J^T, then X_I Y_J^T
+  // K-split job (two-term / three-term BF16 and plain BF16 formats): stages
+  // [sb, se) of the tile's stream, half of it (nst is a multiple of 8)
+  constexpr bool kCanSplit = PREC == kSplit2 || PREC == kSplit3 || PREC == kBF16;
+  const bool split = kCanSplit && (job & kJobSplit) != 0;
+  const int half = split && (job & kJobHalf1) ? 1 : 0;
+  const int sb = split && half ? nst / 2 : 0;
+  const int se = split && !half ? nst / 2 : nst;
+
+  // X operand: the two-term copy for the Z-jobs of the mixed launch (op2),
+  // the copy in this job's format otherwise
+  const char* xop = (const char*)(MIX && kind == kJobZ ? a.x_in.op2 : a.x_in.op);
+  const char* yop = (const char*)a.y_in.op + obs * a.y_in.stride_op;
+  // row block I / J starts at the same byte offset in both layouts:
+  // row-major rows * ldb, tiled (row block * nst) chunks of 128 rows
+  const size_t rowI = (size_t)ti * TM * ldb, rowJ = (size_t)tj * TN * ldb;
+  const char* a0 = (kind == kJobZ ? yop : xop) + rowI;
+  const char* b0 = xop + rowJ;
+  const char* a1 = xop + rowI;
+  const char* b1 = (kind == kJobZ ? yop : xop) + rowJ;
+
+  // kSplitH: the products come out scaled by 2^(s_a + s_b) (usc undoes it);
+  // the copy this job writes is scaled by sc_out = 2^s_out.  P-jobs: both
+  // operands X_n at 2^14.  Z-jobs: Y_n at its own 2^s_in; Y_{n+1} gets the
+  // exponent bounded from ||Y_n||_F.
+  float usc = 1.0f, sc_out = 1.0f;
+  int s_out = 0;
+  if constexpr (PREC == kSplitH) {
+    if (kind == kJobZ) {
+      const MatMeta* mi = (const MatMeta*)(a.y_in.meta + obs * a.y_in.stride_op);
+      usc = ldexpf(1.0f, -(kXScaleExp + mi->scale));
+      const int nb = a.n_pad / 64;   // metadata holds (n_pad / 64)^2 partials
+      s_out = yscale_exp(meta_norm(mi, nb * nb, s_nrm), kYBound);
+    } else {
+      usc = ldexpf(1.0f, -2 * kXScaleExp);
+      s_out = kXScaleExp;
+    }
+    sc_out = ldexpf(1.0f, s_out);
+  }
+
+  // The thread index is made opaque per job so that the compiler keeps the
+  // lane-dependent address arithmetic inside the job (hoisted out of the
+  // job loop it would stay live through the main loop and spill).
+  unsigned int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
+  const int h = lane >> 5, l32 = lane & 31;
+  const int rowA = wr * 64 + l32, rowB = wc * 64 + l32;
+
+  f32x16 acc[BR][BC], tot[BR][BC];
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) acc[i][j] = f32x16{0};
+
+  // The stages of the job's K stream are fetched in order, each call of dma
+  // the next one: cA / cB address stage cs of the A / B panel (tiled: its
+  // chunk, which advances by one chunk per stage; row-major: its column
+  // offset).  A Z-job's stream switches to the second product at stage
+  // spass; stages past the end re-fetch stage 0 into a slot that is never
+  // read again, which keeps the vmcnt bookkeeping uniform.
+  const uint32_t ldb32 = (uint32_t)ldb;
+  const size_t chunkb = (size_t)P::CHUNK;
+  const size_t step_b = P::TILED ? chunkb : (size_t)P::RB;   // bytes from one stage to the next
+  const size_t a_hi = (size_t)spass * chunkb;                // tiled: A rows 128-255 (next row block)
+  const char* cA = sb < spass ? a0 + (size_t)sb * step_b : a1 + (size_t)(sb - spass) * step_b;
+  const char* cB = sb < spass ? b0 + (size_t)sb * step_b : b1 + (size_t)(sb - spass) * step_b;
+  int cs = sb;
+  auto dma = [&](LDS_AS char* slot) {
+    if constexpr (P::TILED) dma_stage_tiled<PREC>(slot, cA, cA + a_hi, cB, wave, lane);
+    else dma_stage_rows<PREC>(slot, cA, cB, ldb32, wave, lane);
+    ++cs;   // selects, not branches: the stage body stays one basic block
+    const bool wrap = cs >= se, second = cs == spass;
+    cA = wrap ? a0 : second ? a1 : cA + step_b;
+    cB = wrap ? b0 : second ? b1 : cB + step_b;
+  };
+
+  if constexpr (PREC == kFP32) {
+    // FP32 products: the MFMA accumulator is added into an FP64 tile sum
+    // every `flush` stages (exact outer sum: the only FP32 rounding chain
+    // left is the accumulator's own, `flush` stages long).  One operand
+    // register set: with 32 MFMAs of 64 cycles per stage the other wave of
+    // the SIMD covers this wave's LDS reads.
+    double td[BR][BC][16];
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) td[i][j][e] = 0.0;
+    Ops<PREC> o;
+    dma(R0);
+    dma(R1);
+    dma(R2);
+    // Block b = (bi, bj) of the accumulator is added into the FP64 sum
+    // every `flush` = 4g stages, the four blocks one stage apart (block b at
+    // stages 4g q + b).  In the stage that flushes block b its MFMAs are
+    // issued first; the conversions follow the stage's last MFMA, when the
+    // operand registers are free and block b's chain has long completed.
+    const int grp = a.flush >= 4 ? a.flush / 4 : 0;   // 0: single level
+    int gq = 0;   // group of 4 stages, modulo grp
+#define DMPT_ITER1(CUR, REFILL, K)                                    \
+    {                                                                 \
+      wait_vm<2 * P::L, true>();                                      \
+      barrier_nofence();                                              \
+      dma(REFILL);                                                    \
+      __builtin_amdgcn_sched_barrier(0);                              \
+      read_ops<PREC>(CUR, o, rowA, rowB, h);                          \
+      mma_fp32_from<K>(o, acc);                                       \
+      if (grp && gq == 0) {                                           \
+        _Pragma("unroll") for (int e = 0; e < 16; ++e)                \
+          td[(K) >> 1][(K) & 1][e] += (double)acc[(K) >> 1][(K) & 1][e]; \
+        acc[(K) >> 1][(K) & 1] = f32x16{0};                           \
+      }                                                               \
+    }
+    for (int s = 0; s < nst; s += 4) {
+      DMPT_ITER1(R0, R3, 0)
+      DMPT_ITER1(R1, R0, 1)
+      DMPT_ITER1(R2, R1, 2)
+      DMPT_ITER1(R3, R2, 3)
+      if (++gq == grp) gq = 0;
+    }
+#undef DMPT_ITER1
+    wait_vm<0, true>();
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) tot[i][j][e] = (float)(td[i][j][e] + (double)acc[i][j][e]);
+  } else {
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) tot[i][j] = f32x16{0};
+  Ops<PREC> o0, o1;
+  dma(R0);
+  dma(R1);
+  dma(R2);
+  wait_vm<2 * P::L, false>();   // stage 0 landed (1 and 2 may be in flight)
+  barrier_nofence();
+  dma(R3);
+  __builtin_amdgcn_sched_barrier(0);
+  read_ops<PREC>(R0, o0, rowA, rowB, h);
+
+  // Iteration s: the operands of stage s are in registers (OC).  Wait until
+  // this wave's DMA of stage s+1 landed (s+2 and s+3 may be in flight) and its
+  // LDS reads of stage s are done, barrier (so has every wave), refill the
+  // slot of stage s with stage s+4, read stage s+1 into the other register
+  // set and multiply stage s: the LDS reads of one stage overlap the MFMAs
+  // of the previous one.
+#define DMPT_ITER(S_, NEXT, REFILL, OC, ON)                \
+  {                                                       \
+    wait_vm<2 * P::L, true>();                            \
+    barrier_nofence();                                    \
+    dma(REFILL);   /* stage (S_) + 4 */                   \
+    __builtin_amdgcn_sched_barrier(0);                    \
+    read_ops<PREC>(NEXT, ON, rowA, rowB, h);              \
+    mma_ops<PREC>(OC, acc);                               \
+    stage_order<PREC>();                                  \
+  }
+  const int flj = MIX && kind == kJobZ && a.flush_z > 0 ? a.flush_z : a.flush;
+  const int fl4 = flj > 0 ? flj : 1 << 30;   // flush every fl4 groups of 4 stages
+  int since = 0;
+  for (int s = sb; s < se; s += 4) {
+    DMPT_ITER(s + 0, R1, R0, o0, o1)
+    DMPT_ITER(s + 1, R2, R1, o1, o0)
+    DMPT_ITER(s + 2, R3, R2, o0, o1)
+    DMPT_ITER(s + 3, R0, R3, o1, o0)
+    if (++since == fl4) {
+      since = 0;
+#pragma unroll
+      for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int j = 0; j < BC; ++j) {
+          tot[i][j] += acc[i][j];
+          acc[i][j] = f32x16{0};
+        }
+    }
+  }
+#undef DMPT_ITER
+  wait_vm<0, true>();
+#pragma unroll
+  for (int i = 0; i < BR; ++i)
+#pragma unroll
+    for (int j = 0; j < BC; ++j) tot[i][j] += acc[i][j];
+  }
+  if constexpr (PREC == kSplitH) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] *= usc;   // a power of two: exact
+  }
+  if (split) {
+    // K-split half: the partial tile sum goes to its scratch slot (coalesced:
+    // 16 stores of 1 KB per wave); the combine launch finishes the tile
+    float* sb_out = a.split_buf + ((size_t)a.split_slot[jpos] * 2 + half) * kSplitTileFloats;
+#pragma unroll
+    for (int q = 0; q < BR * BC; ++q)
+#pragma unroll
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const f32x16& t = tot[q / BC][q % BC];
+        *(f32x4*)(sb_out + ((size_t)((q * 4 + e4) * NW + wave) * 64 + lane) * 4) =
+            f32x4{t[4 * e4], t[4 * e4 + 1], t[4 * e4 + 2], t[4 * e4 + 3]};
+      }
+    return;
+  }
+  if (a.oscale != 0.0f && a.oscale != 1.0f) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
+  }
+  step_epilogue<PREC, MIX>(a, job, sigma, tot, R0, R1, R2, R3, s_red, sc_out, s_out);
+}
+
 // ---------------------------------------------------------------- wide sweep jobs
 
 // Z-jobs on 256 x 256 output tiles (I, J >= I): twice the columns of a
@@ -1060,7 +1105,7 @@ __device__ __forceinline__ void step_job_wide(const StepArgs& a, const uint32_t 
   using P = WPipe<PREC>;
   const int obs = (job >> 1) & 63;
   const int ti = (job >> 8) & 4095;    // 256-row block
-  const int tj = (job >> 20) & 4095;   // 256-column block, tj >= ti
+  const int tj = (job >> 20) & 2047;   // 256-column block, tj >= ti
   const size_t ldb = (size_t)a.n_pad * operand_bytes(PREC);
   const int spass = a.n_pad / Fmt<PREC>::K;
   const int nst = 2 * spass;
@@ -1301,14 +1346,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     LDS_AS char* R3 = (LDS_AS char*)ring3;
     constexpr bool MIX = PP != PZ;
     if constexpr (ZW) {
-      if (job & kJobWide) step_job_wide<PZ, MIX>(a, job, sigma, R0, R1, R2, R3);
-      else if (MIX && (job & 1) == kJobZ) step_job<PZ, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
-      else step_job<PP, MIX>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      if ((job & (kJobSplit | kJobWide)) == kJobWide) step_job_wide<PZ, MIX>(a, job, sigma, R0, R1, R2, R3);
+      else if (MIX && (job & 1) == kJobZ) step_job<PZ, true>(a, job, jpos, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      else step_job<PP, MIX>(a, job, jpos, sigma, R0, R1, R2, R3, s_red, &s_nrm);
     } else if constexpr (!MIX) {
-      step_job<PP>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      step_job<PP>(a, job, jpos, sigma, R0, R1, R2, R3, s_red, &s_nrm);
     } else {
-      if ((job & 1) == kJobZ) step_job<PZ, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
-      else step_job<PP, true>(a, job, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      if ((job & 1) == kJobZ) step_job<PZ, true>(a, job, jpos, sigma, R0, R1, R2, R3, s_red, &s_nrm);
+      else step_job<PP, true>(a, job, jpos, sigma, R0, R1, R2, R3, s_red, &s_nrm);
     }
   }
 }
@@ -1348,6 +1393,70 @@ hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s, bool w
     case kSplit32: hipLaunchKernelGGL((k_step<kSplit3, kSplit2, false>), grid, dim3(NT), 0, s, args); break;
     case kBF16: hipLaunchKernelGGL((k_step<kBF16, kBF16, false>), grid, dim3(NT), 0, s, args); break;
     case kSplitH: hipLaunchKernelGGL((k_step<kSplitH, kSplitH, false>), grid, dim3(NT), 0, s, args); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Combine launch of K-split tiles (see kJobSplit): workgroup q adds the two
+// partial tile sums of slot q and runs the epilogue of tile cjobs[q] with the
+// sigma of the step launch it follows.
+template <int PP, int PZ>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_combine(
+    StepArgs a, const uint32_t* cjobs) {
+  __shared__ __attribute__((aligned(1024))) char stage0[2 * kStageBytes];
+  __shared__ __attribute__((aligned(1024))) char stage1[2 * kStageBytes];
+  __shared__ __attribute__((aligned(1024))) char stage2[2 * kStageBytes];
+  __shared__ __attribute__((aligned(1024))) char stage3[2 * kStageBytes];
+  __shared__ double s_red[3 * NW];
+  const uint32_t job = cjobs[blockIdx.x];
+  const int kind = job & 1;
+  int sigma;
+  if (a.decide) {
+    // the step launch recorded sigma_n, or 0 when it stopped (or never ran
+    // after the stop); its Z-jobs were skipped once the sweep had stopped
+    sigma = a.ctl->rec[a.step].sigma;
+    if (!(sigma == 1 || sigma == -1)) return;
+    if (kind == kJobZ && a.ytol2 > 0.0 && a.ctl->ystop != 0 && a.step >= a.ctl->ystop) return;
+  } else {
+    sigma = a.sigma_src ? a.sigma_src[a.step].sigma : a.fixed_sigma;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float* h0 = a.split_buf + (size_t)blockIdx.x * 2 * kSplitTileFloats;
+  const float* h1 = h0 + kSplitTileFloats;
+  f32x16 tot[BR][BC];
+#pragma unroll
+  for (int q = 0; q < BR * BC; ++q)
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+      const size_t off = ((size_t)((q * 4 + e4) * NW + wave) * 64 + lane) * 4;
+      const f32x4 u = *(const f32x4*)(h0 + off), v = *(const f32x4*)(h1 + off);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tot[q / BC][q % BC][4 * e4 + e] = u[e] + v[e];
+    }
+  if (a.oscale != 0.0f && a.oscale != 1.0f) {
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+      for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
+  }
+  LDS_AS char* R0 = (LDS_AS char*)stage0;
+  LDS_AS char* R1 = (LDS_AS char*)stage1;
+  LDS_AS char* R2 = (LDS_AS char*)stage2;
+  LDS_AS char* R3 = (LDS_AS char*)stage3;
+  constexpr bool MIX = PP != PZ;
+  if (MIX && kind == kJobZ) step_epilogue<PZ, true>(a, job, sigma, tot, R0, R1, R2, R3, s_red, 1.0f, 0);
+  else step_epilogue<PP, MIX>(a, job, sigma, tot, R0, R1, R2, R3, s_red, 1.0f, 0);
+}
+
+hipError_t launch_step_combine(int prec, StepArgs args, const uint32_t* cjobs, int ncomb, hipStream_t s) {
+  if (ncomb <= 0) return hipSuccess;
+  const dim3 grid(ncomb);
+  switch (prec) {
+    case kSplit2: hipLaunchKernelGGL((k_step_combine<kSplit2, kSplit2>), grid, dim3(NT), 0, s, args, cjobs); break;
+    case kSplit32: hipLaunchKernelGGL((k_step_combine<kSplit3, kSplit2>), grid, dim3(NT), 0, s, args, cjobs); break;
+    case kBF16: hipLaunchKernelGGL((k_step_combine<kBF16, kBF16>), grid, dim3(NT), 0, s, args, cjobs); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -51,7 +51,7 @@ def test_no_undeclared_c_exports():
 
 
 def test_abi_version(lib):
-    assert lib.dmpt_abi_version() == 7
+    assert lib.dmpt_abi_version() == 8
 
 
 def test_struct_layouts():
@@ -62,7 +62,7 @@ def test_struct_layouts():
     assert Opts.spin.offset == 80 and Opts.workspace_bytes.offset == 104
     assert Opts.ckpt_interval.offset == 64
     assert Info.sigma.offset == 56
-    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4 + 8 + 2 * 4
+    assert C.sizeof(Info) == 56 + 256 + 3 * 256 * 8 + 4 * 8 + 2 * 4 + 8 + 4 * 4
     assert Info.idem_x.offset == 56 + 256 + 2 * 256 * 8
     assert Opts.profile.offset == 60
 

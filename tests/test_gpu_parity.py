@@ -152,6 +152,29 @@ def test_sweep_tol_matches_closed_form(gpu, case, prec):
     assert eps[info["correction_steps"] - 1] <= 1e-3
 
 
+def test_split_tail_tiles_match_closed_form(gpu):
+    """N = 2048, split3x with the correction: the launches' lists end with
+    K-split tiles (two half-K jobs each, added by a combine launch) where the
+    makespan model picks them; chi must meet the refined 1e-5 against the
+    closed form and agree with refine = 2 (regular tiles only, no split)
+    to the accumulation-order level."""
+    dm = _dm()
+    wl = _case("band2048")
+    H, A = _dev(wl.H, gpu), _dev(wl.A[0], gpu)
+    chi, D, _, info = dm.susceptibility(H, A, wl.nocc, precision="split3x_bf16", refine=1, sweep_tol=1e-3)
+    chi2, _, _, info2 = dm.susceptibility(H, A, wl.nocc, precision="split3x_bf16", refine=2, sweep_tol=1e-3)
+    h = wl.H.astype(np.float64)
+    chiref = cf.susceptibility(h, wl.A[0].astype(np.float64), wl.nocc, spin=2.0)
+    ec, ec2 = cf.rel_frobenius(_np(chi), chiref), cf.rel_frobenius(_np(chi2), chiref)
+    print(f"split tiles {info['split_tiles']} (step), {info['split_tiles_sweep']} (sweep); errchi {ec:.2e}, "
+          f"regular tiles {ec2:.2e}")
+    assert info["split_tiles"] + info["split_tiles_sweep"] > 0
+    assert info2["split_tiles"] == 0 and info2["split_tiles_sweep"] == 0
+    assert ec <= 1e-5 and ec2 <= 1e-5
+    assert cf.rel_frobenius(_np(chi), _np(chi2)) <= 5e-6
+    assert cf.rel_frobenius(_np(D), cf.density_matrix(h, wl.nocc)) <= 1e-5
+
+
 def test_refine_two_observables(gpu):
     """The correction runs every observable through one BF16 sweep: each must
     match its own closed form, and the batch must equal the single runs."""
