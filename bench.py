@@ -79,6 +79,7 @@ def parse():
                          "the closed form on all host threads, and one recursion step and the closed form "
                          "of the same recipe at N/2 on one thread")
     ap.add_argument("--nobs", type=int, default=1, help="--extra fermi: observables in one batch")
+    ap.add_argument("--no-fp32", action="store_true", help="--extra fermi|nonorth: time args.precision only")
     ap.add_argument("--extra", choices=["fermi", "nonorth", "shapes"], default=None,
                     help="instead of the headline metric, time the finite-temperature path (Sec. V.B: "
                          "gapless banded H, kT = 0.01, one random observable), the non-orthonormal one "
@@ -137,7 +138,7 @@ def run_extra(args, dm, torch, W, dev):
     calls after warmup ones, inputs resident); prints one JSON line."""
     t = time.perf_counter()
     if args.extra == "fermi":
-        wl = W.banded_gapless(args.n, half_bandwidth=256, nobs=args.nobs)
+        wl = W.banded_gapless(args.n, half_bandwidth=256, nobs=args.nobs, log=log)
         H, A = torch.from_numpy(wl.H).to(dev), torch.from_numpy(wl.A).to(dev)
         call = lambda prec: dm.susceptibility_fermi(H, A, wl.nocc, 0.01, precision=prec)
         workload = (f"gapless banded H (half-bandwidth 256), N={wl.n}, N_occ={wl.nocc}, kT=0.01, "
@@ -155,7 +156,7 @@ def run_extra(args, dm, torch, W, dev):
     base = args.precision.partition("+")[0]
     if args.extra == "fermi" and base == "split3x_bf16":
         base = "split3_bf16"   # the finite-temperature products take one format for all operands
-    for prec in dict.fromkeys([base, "fp32"]):
+    for prec in dict.fromkeys([base] if args.no_fp32 else [base, "fp32"]):
         for _ in range(args.warmup):
             call(prec)
         torch.cuda.synchronize()

@@ -99,7 +99,7 @@ typedef struct dmpt_opts {
   int32_t precision;      /* dmpt_precision */
   int32_t bounds;         /* dmpt_bounds_mode */
   double emin, emax;      /* spectral bounds, read iff bounds == DMPT_BOUNDS_GIVEN */
-  int32_t lanczos_steps;  /* Lanczos iterations for DMPT_BOUNDS_LANCZOS; 0 -> 48 */
+  int32_t lanczos_steps;  /* Lanczos iterations for DMPT_BOUNDS_LANCZOS; 0 -> 32 */
   int32_t max_iter;       /* SP2 step limit, <= DMPT_MAX_STEPS; 0 -> 100 */
   int32_t min_iter;       /* steps before the stopping test may fire; < 0 -> 10 */
   int32_t sweep;          /* dmpt_sweep (susceptibility only) */

@@ -89,7 +89,7 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
           : o->precision == DMPT_SPLIT3X_BF16 ? kSplit32
           : o->precision == DMPT_SPLIT_FP16 ? kSplitH : kBF16;
   r->bounds = o->bounds;
-  r->lanczos_steps = o->lanczos_steps ? o->lanczos_steps : 48;
+  r->lanczos_steps = o->lanczos_steps ? o->lanczos_steps : 32;
   r->max_iter = o->max_iter ? o->max_iter : 100;
   r->min_iter = o->min_iter < 0 ? 10 : o->min_iter;
   r->sweep = o->sweep;
@@ -1036,11 +1036,18 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       return yf.f32 + (size_t)(q - 2 - nobs) * yf.stride_f32;
     };
     auto nsrc_of = [&](int q) { return (q == 0 || q >= 2 + nobs) ? p.n_pad : o.n; };
+    // D's own operand copy is already in the residual's format when the X
+    // products run in it (written by the step that formed D, from the same
+    // FP32 values and at the same scale): no second copy
+    const bool d_has_copy = (rp == kSplit3 && (p.prec == kSplit3 || p.prec == kSplit32)) ||
+                            (rp == kSplitH && p.prec == kSplitH);
     auto opnd = [&](int q) -> const void* {
       if (rp == kFP32 && (q == 0 || q >= 2 + nobs)) return src_of(q);
+      if (q == 0 && d_has_copy) return xf.op;
       return cpy(q);
     };
     for (int q = 0; q < 2 + 2 * nobs; ++q) {
+      if (q == 0 && d_has_copy) continue;
       if (rp == kFP32) {
         if (q == 1 || (q >= 2 && q < 2 + nobs)) DMPT_HIP(launch_pad(src_of(q), o.n, p.n_pad, (float*)cpy(q), 0, s));
       } else {
@@ -1258,7 +1265,7 @@ void dmpt_opts_default(dmpt_opts* o, int32_t n, int32_t nocc) {
   o->nocc = nocc;
   o->precision = DMPT_FP32;
   o->bounds = DMPT_BOUNDS_LANCZOS;
-  o->lanczos_steps = 48;
+  o->lanczos_steps = 32;
   o->max_iter = 100;
   o->min_iter = 10;
   o->sweep = DMPT_SWEEP_FORWARD;

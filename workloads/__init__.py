@@ -170,18 +170,23 @@ def banded_gapped(n: int = 4096, nocc: int | None = None, gap: float = 0.1,
 
 
 def banded_gapless(n: int = 16384, nocc: int | None = None, half_bandwidth: int = 256, hop_std: float = 0.05,
-                   nobs: int = 32, cfg: int = 5) -> Workload:
+                   nobs: int = 32, cfg: int = 5, log=None) -> Workload:
     """Config 5 (finite temperature): random banded H (half-bandwidth 256,
     hopping ~ N(0, hop_std^2), onsite ~ U(-1, 1)) with no gap opened, and
-    nobs random symmetric Frobenius-normalised observables."""
+    nobs random symmetric Frobenius-normalised observables.  log: optional
+    callable told about each observable as it is drawn (large batches take
+    minutes)."""
     nocc = n // 2 if nocc is None else nocc
     rng = rng_for(cfg, n)
     hop = rng.normal(0.0, hop_std, size=(n, n))
     hop = np.triu(hop, 1) * banded_mask(n, half_bandwidth)
     h = hop + hop.T
     h[np.diag_indices(n)] = rng.uniform(-1.0, 1.0, size=n)
-    a = np.stack([_as32(frobenius_normalised(random_symmetric(rng, n))) for _ in range(nobs)]) if nobs \
-        else np.zeros((0, n, n), np.float32)
+    a = np.zeros((nobs, n, n), np.float32)
+    for k in range(nobs):
+        a[k] = _as32(frobenius_normalised(random_symmetric(rng, n)))
+        if log:
+            log(f"observable {k + 1} of {nobs} drawn")
     return Workload("banded_gapless", n, nocc, _as32(h), a, np.zeros((0, n, n), np.float32),
                     {"cfg": cfg, "half_bandwidth": half_bandwidth})
 
