@@ -127,8 +127,10 @@ typedef struct dmpt_opts {
                              has to be accurate relative to that small correction.  With
                              DMPT_SPLIT3X_BF16 the sweep products of the steps, of the projection
                              and of the correction then run on 256 x 256 output tiles with one
-                             FP32 accumulation level (the correction removes what that adds).
-                             2 -> the same correction on the regular tiles only.  0 -> off. */
+                             FP32 accumulation level (the correction removes what that adds),
+                             and each launch's last tiles as two half-K jobs added by a combine
+                             launch (dmpt_info.split_tiles*).  2 -> the same correction on the
+                             regular tiles only.  0 -> off. */
   double sweep_tol;       /* refine only, 0 <= sweep_tol < 1/4: the sweep products stop at the
                              first X_n with ||X_n - X_n^2||_F^2 <= sweep_tol^2 (every eigenvalue
                              of X_n within sweep_tol of 0 or 1; Y_{n+1} is kept, the recursion of

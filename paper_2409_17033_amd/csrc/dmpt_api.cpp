@@ -826,7 +826,9 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       a.y_out = y_ref(p, ws, (n + 1) & 1);
       a.part_in = part[n & 1];
       a.part_out = part[(n + 1) & 1];
-      a.nparts = n == 1 ? p.nb64 * p.nb64 : p.nparts_step;
+      // X_1's partials come from its initialisation; later ones from the
+      // previous step launch, and 3 more per K-split tile from its combine
+      a.nparts = n == 1 ? p.nb64 * p.nb64 : p.nparts_step + 3 * (int)cjobs_main.size();
       const int ma = prof.mark();
       if (split_launch) {
         // one mixed launch: Z-jobs on two-term copies, then P-jobs on

@@ -18,6 +18,11 @@
 //                                      both operands: P_IJ = X_I X_J^T)
 //     Z = Y_n X_n + X_n Y_n          (kind Z; = Y_I X_J^T + X_I Y_J^T, the two
 //                                      products K-concatenated)
+//   When the residual correction follows, most Z-jobs are 256 x 256 tiles
+//   (one accumulation level; fewer DMA bytes per flop), and each list ends
+//   with K-split tiles: two jobs that each run half of a tile's stages and
+//   store a partial sum, added by a combine launch that runs the tile's
+//   epilogue before the next step launch.
 //   The grid is persistent (one workgroup per CU): workgroups take jobs from
 //   per-XCD queues with atomic tickets and steal from the other queues when
 //   their own runs dry.
@@ -527,13 +532,17 @@ __device__ __forceinline__ int tile_index(int ti, int tj, int tcols) {
 // from the tile sums `tot` (MFMA accumulator layout): sigma-update, direct and
 // mirror stores, operand copies, and for P-jobs the FP64 partials of
 // Tr X_{n+1}, ||X_{n+1}||_F^2 and ||X_n - X_n^2||_F^2.  R0..R3: LDS areas of at
-// least two 64 x 65 FP32 staging blocks each; sc_out / s_out: the scale of the
-// FP16 copy (kSplitH).
+// least two 64 x 65 FP32 staging blocks each (wave w stages in R[w / 2]);
+// sc_out / s_out: the scale of the FP16 copy (kSplitH).  The workgroup's
+// waves are waves wave_base .. wave_base + nwaves - 1 of the tile's eight
+// (the step kernel: all of them); P-jobs write the FP64 partials of those
+// waves to part_out[part_idx].
 template <int PREC, bool MIX>
 __device__ __forceinline__ void step_epilogue(const StepArgs& a, const uint32_t job, const int sigma,
                                               f32x16 (&tot)[BR][BC], LDS_AS char* R0, LDS_AS char* R1,
                                               LDS_AS char* R2, LDS_AS char* R3, double* s_red, const float sc_out,
-                                              const int s_out) {
+                                              const int s_out, const int wave_base, const int nwaves,
+                                              const int part_idx) {
   const int kind = job & 1;
   const int obs = (job >> 1) & 63;
   const int ti = (job >> 8) & 4095;    // 256-row block
@@ -541,7 +550,7 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& a, const uint32_t 
   unsigned int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave = wave_base + __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;   // 4 x 2 waves of 64 x 64
   const int h = lane >> 5, l32 = lane & 31;
   (void)s_out;
@@ -728,29 +737,29 @@ __device__ __forceinline__ void step_epilogue(const StepArgs& a, const uint32_t 
     sq = wave_sum(sq);
     ep = wave_sum(ep);
     if (lane == 0) {
-      s_red[3 * wave] = tr;
-      s_red[3 * wave + 1] = sq;
-      s_red[3 * wave + 2] = ep;
+      s_red[3 * (wave - wave_base)] = tr;
+      s_red[3 * (wave - wave_base) + 1] = sq;
+      s_red[3 * (wave - wave_base) + 2] = ep;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       Part p = {0.0, 0.0, 0.0, 0.0};
-      for (int w = 0; w < NW; ++w) {
+      for (int w = 0; w < nwaves; ++w) {
         p.tr += s_red[3 * w];
         p.sq += s_red[3 * w + 1];
         p.eps += s_red[3 * w + 2];
       }
-      a.part_out[tile_index(ti, tj, a.ntile)] = p;
+      a.part_out[part_idx] = p;
     }
   }
   if constexpr (PREC == kSplitH) {
     if (kind == kJobZ) {
       yq = wave_sum(yq);
-      if (lane == 0) s_red[wave] = yq;
+      if (lane == 0) s_red[wave - wave_base] = yq;
       __syncthreads();
       if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < NW; ++w) t += s_red[w];
+        for (int w = 0; w < nwaves; ++w) t += s_red[w];
         MatMeta* mo = (MatMeta*)(a.y_out.meta + obs * a.y_out.stride_op);
         const int idx = tile_index(ti, tj, a.ntile);
         mo->nrm[idx] = t;
@@ -999,7 +1008,8 @@ __device__ __forceinline__ void step_job(const StepArgs& a, const uint32_t job, 
 #pragma unroll
       for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
   }
-  step_epilogue<PREC, MIX>(a, job, sigma, tot, R0, R1, R2, R3, s_red, sc_out, s_out);
+  step_epilogue<PREC, MIX>(a, job, sigma, tot, R0, R1, R2, R3, s_red, sc_out, s_out, 0, NW,
+                           tile_index(ti, tj, a.ntile));
 }
 
 // ---------------------------------------------------------------- wide sweep jobs
@@ -1398,19 +1408,27 @@ hipError_t launch_step(int prec, StepArgs args, int njobs, hipStream_t s, bool w
   return hipGetLastError();
 }
 
-// Combine launch of K-split tiles (see kJobSplit): workgroup q adds the two
-// partial tile sums of slot q and runs the epilogue of tile cjobs[q] with the
-// sigma of the step launch it follows.
+// Combine launch of K-split tiles (see kJobSplit): four workgroups of two
+// waves per split tile q (the slot), workgroup 4q + s taking the tile's row
+// stripe s (waves 2s, 2s + 1 of the step kernel's eight), add the two partial
+// sums and run those waves' part of the tile's epilogue with the sigma of the
+// step launch it follows.  The X^2 partials of stripe 0 go to the tile's own
+// entry, those of stripes 1-3 to entries 3q + s - 1 after the step tiles'
+// (the next launch's controller sums nparts = tiles + 3 x split tiles).
+constexpr int kCombWaves = 2, kCombStripes = NW / kCombWaves;
 template <int PP, int PZ>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_step_combine(
-    StepArgs a, const uint32_t* cjobs) {
-  __shared__ __attribute__((aligned(1024))) char stage0[2 * kStageBytes];
-  __shared__ __attribute__((aligned(1024))) char stage1[2 * kStageBytes];
-  __shared__ __attribute__((aligned(1024))) char stage2[2 * kStageBytes];
-  __shared__ __attribute__((aligned(1024))) char stage3[2 * kStageBytes];
-  __shared__ double s_red[3 * NW];
-  const uint32_t job = cjobs[blockIdx.x];
+__global__ __launch_bounds__(kCombWaves * 64) void k_step_combine(StepArgs a, const uint32_t* cjobs) {
+  __shared__ __attribute__((aligned(1024))) char stage[kCombWaves * kStageBytes];
+  __shared__ double s_red[3 * kCombWaves];
+  const int q = blockIdx.x / kCombStripes, stripe = blockIdx.x % kCombStripes;
+  const uint32_t job = cjobs[q];
   const int kind = job & 1;
+  const int tiles = (a.n_pad / TM) * (a.n_pad / TM + 1);
+  // A Z tile has no X^2 partials, but the next launch's controller sums the
+  // three extra entries of every split slot: they are zeroed (before any
+  // early return; only step launches with the controller read partials)
+  if (a.decide && kind == kJobZ && stripe > 0 && threadIdx.x == 0)
+    a.part_out[tiles + 3 * q + stripe - 1] = Part{0.0, 0.0, 0.0, 0.0};
   int sigma;
   if (a.decide) {
     // the step launch recorded sigma_n, or 0 when it stopped (or never ran
@@ -1422,18 +1440,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     sigma = a.sigma_src ? a.sigma_src[a.step].sigma : a.fixed_sigma;
   }
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const float* h0 = a.split_buf + (size_t)blockIdx.x * 2 * kSplitTileFloats;
+  const int wave_base = stripe * kCombWaves;
+  const int wave = wave_base + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float* h0 = a.split_buf + (size_t)q * 2 * kSplitTileFloats;
   const float* h1 = h0 + kSplitTileFloats;
   f32x16 tot[BR][BC];
 #pragma unroll
-  for (int q = 0; q < BR * BC; ++q)
+  for (int qq = 0; qq < BR * BC; ++qq)
 #pragma unroll
     for (int e4 = 0; e4 < 4; ++e4) {
-      const size_t off = ((size_t)((q * 4 + e4) * NW + wave) * 64 + lane) * 4;
+      const size_t off = ((size_t)((qq * 4 + e4) * NW + wave) * 64 + lane) * 4;
       const f32x4 u = *(const f32x4*)(h0 + off), v = *(const f32x4*)(h1 + off);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) tot[q / BC][q % BC][4 * e4 + e] = u[e] + v[e];
+      for (int e = 0; e < 4; ++e) tot[qq / BC][qq % BC][4 * e4 + e] = u[e] + v[e];
     }
   if (a.oscale != 0.0f && a.oscale != 1.0f) {
 #pragma unroll
@@ -1441,22 +1460,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
       for (int j = 0; j < BC; ++j) tot[i][j] *= a.oscale;
   }
-  LDS_AS char* R0 = (LDS_AS char*)stage0;
-  LDS_AS char* R1 = (LDS_AS char*)stage1;
-  LDS_AS char* R2 = (LDS_AS char*)stage2;
-  LDS_AS char* R3 = (LDS_AS char*)stage3;
+  // wave w stages in R[w / 2] + (w % 2) blocks: this workgroup's two waves
+  // (2 stripe, 2 stripe + 1) both map to the one staging area
+  LDS_AS char* R = (LDS_AS char*)stage;
+  const int ti = (job >> 8) & 4095, tj = (job >> 20) & 2047;
+  const int part_idx = stripe == 0 ? tile_index(ti, tj, a.ntile) : tiles + 3 * q + stripe - 1;
   constexpr bool MIX = PP != PZ;
-  if (MIX && kind == kJobZ) step_epilogue<PZ, true>(a, job, sigma, tot, R0, R1, R2, R3, s_red, 1.0f, 0);
-  else step_epilogue<PP, MIX>(a, job, sigma, tot, R0, R1, R2, R3, s_red, 1.0f, 0);
+  if (MIX && kind == kJobZ)
+    step_epilogue<PZ, true>(a, job, sigma, tot, R, R, R, R, s_red, 1.0f, 0, wave_base, kCombWaves, part_idx);
+  else
+    step_epilogue<PP, MIX>(a, job, sigma, tot, R, R, R, R, s_red, 1.0f, 0, wave_base, kCombWaves, part_idx);
 }
 
 hipError_t launch_step_combine(int prec, StepArgs args, const uint32_t* cjobs, int ncomb, hipStream_t s) {
   if (ncomb <= 0) return hipSuccess;
-  const dim3 grid(ncomb);
+  const dim3 grid(ncomb * kCombStripes), block(kCombWaves * 64);
   switch (prec) {
-    case kSplit2: hipLaunchKernelGGL((k_step_combine<kSplit2, kSplit2>), grid, dim3(NT), 0, s, args, cjobs); break;
-    case kSplit32: hipLaunchKernelGGL((k_step_combine<kSplit3, kSplit2>), grid, dim3(NT), 0, s, args, cjobs); break;
-    case kBF16: hipLaunchKernelGGL((k_step_combine<kBF16, kBF16>), grid, dim3(NT), 0, s, args, cjobs); break;
+    case kSplit2: hipLaunchKernelGGL((k_step_combine<kSplit2, kSplit2>), grid, block, 0, s, args, cjobs); break;
+    case kSplit32: hipLaunchKernelGGL((k_step_combine<kSplit3, kSplit2>), grid, block, 0, s, args, cjobs); break;
+    case kBF16: hipLaunchKernelGGL((k_step_combine<kBF16, kBF16>), grid, block, 0, s, args, cjobs); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
