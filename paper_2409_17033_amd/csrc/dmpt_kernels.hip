@@ -2147,40 +2147,16 @@ hipError_t launch_resplit(int prec, MatRef m, int n_pad, int nmat, hipStream_t s
 // X_1 = alpha I + beta H (Eq. DM0) and Y_1 = c A_k (c = beta for Eq. DM3 /
 // DMSuscept, c = 1 for the start Y_M = A of Eq. DM2), built from the
 // symmetric parts (S + S^T)/2 of H and A (exactly symmetric in FP32).  One
-// 64 x 64 block per workgroup over the full n_pad square; the block and its
-// transpose are both read row-wise and combined through LDS.  Blocks of X
-// emit (Tr, ||.||^2) partials.
-__global__ __launch_bounds__(256) void k_init(int prec, const float* h, const float* a, int n,
-                                              int n_pad, int zoff, MatRef x, MatRef y,
-                                              double y_scale_mode, Part* part, Ctl* ctl) {
-  __shared__ float tile[64][65];    // block (bi, bj) of the source
-  __shared__ float tileT[64][65];   // block (bj, bi) of the source
-  __shared__ double s_red[8];
-  const int bi = blockIdx.y, bj = blockIdx.x;   // output block (row, col)
-  const int z = blockIdx.z + zoff;               // 0: X from H; k >= 1: Y_{k-1} from A_{k-1}
-  const float* src = z == 0 ? h : a + (size_t)(z - 1) * n * n;
+// pair of mirror 64 x 64 blocks (bi, bj), (bj, bi) with bi <= bj per
+// workgroup: both are read once, row-wise, into LDS, and both output blocks
+// are written from them.  Blocks of X emit (Tr, ||.||^2) partials, each
+// block its own in a fixed order.
+__device__ __forceinline__ void init_block(int prec, const float (*p)[65], const float (*q)[65], int bi, int bj,
+                                           int nb, int n, int n_pad, int z, const MatRef& x, const MatRef& y,
+                                           double y_scale_mode, Part* part, const Ctl* ctl, double* s_red) {
+  // output block (bi, bj): element (r, c) = (p[r][c] + q[c][r]) / 2, p the
+  // source block (bi, bj), q the source block (bj, bi)
   const int t = threadIdx.x;
-  int bad = 0;
-  // stage both blocks row-wise (coalesced); the symmetric part is
-  // (S_ij + S_ji) / 2, formed below from tile[r][c] and tileT[c][r]
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    const int gi = bi * 64 + r, gj = bj * 64 + c;
-    const int ti_ = bj * 64 + r, tj_ = bi * 64 + c;
-    float v = 0.0f, w = 0.0f;
-    if (gi < n && gj < n) {
-      v = src[(size_t)gi * n + gj];
-      if (!isfinite(v)) bad = 1;
-    }
-    if (ti_ < n && tj_ < n) {
-      w = src[(size_t)ti_ * n + tj_];
-      if (!isfinite(w)) bad = 1;
-    }
-    tile[r][c] = v;
-    tileT[r][c] = w;
-  }
-  if (bad) ctl->nonfinite = 1;
-  __syncthreads();
   const double alpha = ctl->alpha, beta = ctl->beta;
   const double ys = y_scale_mode == 0.0 ? beta : y_scale_mode;
   const MatRef& m = z == 0 ? x : y;
@@ -2203,7 +2179,7 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int c = cg + e, gj = bj * 64 + c;
-      const double s = 0.5 * ((double)tile[r][c] + (double)tileT[c][r]);
+      const double s = 0.5 * ((double)p[r][c] + (double)q[c][r]);
       double val;
       if (z == 0) {
         val = beta * (double)s + ((gi == gj && gi < n) ? alpha : 0.0);
@@ -2227,9 +2203,10 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
     __syncthreads();
     if (t == 0) {
       MatMeta* mm = (MatMeta*)(m.meta + (size_t)(z - 1) * m.stride_op);
-      mm->nrm[bi * gridDim.x + bj] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
-      if (bi == 0 && bj == 0) mm->count = gridDim.x * gridDim.y;
+      mm->nrm[bi * nb + bj] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+      if (bi == 0 && bj == 0) mm->count = nb * nb;
     }
+    __syncthreads();
   }
   if (z == 0) {
     tr = wave_sum(tr);
@@ -2245,8 +2222,49 @@ __global__ __launch_bounds__(256) void k_init(int prec, const float* h, const fl
         tt += s_red[2 * w];
         qq += s_red[2 * w + 1];
       }
-      part[bi * gridDim.x + bj] = Part{tt, qq, 0.0, 0.0};
+      part[bi * nb + bj] = Part{tt, qq, 0.0, 0.0};
     }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init(int prec, const float* h, const float* a, int n,
+                                              int n_pad, int zoff, MatRef x, MatRef y,
+                                              double y_scale_mode, Part* part, Ctl* ctl) {
+  __shared__ float tile[64][65];    // block (bi, bj) of the source
+  __shared__ float tileT[64][65];   // block (bj, bi) of the source
+  __shared__ double s_red[8];
+  const int bi = blockIdx.y, bj = blockIdx.x;   // output blocks (bi, bj) and (bj, bi)
+  if (bi > bj) return;                          // the workgroup of (bj, bi) writes both
+  const int nb = gridDim.x;
+  const int z = blockIdx.z + zoff;               // 0: X from H; k >= 1: Y_{k-1} from A_{k-1}
+  const float* src = z == 0 ? h : a + (size_t)(z - 1) * n * n;
+  const int t = threadIdx.x;
+  int bad = 0;
+  // stage both blocks row-wise (coalesced)
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int gi = bi * 64 + r, gj = bj * 64 + c;
+    const int ti_ = bj * 64 + r, tj_ = bi * 64 + c;
+    float v = 0.0f, w = 0.0f;
+    if (gi < n && gj < n) {
+      v = src[(size_t)gi * n + gj];
+      if (!isfinite(v)) bad = 1;
+    }
+    if (bi != bj && ti_ < n && tj_ < n) {
+      w = src[(size_t)ti_ * n + tj_];
+      if (!isfinite(w)) bad = 1;
+    }
+    tile[r][c] = v;
+    tileT[r][c] = w;
+  }
+  if (bad) ctl->nonfinite = 1;
+  __syncthreads();
+  if (bi == bj) {
+    init_block(prec, tile, tile, bi, bj, nb, n, n_pad, z, x, y, y_scale_mode, part, ctl, s_red);
+  } else {
+    init_block(prec, tile, tileT, bi, bj, nb, n, n_pad, z, x, y, y_scale_mode, part, ctl, s_red);
+    init_block(prec, tileT, tile, bj, bi, nb, n, n_pad, z, x, y, y_scale_mode, part, ctl, s_red);
   }
 }
 
