@@ -330,7 +330,8 @@ def cpu_baseline_full(wl, W, closed_s):
 def measured_traffic(prec, n):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), used only
-    while the kernel sources still hash to the value recorded with it."""
+    while the kernel sources and the job-list builder (which sets the order
+    the tiles stream through L2) still hash to the value recorded with it."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_step_{prec}_n{n}_traffic.md")
     if not os.path.exists(path):
@@ -341,7 +342,8 @@ def measured_traffic(prec, n):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for src in ("paper_2409_17033_amd/csrc/dmpt_kernels.hip", "paper_2409_17033_amd/csrc/dmpt_internal.h"):
+    for src in ("paper_2409_17033_amd/csrc/dmpt_kernels.hip", "paper_2409_17033_amd/csrc/dmpt_internal.h",
+                "paper_2409_17033_amd/csrc/dmpt_lists.h"):
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:

@@ -1,6 +1,7 @@
 """Host-side checks of bench.py's contract (no GPU): more than one GPU is
 refused with a message, and the committed HBM-traffic figure is used only
-while the kernel sources hash to the value recorded with it."""
+while the kernel sources and the job-list builder hash to the value recorded
+with it."""
 import os
 import subprocess
 import sys
@@ -30,6 +31,7 @@ def test_traffic_figure_follows_the_kernel_sources(tmp_path, monkeypatch):
     csrc.mkdir(parents=True)
     (csrc / "dmpt_kernels.hip").write_text("// changed\n")
     (csrc / "dmpt_internal.h").write_text("// changed\n")
+    (csrc / "dmpt_lists.h").write_text("// changed\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("split3x_bf16", 8192) is None
     assert bench.measured_traffic("no_such_precision", 8192) is None
