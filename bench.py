@@ -91,7 +91,8 @@ def parse():
 
 def run_shapes(args, dm, torch, W, dev):
     """The matrix shapes of Sec. VI's water clusters (Table 2): for 100, 190 and
-    301 molecules, time-to-chi and the step kernel's rate in args.precision and
+    301 molecules, time-to-chi and the step kernel's rate in args.precision,
+    the FP16 split (the analogue of the paper's FP16 tensor-core runs) and
     FP32, and the first-order response by both routes of the duality:
     Tr[chi^A H1] (timed) and s Tr[A D1] (D1 from the same recursion with H1 in
     place of A).  Prints one JSON line."""
@@ -103,7 +104,7 @@ def run_shapes(args, dm, torch, W, dev):
         H, A, H1 = (torch.from_numpy(x).to(dev) for x in (wl.H, wl.A[0], wl.H1[0]))
         n_pad = -(-wl.n // 256) * 256
         row = {"molecules": mol, "n": wl.n, "nocc": wl.nocc, "n_pad": n_pad, "paths": {}}
-        for path in dict.fromkeys([args.precision, "fp32"]):
+        for path in dict.fromkeys([args.precision, "split_fp16", "fp32"]):
             prec = path.partition("+")[0]
             ms, chi, D, a0, resp, infos = run_path(dm, torch, H, A, H1, wl.nocc, path, args.steps, args.warmup)
             info = infos[-1]

@@ -23,7 +23,19 @@ from oracle import closed_form as cf
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "split_fp16": 1e-5, "split3_bf16": 1e-4}
+TOL = {"fp32": 1e-5, "split_fp16": 1e-5, "split3_bf16": 1e-4, "split3x_bf16+refine@3e-3": 1e-5}
+HEADLINE = "split3x_bf16+refine@3e-3"   # bench.py's default path
+
+
+def _kw(path):
+    """precision[+refine[@sweep_tol]] -> susceptibility() keywords."""
+    prec, _, rest = path.partition("+")
+    kw = {"precision": prec}
+    if rest:
+        kw["refine"] = True
+        if "@" in rest:
+            kw["sweep_tol"] = float(rest.partition("@")[2])
+    return kw
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +50,7 @@ def water100():
     return wl, d, chi, d1
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_fp16", "split3_bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16", "split3_bf16", HEADLINE])
 def test_water_shape_both_routes(gpu, water100, prec):
     import torch
 
@@ -48,8 +60,8 @@ def test_water_shape_both_routes(gpu, water100, prec):
     H = torch.from_numpy(wl.H).to(gpu)
     A = torch.from_numpy(wl.A[0]).to(gpu)
     H1 = torch.from_numpy(wl.H1[0]).to(gpu)
-    chi, D, a0, info = dm.susceptibility(H, A, wl.nocc, precision=prec, profile=True)
-    d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, precision=prec, spin=1.0, want_density=False)
+    chi, D, a0, info = dm.susceptibility(H, A, wl.nocc, profile=True, **_kw(prec))
+    d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, spin=1.0, want_density=False, **_kw(prec))
     ed = cf.rel_frobenius(D.double().cpu().numpy(), dref)
     ec = cf.rel_frobenius(chi.double().cpu().numpy(), chiref)
     ed1 = cf.rel_frobenius(d1.double().cpu().numpy(), d1ref)
@@ -75,17 +87,19 @@ def water301():
     import time
     wl = W.water_shaped(301, cache=False)
     t = time.perf_counter()
-    chi = cf.susceptibility(wl.H.astype(np.float64), wl.A[0].astype(np.float64), wl.nocc, spin=2.0)
     h1 = wl.H1[0].astype(np.float64)
+    # chi' of A and D1 of H1 from one eigendecomposition
+    resp = cf.first_order_responses(wl.H.astype(np.float64), np.stack([wl.A[0].astype(np.float64), h1]), wl.nocc)
+    chi, d1 = 2.0 * resp[0], resp[1]
     rref = float(np.sum(chi * h1))
     print(f"\nwater N=7224 closed form in {time.perf_counter() - t:.1f} s: Tr[chi H1] = {rref:.6f}", flush=True)
-    return wl, chi, rref, np.linalg.norm(chi) * np.linalg.norm(h1)
+    return wl, chi, d1, rref, np.linalg.norm(chi) * np.linalg.norm(h1)
 
 
-TOL_WATER = {"fp32": 1e-5, "split_fp16": 1e-4}
+TOL_WATER = {"fp32": 1e-5, "split_fp16": 1e-4, HEADLINE: 1e-5}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "split_fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "split_fp16", HEADLINE])
 def test_water_shape_largest(gpu, water301, prec):
     """The largest shape of Table 2 (301 molecules, N = 7224, padded to 7424)
     in the launch configuration bench.py's shapes run times: chi against the
@@ -95,22 +109,23 @@ def test_water_shape_largest(gpu, water301, prec):
     import torch
 
     import paper_2409_17033_amd as dm
-    wl, chiref, rref, scale = water301
+    wl, chiref, d1ref, rref, scale = water301
     assert (wl.n, wl.nocc) == (7224, 1505)
     H = torch.from_numpy(wl.H).to(gpu)
     A = torch.from_numpy(wl.A[0]).to(gpu)
     H1 = torch.from_numpy(wl.H1[0]).to(gpu)
-    chi, _, _, info = dm.susceptibility(H, A, wl.nocc, precision=prec, want_density=False)
+    chi, _, _, info = dm.susceptibility(H, A, wl.nocc, want_density=False, **_kw(prec))
     r_chi = float(dm.response(chi, H1)[0, 0])
     ec = cf.rel_frobenius(chi.double().cpu().numpy(), chiref)
     del chi
-    d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, precision=prec, spin=1.0, want_density=False)
+    d1, _, _, info1 = dm.susceptibility(H, H1, wl.nocc, spin=1.0, want_density=False, **_kw(prec))
     r_d1 = 2.0 * float(dm.response(d1, A)[0, 0])
-    print(f"\nwater N=7224 {prec}: M={info['m']} (D1 route M={info1['m']}) errchi={ec:.2e} "
+    ed1 = cf.rel_frobenius(d1.double().cpu().numpy(), d1ref)
+    print(f"\nwater N=7224 {prec}: M={info['m']} (D1 route M={info1['m']}) errchi={ec:.2e} errD1={ed1:.2e} "
           f"Tr[chi H1]={r_chi:.6f} ({abs(r_chi - rref) / abs(rref):.1e} of the value) "
           f"2Tr[A D1]={r_d1:.6f} ({abs(r_d1 - rref) / abs(rref):.1e})")
-    # spec targets: 1e-5 for the FP32 path, 1e-4 for split products
-    # (the FP16 split measures 1.0e-5 here)
+    # spec targets: 1e-5 for the FP32 path and refined runs, 1e-4 for
+    # split products (the FP16 split measures 1.0e-5 here)
     tol = TOL_WATER[prec]
-    assert ec <= tol
+    assert ec <= tol and ed1 <= tol
     assert abs(r_chi - rref) <= tol * scale and abs(r_d1 - rref) <= tol * scale
