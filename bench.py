@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--precision", default="split3x_bf16+refine@3e-3",
+    ap.add_argument("--precision", default="split3x_bf16+refine@1e-3",
                     help="headline path: a precision, optionally with +refine (the residual correction) "
                          "and @t (the sweeps stop at sweep_tol t)")
     ap.add_argument("--compare", default="fp32,split3_bf16,split_fp16,split3x_bf16+refine,split_fp16+refine,"

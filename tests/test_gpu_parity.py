@@ -124,7 +124,7 @@ def test_refined_matches_closed_form(gpu, case, prec):
     assert abs(np.trace(c)) <= 1e-4 * np.linalg.norm(c) * np.sqrt(wl.n)
 
 
-@pytest.mark.parametrize("case", ["dense300", "band1000"])
+@pytest.mark.parametrize("case", ["c1", "dense300", "band1000"])
 @pytest.mark.parametrize("prec", ["fp32", "split_fp16", "split3x_bf16"])
 def test_sweep_tol_matches_closed_form(gpu, case, prec):
     """opts.sweep_tol with the residual correction: the sweep stops once X_n

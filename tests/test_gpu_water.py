@@ -23,8 +23,8 @@ from oracle import closed_form as cf
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "split_fp16": 1e-5, "split3_bf16": 1e-4, "split3x_bf16+refine@3e-3": 1e-5}
-HEADLINE = "split3x_bf16+refine@3e-3"   # bench.py's default path
+TOL = {"fp32": 1e-5, "split_fp16": 1e-5, "split3_bf16": 1e-4, "split3x_bf16+refine@1e-3": 1e-5}
+HEADLINE = "split3x_bf16+refine@1e-3"   # bench.py's default path
 
 
 def _kw(path):
