@@ -124,7 +124,7 @@ def test_water_shape_largest(gpu, water301, prec):
     print(f"\nwater N=7224 {prec}: M={info['m']} (D1 route M={info1['m']}) errchi={ec:.2e} errD1={ed1:.2e} "
           f"Tr[chi H1]={r_chi:.6f} ({abs(r_chi - rref) / abs(rref):.1e} of the value) "
           f"2Tr[A D1]={r_d1:.6f} ({abs(r_d1 - rref) / abs(rref):.1e})")
-    # spec targets: 1e-5 for the FP32 path and refined runs, 1e-4 for
+    # targets: 1e-5 for the FP32 path and refined runs, 1e-4 for
     # split products (the FP16 split measures 1.0e-5 here)
     tol = TOL_WATER[prec]
     assert ec <= tol and ed1 <= tol
