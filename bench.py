@@ -66,9 +66,10 @@ def parse():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--precision", default="split3x_bf16+refine@1e-3",
                     help="headline path: a precision, optionally with +refine (the residual correction) "
-                         "and @t (the sweeps stop at sweep_tol t)")
-    ap.add_argument("--compare", default="fp32,split3_bf16,split_fp16,split3x_bf16+refine,split_fp16+refine,"
-                                         "split_bf16",
+                         "and @t (the sweeps stop at sweep_tol t), and +project2 (the projections above "
+                         "the sweep's precision)")
+    ap.add_argument("--compare", default="fp32,split3_bf16,split_fp16,split3x_bf16+refine,"
+                                         "split3x_bf16+refine@1e-3+project2,split_fp16+refine,split_bf16",
                     help="other paths timed for context")
     ap.add_argument("--compare-steps", type=int, default=1)
     ap.add_argument("--no-errors", action="store_true", help="skip the closed-form errors of each path")
@@ -196,10 +197,18 @@ def property_errors(torch, H, A, D, chi, nocc, spin):
 
 
 def path_kw(path):
-    """Options of a path "precision[+refine[@sweep_tol]]"."""
-    prec, _, rf = path.partition("+")
-    rf, _, tol = rf.partition("@")
-    return dict(precision=prec, refine=rf == "refine", sweep_tol=float(tol) if tol else 0.0)
+    """Options of a path "precision[+refine[@sweep_tol]][+project2]"."""
+    parts = path.split("+")
+    kw = dict(precision=parts[0], refine=False, sweep_tol=0.0)
+    for part in parts[1:]:
+        if part.startswith("refine"):
+            tol = part.partition("@")[2]
+            kw.update(refine=True, sweep_tol=float(tol) if tol else 0.0)
+        elif part == "project2":
+            kw["project"] = 2
+        else:
+            raise ValueError(f"unknown path option {part!r} in {path!r}")
+    return kw
 
 
 def run_path(dm, torch, H, A, H1, nocc, path, steps, warmup):

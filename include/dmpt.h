@@ -109,7 +109,15 @@ typedef struct dmpt_opts {
                              precision of the recursion; FP32 when it is plain BF16).  When the
                              launch after the last step took sigma = +1 (forward sweep, one
                              precision for all products), its Y is the first of the two and
-                             is used as it is. */
+                             is used as it is.  2 -> DMPT_SPLIT3X_BF16 with refine only: Y is
+                             projected in the three-term split (a three-term copy of Y and D's
+                             three-term copy, regular tiles) and the correction's delta in the
+                             two-term split with D's two-term copy, instead of the two-term and
+                             plain-BF16 projections.  What the cheaper projections leave in the
+                             occupied-occupied / virtual-virtual blocks (about 2^-16 and 2^-8 of
+                             Y and delta) is small in norm but can add up in traces against
+                             smooth weights (a dipole Tr[A D1] with A the position); about 5 %
+                             more time at n = 8192. */
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
   int32_t ckpt_interval;  /* ADJOINT sweep only: keep X_n every ckpt_interval steps and recompute
                              the steps in between during the backward sweep; 0 -> keep every X_n */

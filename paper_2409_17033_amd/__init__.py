@@ -40,7 +40,7 @@ def _check_matrix(t, n=None, name="matrix"):
 def make_opts(n: int, nocc: int, *, precision: str = "fp32", bounds: str = "lanczos",
               emin: float | None = None, emax: float | None = None, lanczos_steps: int = 0,
               max_iter: int = 0, min_iter: int = -1, sweep: str = "forward",
-              idem_tol: float = 0.0, project: bool = True, spin: float = 2.0,
+              idem_tol: float = 0.0, project: bool | int = True, spin: float = 2.0,
               profile: bool = False, ckpt_interval: int = 0, refine: bool | int = False,
               sweep_tol: float = 0.0, stream=None) -> Opts:
     lib = load()
@@ -55,7 +55,7 @@ def make_opts(n: int, nocc: int, *, precision: str = "fp32", bounds: str = "lanc
     o.min_iter = min_iter
     o.sweep = SWEEP[sweep]
     o.idem_tol = idem_tol
-    o.project = 1 if project else 0
+    o.project = int(project)   # True -> 1; 2: the projections above the sweep's precision (split3x)
     o.spin = spin
     o.profile = 1 if profile else 0
     o.ckpt_interval = ckpt_interval

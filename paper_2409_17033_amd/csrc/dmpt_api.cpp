@@ -70,7 +70,9 @@ dmpt_status normalise(const dmpt_opts* o, Opts* r) {
   if (o->sweep != DMPT_SWEEP_FORWARD && o->sweep != DMPT_SWEEP_ADJOINT) return fail(DMPT_ERR_ARG, "unknown sweep %d", o->sweep);
   if (!(std::isfinite(o->idem_tol) && o->idem_tol >= 0)) return fail(DMPT_ERR_ARG, "idem_tol must be finite and >= 0");
   if (!std::isfinite(o->spin)) return fail(DMPT_ERR_ARG, "spin must be finite");
-  if (o->project != 0 && o->project != 1) return fail(DMPT_ERR_ARG, "project must be 0 or 1");
+  if (o->project < 0 || o->project > 2) return fail(DMPT_ERR_ARG, "project must be 0, 1 or 2");
+  if (o->project == 2 && (o->precision != DMPT_SPLIT3X_BF16 || !o->refine))
+    return fail(DMPT_ERR_ARG, "project = 2 needs DMPT_SPLIT3X_BF16 with refine");
   if (o->profile != 0 && o->profile != 1) return fail(DMPT_ERR_ARG, "profile must be 0 or 1");
   if (o->ckpt_interval < 0 || o->ckpt_interval > DMPT_MAX_STEPS)
     return fail(DMPT_ERR_ARG, "ckpt_interval out of range [0, %d]", DMPT_MAX_STEPS);
@@ -715,7 +717,11 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     // (f_i + f_j)(2 - f_i - f_j): 1 on occupied-virtual pairs, 0 elsewhere.
     // They run in the precision of the sweep products (FP32 for plain BF16),
     // on the operand copies of D and Y the last step wrote.
-    const int pprec = p.prec == kBF16 ? kFP32 : yprec;
+    // project = 2 (three-term-X^2 option): Y is projected in the three-term
+    // split, from a three-term copy of Y and D's three-term copy, on the
+    // regular tiles (in the main list's buffer, free once the steps are done)
+    const bool proj3 = o.project == 2;
+    const int pprec = proj3 ? kSplit3 : p.prec == kBF16 ? kFP32 : yprec;
     // (the list also serves the launches of the residual correction)
     std::vector<uint32_t> pjobs;
     if (wide) {
@@ -745,7 +751,19 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
     b.split_slot = d_slots_proj;
     b.split_buf = d_split_buf;
     auto view = [&](MatRef m) { return pprec == kFP32 ? as_fp32(m) : m; };
-    b.x_in = pprec == kFP32 ? as_fp32(x_ref(p, ws, xfin)) : sweep_x(x_ref(p, ws, xfin));
+    b.x_in = pprec == kFP32 ? as_fp32(x_ref(p, ws, xfin)) : proj3 ? x_ref(p, ws, xfin) : sweep_x(x_ref(p, ws, xfin));
+    std::vector<uint32_t> rjobs;
+    if (proj3) {
+      rjobs = build_jobs(p.n_pad, nobs, false);
+      DMPT_HIP(hipMemcpyAsync(d_jobs, rjobs.data(), rjobs.size() * 4, hipMemcpyHostToDevice, s));
+      b.jobs = d_jobs;
+      b.split_slot = nullptr;
+      b.split_buf = nullptr;
+      const MatRef y0 = y_ref(p, ws, yfin);   // its operand area holds the three-term copy
+      for (int k = 0; k < nobs; ++k)
+        DMPT_HIP(launch_copy_src(kSplit3, y0.f32 + (size_t)k * y0.stride_f32, p.n_pad,
+                                 (char*)y0.op + (size_t)k * y0.stride_op, p.n_pad, 0, s));
+    }
     // The launch after the last step (it ran before the stop was seen, since
     // the stopping test needs its idempotency error) formed Z = D Y + Y D from
     // D = X_{m+1} and Y_{m+1}, the product of the first projection step.
@@ -772,8 +790,12 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       b.write_split = q == 0 && pprec != kFP32;   // the second step reads it
       b.y_in = view(y_ref(p, ws, yfin));
       b.y_out = view(y_ref(p, ws, yfin ^ 1));
-      DMPT_HIP(run_step(pprec, b, (int)pjobs.size(), wide));
-      DMPT_HIP(combine(pprec, b, d_cjobs_proj, cjobs_proj.size()));
+      if (proj3) {
+        DMPT_HIP(run_step(pprec, b, (int)rjobs.size()));
+      } else {
+        DMPT_HIP(run_step(pprec, b, (int)pjobs.size(), wide));
+        DMPT_HIP(combine(pprec, b, d_cjobs_proj, cjobs_proj.size()));
+      }
       yfin ^= 1;
     }
   }
@@ -930,16 +952,42 @@ dmpt_status run(const float* H, const float* A, int nobs, float* chi, float* D, 
       DMPT_HIP(run_step(kBF16, r, nzj, wide));
       DMPT_HIP(combine(kBF16, r, d_cjobs_proj, cjobs_proj.size()));
     }
-    // projection of delta with D, then Y += P(delta)
+    // projection of delta with D, then Y += P(delta).  project = 2: delta is
+    // copied to the two-term split and projected with D's two-term copy (D's
+    // BF16 copy spans an occupied subspace turned by about 2^-8 against H's,
+    // and delta from the BF16 sweep is occupied-virtual in that one); the
+    // free Y slot holds the copies (its operand area and the one after it)
     int yd = (mcorr + 1) & 1;
+    const bool proj3 = o.project == 2;
+    const MatRef yfree = y_ref(p, ws, yfin ^ 1);
+    if (proj3) {
+      const MatRef dd = by(yd);
+      for (int k = 0; k < nobs; ++k)
+        DMPT_HIP(launch_copy_src(kSplit2, dd.f32 + (size_t)k * dd.stride_f32, p.n_pad,
+                                 (char*)yfree.op + (size_t)k * yfree.stride_op, p.n_pad, 0, s));
+      b.flush = flush_interval(kSplit2, p.n_pad);
+      b.x_in = sweep_x(xf);
+    }
     for (int q = 0; q < 2; ++q) {
       b.fixed_sigma = q == 0 ? 1 : -1;
       b.write_split = q == 0;
       b.oscale = 1.0f;
       b.y_in = by(yd);
       b.y_out = by(yd ^ 1);
-      DMPT_HIP(run_step(kBF16, b, nzj, wide));
-      DMPT_HIP(combine(kBF16, b, d_cjobs_proj, cjobs_proj.size()));
+      if (proj3) {
+        char* copy2 = (char*)yfree.op + align_up(p.mat_op);   // step 1's output copy
+        b.y_in.op = q == 0 ? yfree.op : (void*)copy2;
+        b.y_in.stride_op = yfree.stride_op;
+        b.y_in.meta = yfree.meta;
+        b.y_out.op = copy2;
+        b.y_out.stride_op = yfree.stride_op;
+        b.y_out.meta = yfree.meta;
+        DMPT_HIP(run_step(kSplit2, b, nzj, wide));
+        DMPT_HIP(combine(kSplit2, b, d_cjobs_proj, cjobs_proj.size()));
+      } else {
+        DMPT_HIP(run_step(kBF16, b, nzj, wide));
+        DMPT_HIP(combine(kBF16, b, d_cjobs_proj, cjobs_proj.size()));
+      }
       yd ^= 1;
     }
     const MatRef dl = by(yd);

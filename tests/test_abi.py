@@ -122,6 +122,21 @@ def test_sweep_tol_validation(lib):
         assert b"sweep_tol" in lib.dmpt_last_error()
 
 
+def test_project_validation(lib):
+    """project = 2 (the projections above the sweep's precision) exists for
+    the three-term-X^2 option with the correction only; it needs no more
+    workspace than project = 1 (it reuses the free Y slot and the main list's
+    buffer); other values are refused before any device work."""
+    ok = _opts(lib, 1000, 500, precision=4, refine=1, project=2)
+    base = _opts(lib, 1000, 500, precision=4, refine=1, project=1)
+    assert lib.dmpt_workspace_bytes(C.byref(ok), 2) == lib.dmpt_workspace_bytes(C.byref(base), 2) > 0
+    for prec, refine, project in ((4, 0, 2), (2, 1, 2), (5, 1, 2), (0, 1, 2), (4, 1, 3), (4, 1, -1)):
+        bad = _opts(lib, 1000, 500, precision=prec, refine=refine, project=project)
+        assert lib.dmpt_workspace_bytes(C.byref(bad), 1) == 0, (prec, refine, project)
+        assert lib.dmpt_susceptibility(FAKE, FAKE, 1, FAKE, None, None, C.byref(bad), None) == 1
+        assert b"project" in lib.dmpt_last_error()
+
+
 def test_workspace_bytes(lib):
     o = _opts(lib, 1000, 500)
     w0 = lib.dmpt_workspace_bytes(C.byref(o), 0)

@@ -62,3 +62,15 @@ def test_water_shaped_workload():
     assert (blocks == blocks[:, :1]).all() and len(np.unique(blocks[:, 0])) == 18
     assert np.abs(d).max() <= 1.0
     assert np.array_equal(np.diag(wl.A[0]), np.arange(144, dtype=np.float32) - 71.5)
+
+
+def test_path_names():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.path_kw("fp32") == dict(precision="fp32", refine=False, sweep_tol=0.0)
+    assert bench.path_kw("split3x_bf16+refine") == dict(precision="split3x_bf16", refine=True, sweep_tol=0.0)
+    assert bench.path_kw("split3x_bf16+refine@1e-3+project2") == dict(precision="split3x_bf16", refine=True,
+                                                                      sweep_tol=1e-3, project=2)
+    import pytest
+    with pytest.raises(ValueError):
+        bench.path_kw("split3x_bf16+refin")

@@ -67,7 +67,7 @@ def test_full_size_properties(gpu, m8):
 # 1.5e-5; D within 1e-6 on all of them.
 TOL_FULL = {"fp32": 1e-5, "split_fp16": 1e-4, "split3_bf16": 1e-4, "split_fp16+refine": 1e-5,
             "split3_bf16+refine": 1e-5, "split3x_bf16+refine": 1e-5, "split3x_bf16+refine@1e-3": 1e-5,
-            "split3x_bf16+refine@3e-3": 1e-5}
+            "split3x_bf16+refine@3e-3": 1e-5, "split3x_bf16+refine@1e-3+project2": 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -85,7 +85,7 @@ def m8_closed_form(m8):
 
 
 PATHS = ["fp32", "split_fp16", "split3_bf16", "split_fp16+refine", "split3x_bf16+refine",
-         "split3x_bf16+refine@1e-3", "split3x_bf16+refine@3e-3",
+         "split3x_bf16+refine@1e-3", "split3x_bf16+refine@3e-3", "split3x_bf16+refine@1e-3+project2",
          pytest.param("split_bf16", marks=pytest.mark.skip(
              reason="two-term BF16 split: chi 5.0e-4 at N = 8192 (measured), above 1e-4; its X^2 leaves D "
                     "3.4e-5 off (subspace), which no correction of chi built on that D removes")),
@@ -96,6 +96,21 @@ PATHS = ["fp32", "split_fp16", "split3_bf16", "split_fp16+refine", "split3x_bf16
                     "1e-4; its refined run is tested"))]
 
 
+def _path_kw(path):
+    """path: precision[+refine[@sweep_tol]][+project2], as bench.py names its paths."""
+    parts = path.split("+")
+    kw = dict(precision=parts[0])
+    for part in parts[1:]:
+        if part.startswith("refine"):
+            tol = part.partition("@")[2]
+            kw.update(refine=True, sweep_tol=float(tol) if tol else 0.0)
+        elif part == "project2":
+            kw["project"] = 2
+        else:
+            raise ValueError(part)
+    return kw
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_full_size_against_closed_form(gpu, m8, m8_closed_form, path):
     import torch
@@ -103,14 +118,10 @@ def test_full_size_against_closed_form(gpu, m8, m8_closed_form, path):
     import paper_2409_17033_amd as dm
     wl = m8
     dref, chiref, a0ref = m8_closed_form
-    # path: precision[+refine[@sweep_tol]]
-    prec, _, rf = path.partition("+")
-    rf, _, tol = rf.partition("@")
     H = torch.from_numpy(wl.H).to(gpu)
     A = torch.from_numpy(wl.A[0]).to(gpu)
     H1 = torch.from_numpy(wl.H1).to(gpu)
-    chi, D, a0, info = dm.susceptibility(H, A, wl.nocc, precision=prec, refine=rf == "refine",
-                                         sweep_tol=float(tol) if tol else 0.0)
+    chi, D, a0, info = dm.susceptibility(H, A, wl.nocc, **_path_kw(path))
     resp = dm.response(chi, H1)[0]
     ec = cf.rel_frobenius(chi.double().cpu().numpy(), chiref)
     ed = cf.rel_frobenius(D.double().cpu().numpy(), dref)

@@ -49,6 +49,11 @@ def _np(t):
     return t.detach().double().cpu().numpy()
 
 
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a, b))
+
+
 def _case(name):
     if name == "c1":
         return W.dense_gapped(128)
@@ -199,6 +204,28 @@ def test_headline_path_four_observables(gpu):
         e1 = cf.rel_frobenius(_np(one), _np(chi[k]))
         print(f"obs {k}: errchi {ek:.2e}, single run differs by {e1:.2e}")
         assert ek <= 1e-5 and e1 <= 1e-5
+
+
+def test_accurate_projections_three_observables(gpu):
+    """project = 2 (Y projected in three terms, the correction's delta in two)
+    with the timed configuration on three random observables at N = 2048:
+    each chi against its closed form at the refined 1e-5, each equal to its
+    single-observable run, and D untouched by the option (bit for bit)."""
+    dm = _dm()
+    wl = W.banded_gapped(2048, observable="random", nobs=3, npert=1, cfg=16, cache=False)
+    H, A = _dev(wl.H, gpu), _dev(wl.A, gpu)
+    kw = dict(precision="split3x_bf16", refine=True, sweep_tol=1e-3)
+    chi, D, _, info = dm.susceptibility(H, A, wl.nocc, project=2, **kw)
+    chi1, D1, _, _ = dm.susceptibility(H, A, wl.nocc, **kw)
+    refs = 2.0 * cf.first_order_responses(wl.H.astype(np.float64), wl.A.astype(np.float64), wl.nocc)
+    assert torch_equal(D, D1)
+    for k, ref in enumerate(refs):
+        e2 = cf.rel_frobenius(_np(chi[k]), ref)
+        e1 = cf.rel_frobenius(_np(chi1[k]), ref)
+        one, _, _, _ = dm.susceptibility(H, A[k].contiguous(), wl.nocc, project=2, **kw)
+        d1 = cf.rel_frobenius(_np(one), _np(chi[k]))
+        print(f"obs {k}: errchi project=2 {e2:.2e} (project=1 {e1:.2e}), single run differs by {d1:.2e}")
+        assert e2 <= 1e-5 and d1 <= 1e-5
 
 
 def test_refine_two_observables(gpu):
