@@ -116,7 +116,7 @@ typedef struct dmpt_opts {
                              plain-BF16 projections.  What the cheaper projections leave in the
                              occupied-occupied / virtual-virtual blocks (about 2^-16 and 2^-8 of
                              Y and delta) is small in norm but can add up in traces against
-                             smooth weights (a dipole Tr[A D1] with A the position); 3 - 6 %
+                             smooth weights (a dipole Tr[A D1] with A the position); about 6 %
                              more time at n = 8192. */
   int32_t profile;        /* 1 -> time every step-kernel launch with events (dmpt_info.*_ms) */
   int32_t ckpt_interval;  /* ADJOINT sweep only: keep X_n every ckpt_interval steps and recompute
